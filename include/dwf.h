@@ -1,0 +1,189 @@
+/*
+ * dwf.h -- C ABI of libdwf: the red-black (Schur) preconditioned Shamir
+ * domain-wall operator and the solver / filter built on it, for AMD gfx950.
+ *
+ * The operators are those of the paper's "Chiral Fermion Actions" section:
+ *   D_hop   = sum_mu (1 - g_mu) U_mu(x) d_{x+mu,y} + (1 + g_mu) U_mu(x-mu)^dag d_{x-mu,y}
+ *   D_DW    = the Ls x Ls block matrix with D_par = 5 - M5 - D_hop/2 on the
+ *             diagonal, -P_- above, -P_+ below, m P_+ / m P_- in the corners
+ *   M5D     = D_DW with D_hop removed (= M_ee = M_oo, local in the 4D site)
+ *   M_pc    = M_ee - M_eo M_oo^{-1} M_oe = M5D - D_hop^{eo} M5D^{-1} D_hop^{oe} / 4
+ *             (first Schur form; the red-black CGNR of the Results section)
+ * and the setup filter of the "Deflation basis setup" section.
+ *
+ * Conventions.  Chiral gamma basis, gamma5 = diag(1,1,-1,-1), P_+- = (1 +- gamma5)/2.
+ * Lattice extents dims = {X, Y, Z, T}, all even; periodic 4D boundaries;
+ * parity = (x+y+z+t) mod 2, even = 0.  V4 = X*Y*Z*T, V4h = V4/2.
+ *
+ * Layouts (all device memory, owned by the caller):
+ *  - natural gauge field  U[T][Z][Y][X][mu][a][b], complex128 (re, im interleaved);
+ *  - natural 5D fermion   psi[rhs][Ls][T][Z][Y][X][spin][colour], complex128;
+ *  - packed half field (one parity) per right-hand side: [V4h][12][Ls] complex
+ *    values, spin-colour index c = 3*spin + colour, s fastest, site index
+ *    h = (x + X*(y + Y*(z + Z*t))) / 2; right-hand sides are consecutive blocks.
+ *      DWF_F64 : complex128, 192 * Ls * V4h bytes per rhs
+ *      DWF_F32 : complex64,   96 * Ls * V4h bytes per rhs
+ *      DWF_F16S: per rhs, [V4h][12][Ls] pairs of IEEE halves (v / scale, round to
+ *                nearest even) followed by [V4h][Ls] float scales = max |v| over
+ *                the 24 reals of the spinor; 52 * Ls * V4h bytes per rhs
+ *  - packed "both parities" field: the even half field of all rhs, then the odd.
+ *
+ * Every call that takes device pointers is asynchronous on the handle's stream
+ * unless marked synchronous.  Calls return DWF_OK or a negative status; the
+ * message of the last failure on the calling thread is dwf_last_error().
+ * No exception crosses the ABI.  A handle must not be used from two host
+ * threads at once.
+ */
+#ifndef DWF_H
+#define DWF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dwf_context* dwf_handle;
+
+enum dwf_status {
+  DWF_OK = 0,
+  DWF_EINVAL = -1,      /* bad argument: odd extent, Ls < 1, null pointer, nrhs out of range */
+  DWF_ENOMEM = -2,      /* workspace smaller than dwf_workspace_bytes() */
+  DWF_EHIP = -3,        /* a HIP runtime call failed (message holds its text) */
+  DWF_ENOCONV = -4,     /* maxiter reached; x holds the last iterate */
+  DWF_EBREAKDOWN = -5,  /* non-finite or non-positive curvature in CG (e.g. NaN source) */
+  DWF_WLAMBDA = 1       /* warning: filter upper bound below the measured lambda_max */
+};
+
+enum dwf_precision { DWF_F64 = 0, DWF_F32 = 1, DWF_F16S = 2 };
+enum dwf_parity { DWF_EVEN = 0, DWF_ODD = 1, DWF_BOTH = 2 };
+
+/* ---- set-up -------------------------------------------------------------- */
+
+/* Bytes of device workspace a handle needs (host only, no GPU call).  prec is
+ * the storage precision of the handle's fields; max_nrhs is the number of
+ * right-hand sides the operator temporaries hold at once (operator and filter
+ * calls with more are processed in chunks of max_nrhs); max_cg_rhs bounds the
+ * nrhs of dwf_cg and enables dwf_solve_rb / dwf_force (0 = no solver
+ * workspace).  Returns 0 on invalid arguments. */
+size_t dwf_workspace_bytes(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs);
+
+/* Bytes of one packed half field of nrhs right-hand sides at precision prec
+ * (host only). */
+size_t dwf_field_bytes(const int dims[4], int Ls, int prec, int nrhs);
+
+/* Create a handle: validates the arguments, carves the caller's workspace
+ * (device memory of at least dwf_workspace_bytes bytes, kept alive by the
+ * caller until dwf_destroy, 256-byte aligned), packs the links U (natural
+ * layout, device) into it and builds the neighbour tables, on `stream` (a
+ * hipStream_t; NULL is the null stream).  M5 is the domain-wall height
+ * (M5 != 5), mf the quark mass of the corner terms.  Extents must be even and
+ * >= 2, 1 <= Ls <= 128. */
+int dwf_create(dwf_handle* h, const void* U, const int dims[4], int Ls, double M5, double mf,
+               int prec, int max_nrhs, int max_cg_rhs, void* workspace, size_t ws_bytes,
+               void* stream);
+
+/* Re-pack new links (same lattice), e.g. after an HMC update. */
+int dwf_update_links(dwf_handle h, const void* U);
+
+/* Change the stream later calls are queued on. */
+int dwf_set_stream(dwf_handle h, void* stream);
+
+/* Free the host-side handle; does not free the caller's workspace. */
+int dwf_destroy(dwf_handle h);
+
+/* Thread-local text of the last failure (never NULL). */
+const char* dwf_last_error(void);
+
+/* Natural complex128 <-> packed (handle precision).  parity selects which
+ * sites are moved; unpack writes only the sites of that parity. */
+int dwf_pack(dwf_handle h, const void* natural, void* packed, int nrhs, int parity);
+int dwf_unpack(dwf_handle h, const void* packed, void* natural, int nrhs, int parity);
+
+/* ---- operators (handle precision, packed layout) -------------------------- */
+
+/* out = D_hop in (dagger = 0) or D_hop^dag in (dagger = 1) on every slice s,
+ * from the other parity into out_parity (the D_hop equation). */
+int dwf_dhop(dwf_handle h, const void* in, void* out, int out_parity, int nrhs, int dagger);
+
+/* out = M5D in or M5D^dag in, and the exact inverses (site-local, one parity). */
+int dwf_m5d(dwf_handle h, const void* in, void* out, int nrhs, int dagger);
+int dwf_m5d_inv(dwf_handle h, const void* in, void* out, int nrhs, int dagger);
+
+/* Full D_DW (or D_DW^dag) on both parities (packed "both" layout). */
+int dwf_ddw(dwf_handle h, const void* in, void* out, int nrhs, int dagger);
+
+/* out_e = M_pc in_e (dagger = 0) or M_pc^dag in_e (dagger = 1): two passes,
+ * t_o = M5D^{-1} D_hop^{oe} in_e then out_e = M5D in_e - D_hop^{eo} t_o / 4. */
+int dwf_mpc(dwf_handle h, const void* in_e, void* out_e, int nrhs, int dagger);
+
+/* out_e = M_pc^dag M_pc in_e: four passes. */
+int dwf_mpcdagmpc(dwf_handle h, const void* in_e, void* out_e, int nrhs);
+
+/* ---- solver, filter, orthonormalisation ----------------------------------- */
+
+/* SYNCHRONOUS.  Solve M_pc^dag M_pc x = b for nrhs right-hand sides by CG
+ * (Hestenes-Stiefel).  b and x are FP64 packed even fields whatever the
+ * handle precision; x holds the initial guess on entry.  With a DWF_F64
+ * handle every step is FP64; with DWF_F32 / DWF_F16S the iteration runs on
+ * low-precision fields with FP64 dot products and FP64 reliable updates
+ * r = b - A x whenever |r| falls by 10x since the last update.  Stops when
+ * every ||r|| / ||b|| < tol; iters[nrhs] and true_rel_resid[nrhs] are host
+ * arrays (either may be NULL) receiving iterations and ||b - A x|| / ||b||
+ * in FP64.  Returns DWF_ENOCONV after maxiter, DWF_EBREAKDOWN on NaN. */
+int dwf_cg(dwf_handle h, const void* b, void* x, int nrhs, double tol, int maxiter, int* iters,
+           double* true_rel_resid);
+
+/* SYNCHRONOUS.  Red-black solve of D_DW psi = eta (FP64, packed "both"
+ * layout, nrhs = 1): eta' = eta_e - M_eo M5D^{-1} eta_o, CG on
+ * M_pc^dag M_pc psi_e = M_pc^dag eta', psi_o = M5D^{-1}(eta_o - M_oe psi_e).
+ * psi's even half is the initial guess. */
+int dwf_solve_rb(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters,
+                 double* true_rel_resid);
+
+/* SYNCHRONOUS.  Power method for lambda_max of M_pc^dag M_pc from the start
+ * vector v (handle precision, one rhs, overwritten with the last iterate). */
+int dwf_power(dwf_handle h, void* v, int iters, double rtol, double* lambda_max, int* iters_done);
+
+/* In place: vecs <- T_order(x(A)) vecs, x(A) = 2 (A - lo) / (hi - lo) - 1,
+ * A = M_pc^dag M_pc, for nvecs right-hand sides at once (handle precision),
+ * no normalisation (Chebyshev smoothers / Deflation basis setup sections). */
+int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* vecs, int nvecs);
+
+/* The recursive series of the setup: v0 = T_m(x_[lam_lo, lam_max](A)) eta,
+ * then out_series[k] = T_{k delta}(2 A / lam_max - 1) v0 for k = 0..nvec-1
+ * (one rhs; out_series holds nvec packed fields).  eta is not modified. */
+int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int delta, int nvec,
+                         const void* eta, void* out_series);
+
+/* SYNCHRONOUS.  In place Q R = V for nvecs packed even fields (handle
+ * precision) by classical Gram-Schmidt applied twice with FP64 dot products;
+ * R (nvecs x nvecs complex128, row-major, upper triangular, positive real
+ * diagonal) is written to host memory R_host if non-NULL. */
+int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
+
+/* ---- HMC force ------------------------------------------------------------ */
+
+/* Link gradient of S = phi^dag (M_pc^dag M_pc)^{-1} phi given X = A^{-1} phi
+ * and Y = M_pc X (FP64 packed even fields, one rhs):
+ *   G_mu(x) = -sum_s sum_spin [ a(x,s) ((1-g_mu) b(x+mu,s))^dag + ((1+g_mu) b(x,s)) a(x+mu,s)^dag ],
+ * a = (Y even, M5D^{-dag} M_eo^dag Y odd), b = (X even, M5D^{-1} M_oe X odd),
+ * written as grad_U in the natural link layout (complex128), with the
+ * convention G = dS/dRe U + i dS/dIm U.  Needs a DWF_F64 handle. */
+int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U);
+
+/* ---- introspection -------------------------------------------------------- */
+
+/* Launch shape of the hopping kernels: sites per workgroup (0 = default). */
+int dwf_set_tile(dwf_handle h, int sites_per_block, int rhs_per_block);
+
+/* Average duration (ms) of the hopping-term kernels since the last reset, as
+ * measured by HIP events on the handle's stream when timing is enabled. */
+int dwf_enable_timing(dwf_handle h, int enable);
+int dwf_kernel_time(dwf_handle h, double* ms_total, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DWF_H */

@@ -1,0 +1,318 @@
+"""Python binding of libdwf: the red-black Shamir domain-wall operator on gfx950.
+
+The binding only marshals arguments: every step runs in the HIP kernels of
+``libdwf.so``.  PyTorch provides device memory (the workspace and the field
+buffers are torch tensors) and the stream (torch's current stream).  If the
+library has not been built this module raises at import-free call time --
+there is no CPU fallback.
+
+Two levels:
+
+* module functions with the C ABI's names (``dwf_create``, ``dwf_mpc``, ...)
+  taking raw integers / pointers, for callers who manage memory themselves;
+* :class:`Operator`, which owns a workspace tensor and a handle and accepts
+  torch tensors.
+
+Packed fields are 1-D ``torch.uint8`` tensors of ``field_bytes(nrhs)`` bytes
+(layout documented in ``include/dwf.h``); natural fields are complex128
+tensors ``[nrhs][Ls][T][Z][Y][X][4][3]``; links are complex128
+``[T][Z][Y][X][4][3][3]``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libdwf.so")
+
+DWF_OK, DWF_EINVAL, DWF_ENOMEM, DWF_EHIP, DWF_ENOCONV, DWF_EBREAKDOWN, DWF_WLAMBDA = 0, -1, -2, -3, -4, -5, 1
+DWF_F64, DWF_F32, DWF_F16S = 0, 1, 2
+DWF_EVEN, DWF_ODD, DWF_BOTH = 0, 1, 2
+
+_STATUS = {
+    DWF_EINVAL: "DWF_EINVAL",
+    DWF_ENOMEM: "DWF_ENOMEM",
+    DWF_EHIP: "DWF_EHIP",
+    DWF_ENOCONV: "DWF_ENOCONV",
+    DWF_EBREAKDOWN: "DWF_EBREAKDOWN",
+}
+
+
+class DWFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+# name -> (restype, argtypes); mirrors include/dwf.h
+_PROTOS = {
+    "dwf_workspace_bytes": (ctypes.c_size_t, [_c_int_p, _i, _i, _i, _i]),
+    "dwf_field_bytes": (ctypes.c_size_t, [_c_int_p, _i, _i, _i]),
+    "dwf_create": (_i, [ctypes.POINTER(_vp), _vp, _c_int_p, _i, _d, _d, _i, _i, _i, _vp, ctypes.c_size_t, _vp]),
+    "dwf_update_links": (_i, [_vp, _vp]),
+    "dwf_set_stream": (_i, [_vp, _vp]),
+    "dwf_destroy": (_i, [_vp]),
+    "dwf_last_error": (ctypes.c_char_p, []),
+    "dwf_pack": (_i, [_vp, _vp, _vp, _i, _i]),
+    "dwf_unpack": (_i, [_vp, _vp, _vp, _i, _i]),
+    "dwf_dhop": (_i, [_vp, _vp, _vp, _i, _i, _i]),
+    "dwf_m5d": (_i, [_vp, _vp, _vp, _i, _i]),
+    "dwf_m5d_inv": (_i, [_vp, _vp, _vp, _i, _i]),
+    "dwf_ddw": (_i, [_vp, _vp, _vp, _i, _i]),
+    "dwf_mpc": (_i, [_vp, _vp, _vp, _i, _i]),
+    "dwf_mpcdagmpc": (_i, [_vp, _vp, _vp, _i]),
+    "dwf_cg": (_i, [_vp, _vp, _vp, _i, _d, _i, _c_int_p, _c_dbl_p]),
+    "dwf_solve_rb": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p]),
+    "dwf_power": (_i, [_vp, _vp, _i, _d, _c_dbl_p, _c_int_p]),
+    "dwf_chebyshev_filter": (_i, [_vp, _i, _d, _d, _vp, _i]),
+    "dwf_chebyshev_series": (_i, [_vp, _i, _d, _d, _i, _i, _vp, _vp]),
+    "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
+    "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_set_tile": (_i, [_vp, _i, _i]),
+    "dwf_enable_timing": (_i, [_vp, _i]),
+    "dwf_kernel_time": (_i, [_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdwf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2103_05034_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().dwf_last_error().decode()
+
+
+def _check(code, allow=()):
+    if code != DWF_OK and code not in allow:
+        raise DWFError(code, last_error())
+    return code
+
+
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(d) for d in dims])
+
+
+# ---- thin functions with the C names -------------------------------------------------
+def dwf_workspace_bytes(dims, Ls, prec, max_nrhs, max_cg_rhs):
+    return load_library().dwf_workspace_bytes(_dims(dims), Ls, prec, max_nrhs, max_cg_rhs)
+
+
+def dwf_field_bytes(dims, Ls, prec, nrhs):
+    return load_library().dwf_field_bytes(_dims(dims), Ls, prec, nrhs)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr() if hasattr(t, "data_ptr") else int(t))
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Operator:
+    """A libdwf handle with its torch-allocated workspace.
+
+    ``U`` is a complex128 CUDA tensor ``[T][Z][Y][X][4][3][3]``; ``dims`` =
+    (X, Y, Z, T).  ``prec`` selects the storage precision of the handle's
+    packed fields; ``max_nrhs`` the batch held by the operator temporaries;
+    ``max_cg_rhs`` the number of simultaneous CG right-hand sides.
+    """
+
+    def __init__(self, U, dims, Ls, M5, mf, prec=DWF_F64, max_nrhs=1, max_cg_rhs=1):
+        import torch
+
+        lib = load_library()
+        self.lib = lib
+        self.dims = tuple(int(d) for d in dims)
+        self.Ls, self.M5, self.mf, self.prec = int(Ls), float(M5), float(mf), int(prec)
+        self.max_nrhs, self.max_cg_rhs = int(max_nrhs), int(max_cg_rhs)
+        self.device = U.device
+        nbytes = lib.dwf_workspace_bytes(_dims(self.dims), self.Ls, self.prec, self.max_nrhs, self.max_cg_rhs)
+        if nbytes == 0:
+            raise DWFError(DWF_EINVAL, last_error())
+        # 256-byte alignment: torch's caching allocator returns >= 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=U.device)
+        self.U = U.contiguous()
+        h = ctypes.c_void_p()
+        _check(
+            lib.dwf_create(
+                ctypes.byref(h), _ptr(self.U), _dims(self.dims), self.Ls, self.M5, self.mf, self.prec,
+                self.max_nrhs, self.max_cg_rhs, _ptr(self.workspace), nbytes, _stream(),
+            )
+        )
+        self.h = h
+        X, Y, Z, T = self.dims
+        self.V4 = X * Y * Z * T
+        self.V4h = self.V4 // 2
+
+    # -- memory helpers -------------------------------------------------------
+    def field_bytes(self, nrhs=1, prec=None):
+        p = self.prec if prec is None else prec
+        return self.lib.dwf_field_bytes(_dims(self.dims), self.Ls, p, int(nrhs))
+
+    def new_field(self, nrhs=1, both=False, prec=None):
+        import torch
+
+        n = self.field_bytes(nrhs, prec) * (2 if both else 1)
+        return torch.zeros(n, dtype=torch.uint8, device=self.device)
+
+    def natural_shape(self, nrhs=1):
+        X, Y, Z, T = self.dims
+        return (nrhs, self.Ls, T, Z, Y, X, 4, 3)
+
+    def _sync_stream(self):
+        self.lib.dwf_set_stream(self.h, _stream())
+
+    # -- ABI calls ------------------------------------------------------------
+    def update_links(self, U):
+        self.U = U.contiguous()
+        _check(self.lib.dwf_update_links(self.h, _ptr(self.U)))
+
+    def pack(self, natural, parity, out=None):
+        nrhs = natural.shape[0]
+        if out is None:
+            out = self.new_field(nrhs, both=(parity == DWF_BOTH))
+        self._sync_stream()
+        _check(self.lib.dwf_pack(self.h, _ptr(natural.contiguous()), _ptr(out), nrhs, parity))
+        return out
+
+    def unpack(self, packed, nrhs, parity, out=None):
+        import torch
+
+        if out is None:
+            out = torch.zeros(self.natural_shape(nrhs), dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        _check(self.lib.dwf_unpack(self.h, _ptr(packed), _ptr(out), nrhs, parity))
+        return out
+
+    def dhop(self, inp, out, out_parity, nrhs=1, dagger=False):
+        self._sync_stream()
+        _check(self.lib.dwf_dhop(self.h, _ptr(inp), _ptr(out), out_parity, nrhs, int(dagger)))
+        return out
+
+    def m5d(self, inp, out, nrhs=1, dagger=False):
+        self._sync_stream()
+        _check(self.lib.dwf_m5d(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        return out
+
+    def m5d_inv(self, inp, out, nrhs=1, dagger=False):
+        self._sync_stream()
+        _check(self.lib.dwf_m5d_inv(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        return out
+
+    def ddw(self, inp, out, nrhs=1, dagger=False):
+        self._sync_stream()
+        _check(self.lib.dwf_ddw(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        return out
+
+    def mpc(self, inp, out, nrhs=1, dagger=False):
+        self._sync_stream()
+        _check(self.lib.dwf_mpc(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        return out
+
+    def mpcdagmpc(self, inp, out, nrhs=1):
+        self._sync_stream()
+        _check(self.lib.dwf_mpcdagmpc(self.h, _ptr(inp), _ptr(out), nrhs))
+        return out
+
+    def cg(self, b, x, nrhs=1, tol=1e-10, maxiter=10000, allow_noconv=False):
+        """Synchronous CG on M_pc^dag M_pc (b, x FP64 packed); returns (status, iters, true_rel_resid)."""
+        it = (ctypes.c_int * nrhs)()
+        res = (ctypes.c_double * nrhs)()
+        self._sync_stream()
+        code = self.lib.dwf_cg(self.h, _ptr(b), _ptr(x), nrhs, tol, maxiter, it, res)
+        _check(code, allow=(DWF_ENOCONV,) if allow_noconv else ())
+        return code, list(it), list(res)
+
+    def solve_rb(self, eta, psi, tol=1e-10, maxiter=10000):
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        self._sync_stream()
+        code = self.lib.dwf_solve_rb(self.h, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
+        _check(code)
+        return it.value, res.value
+
+    def power(self, v, iters=100, rtol=1e-6):
+        lam = ctypes.c_double()
+        done = ctypes.c_int()
+        self._sync_stream()
+        _check(self.lib.dwf_power(self.h, _ptr(v), iters, rtol, ctypes.byref(lam), ctypes.byref(done)))
+        return lam.value, done.value
+
+    def chebyshev_filter(self, vecs, nvecs, order, lo, hi):
+        self._sync_stream()
+        _check(self.lib.dwf_chebyshev_filter(self.h, order, lo, hi, _ptr(vecs), nvecs))
+        return vecs
+
+    def chebyshev_series(self, eta, out_series, m, lam_lo, lam_max, delta, nvec):
+        self._sync_stream()
+        _check(self.lib.dwf_chebyshev_series(self.h, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out_series)))
+        return out_series
+
+    def gram_schmidt(self, vecs, nvecs):
+        import numpy as np
+
+        R = (ctypes.c_double * (2 * nvecs * nvecs))()
+        self._sync_stream()
+        _check(self.lib.dwf_gram_schmidt(self.h, _ptr(vecs), nvecs, R))
+        r = np.frombuffer(R, dtype=np.float64).reshape(nvecs, nvecs, 2)
+        return r[..., 0] + 1j * r[..., 1]
+
+    def force(self, X_e, Y_e, grad=None):
+        import torch
+
+        if grad is None:
+            X, Y, Z, T = self.dims
+            grad = torch.zeros((T, Z, Y, X, 4, 3, 3), dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        _check(self.lib.dwf_force(self.h, _ptr(X_e), _ptr(Y_e), _ptr(grad)))
+        return grad
+
+    def set_tile(self, sites_per_block, rhs_per_block=0):
+        _check(self.lib.dwf_set_tile(self.h, sites_per_block, rhs_per_block))
+
+    def enable_timing(self, on=True):
+        _check(self.lib.dwf_enable_timing(self.h, int(on)))
+
+    def kernel_time(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        _check(self.lib.dwf_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dwf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

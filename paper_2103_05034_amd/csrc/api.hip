@@ -1,0 +1,770 @@
+// extern "C" entry points of libdwf: argument checks, workspace carving and the
+// host-side drivers of the red-black operator, CG, the Chebyshev filter, the
+// power method, Gram-Schmidt and the force.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "dwf_internal.hpp"
+#include "kernels.hpp"
+
+using namespace dwf;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(DWF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+constexpr size_t ALIGN = 256;
+constexpr int GS_MAX = 256;
+
+size_t up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool valid_dims(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs, std::string* why) {
+  if (!dims) {
+    *why = "dims is NULL";
+    return false;
+  }
+  for (int i = 0; i < 4; ++i)
+    if (dims[i] < 2 || (dims[i] & 1)) {
+      char b[96];
+      snprintf(b, sizeof b, "lattice extent %d (dim %d) must be even and >= 2", dims[i], i);
+      *why = b;
+      return false;
+    }
+  if (Ls < 1 || Ls > 128) {
+    *why = "Ls must be in [1, 128]";
+    return false;
+  }
+  if (prec != DWF_F64 && prec != DWF_F32 && prec != DWF_F16S) {
+    *why = "unknown precision";
+    return false;
+  }
+  if (max_nrhs < 1 || max_nrhs > 4096 || max_cg_rhs < 0 || max_cg_rhs > 4096) {
+    *why = "max_nrhs must be in [1, 4096], max_cg_rhs in [0, 4096]";
+    return false;
+  }
+  const long long V4 = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+  if (V4 / 2 > (1LL << 31) - 1) {
+    *why = "lattice too large for 32-bit neighbour indices";
+    return false;
+  }
+  return true;
+}
+
+// Carves (or sizes, when base == nullptr) the workspace; returns bytes used.
+size_t carve(dwf_context* c, const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs, char* base) {
+  const long long V4 = (long long)dims[0] * dims[1] * dims[2] * dims[3];
+  const long long V4h = V4 / 2;
+  auto fb = [&](int p) { return spinor_bytes(p) * (size_t)Ls * (size_t)V4h; };
+  size_t off = 0;
+  auto take = [&](size_t n) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += up(n);
+    return p;
+  };
+  const int chunk = max_nrhs > max_cg_rhs ? max_nrhs : max_cg_rhs;
+  dwf_context tmp{};
+  dwf_context* d = c ? c : &tmp;
+  d->links64 = take((size_t)2 * 8 * 9 * V4h * 16);
+  d->links32 = prec != DWF_F64 ? take((size_t)2 * 8 * 9 * V4h * 8) : nullptr;
+  d->nbr = reinterpret_cast<int*>(take((size_t)2 * 8 * V4h * 4));
+  d->t_buf = take(fb(prec) * chunk);
+  d->u_buf = take(fb(prec) * chunk);
+  d->cheb_a = take(fb(prec) * (max_nrhs > 2 ? max_nrhs : 2));
+  if (max_cg_rhs > 0) {
+    d->r64 = take(fb(DWF_F64) * max_cg_rhs);
+    d->p64 = take(fb(DWF_F64) * max_cg_rhs);
+    d->q64 = take(fb(DWF_F64) * max_cg_rhs);
+    d->b64 = take(fb(DWF_F64) * max_cg_rhs);
+    if (prec != DWF_F64) {
+      d->t64 = take(fb(DWF_F64) * max_cg_rhs);
+      d->u64 = take(fb(DWF_F64) * max_cg_rhs);
+      d->lo_r = take(fb(DWF_F32) * max_cg_rhs);
+      d->lo_x = take(fb(DWF_F32) * max_cg_rhs);
+      d->lo_p = take(fb(prec) * max_cg_rhs);
+      d->lo_q = take(fb(prec) * max_cg_rhs);
+    } else {
+      d->t64 = d->t_buf;
+      d->u64 = d->u_buf;
+    }
+  }
+  int pc = chunk;
+  d->partial_count = (size_t)pc;
+  d->partials = reinterpret_cast<double*>(take((size_t)pc * RED_BLOCKS * 2 * sizeof(double)));
+  d->scalars = reinterpret_cast<double*>(take((size_t)(chunk * NSCAL) * sizeof(double)));
+  d->coef = reinterpret_cast<double*>(take((size_t)(4 * GS_MAX + 8) * sizeof(double)));
+  return off;
+}
+
+int check_h(dwf_handle h) {
+  if (!h) return fail(DWF_EINVAL, "null handle");
+  return DWF_OK;
+}
+
+size_t fbytes(const dwf_context* c, int prec) { return field_bytes_rhs(c, prec); }
+
+// ---------------------------------------------------------------------------
+// Operator compositions (one chunk of at most the temporaries' capacity).
+// ---------------------------------------------------------------------------
+hipError_t mpc_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, int n, int dag) {
+  HopArgs a{};
+  a.in = in;
+  a.out = t;
+  a.alpha = 1.0;
+  hipError_t e = launch_hop(c, prec, a, DWF_ODD, dag, EPI_M5INV, n);
+  if (e != hipSuccess) return e;
+  HopArgs b{};
+  b.in = t;
+  b.x = in;
+  b.out = out;
+  b.alpha = -0.25;
+  return launch_hop(c, prec, b, DWF_EVEN, dag, EPI_M5, n);
+}
+
+hipError_t mdagm_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, char* u, int n) {
+  hipError_t e = mpc_chunk(c, prec, in, u, t, n, 0);
+  if (e != hipSuccess) return e;
+  return mpc_chunk(c, prec, u, out, t, n, 1);
+}
+
+// out = ca * A in + cb * y + cc * z   (A = M_pc^dag M_pc; out may alias z)
+hipError_t cheb_step(dwf_context* c, int prec, const char* in, char* out, const char* y, const char* z, double ca,
+                     double cb, double cc, char* t, char* u, int n) {
+  hipError_t e = mpc_chunk(c, prec, in, u, t, n, 0);
+  if (e != hipSuccess) return e;
+  HopArgs a{};
+  a.in = u;
+  a.out = t;
+  a.alpha = 1.0;
+  e = launch_hop(c, prec, a, DWF_ODD, 1, EPI_M5INV, n);
+  if (e != hipSuccess) return e;
+  HopArgs b{};
+  b.in = t;
+  b.x = u;
+  b.y = y;
+  b.z = z;
+  b.out = out;
+  b.alpha = -0.25;
+  b.ca = ca;
+  b.cb = cb;
+  b.cc = cc;
+  return launch_hop(c, prec, b, DWF_EVEN, 1, EPI_CHEB, n);
+}
+
+int sync(dwf_context* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(DWF_EHIP, "stream synchronize: %s", hipGetErrorString(e));
+  return DWF_OK;
+}
+
+int read_scalars(dwf_context* c, int nrhs, std::vector<double>& out) {
+  out.resize((size_t)nrhs * NSCAL);
+  hipError_t e = hipMemcpyAsync(out.data(), c->scalars, out.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return fail(DWF_EHIP, "scalar readback: %s", hipGetErrorString(e));
+  return sync(c);
+}
+
+}  // namespace
+
+// kernel timing (used by launch_hop)
+namespace dwf {
+void timing_begin(dwf_context* ctx) {
+  if (!ctx->timing) return;
+  if (ctx->ev_used == ctx->ev_pool.size()) {
+    // drain
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& p : ctx->ev_pool) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, p.a, p.b);
+      ctx->ev_ms += ms;
+    }
+    ctx->ev_launches += (long long)ctx->ev_pool.size();
+    ctx->ev_used = 0;
+  }
+  (void)hipEventRecord(ctx->ev_pool[ctx->ev_used].a, ctx->stream);
+}
+void timing_end(dwf_context* ctx) {
+  if (!ctx->timing) return;
+  (void)hipEventRecord(ctx->ev_pool[ctx->ev_used].b, ctx->stream);
+  ctx->ev_used++;
+}
+}  // namespace dwf
+
+extern "C" {
+
+const char* dwf_last_error(void) { return g_err.c_str(); }
+
+size_t dwf_field_bytes(const int dims[4], int Ls, int prec, int nrhs) {
+  std::string why;
+  if (!valid_dims(dims, Ls, prec, 1, 0, &why) || nrhs < 0) {
+    fail(DWF_EINVAL, "%s", why.c_str());
+    return 0;
+  }
+  const long long V4h = (long long)dims[0] * dims[1] * dims[2] * dims[3] / 2;
+  return spinor_bytes(prec) * (size_t)Ls * (size_t)V4h * (size_t)nrhs;
+}
+
+size_t dwf_workspace_bytes(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs) {
+  std::string why;
+  if (!valid_dims(dims, Ls, prec, max_nrhs, max_cg_rhs, &why)) {
+    fail(DWF_EINVAL, "%s", why.c_str());
+    return 0;
+  }
+  return carve(nullptr, dims, Ls, prec, max_nrhs, max_cg_rhs, nullptr);
+}
+
+int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double M5, double mf, int prec,
+               int max_nrhs, int max_cg_rhs, void* workspace, size_t ws_bytes, void* stream) {
+  if (!out) return fail(DWF_EINVAL, "handle pointer is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!valid_dims(dims, Ls, prec, max_nrhs, max_cg_rhs, &why)) return fail(DWF_EINVAL, "%s", why.c_str());
+  if (!U || !workspace) return fail(DWF_EINVAL, "U and workspace must be device pointers");
+  if (!std::isfinite(M5) || !std::isfinite(mf) || M5 == 5.0) return fail(DWF_EINVAL, "M5 must be finite and != 5");
+  const size_t need = carve(nullptr, dims, Ls, prec, max_nrhs, max_cg_rhs, nullptr);
+  if (ws_bytes < need) return fail(DWF_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(DWF_EINVAL, "workspace must be 256-byte aligned");
+  dwf_context* c = new (std::nothrow) dwf_context();
+  if (!c) return fail(DWF_ENOMEM, "host allocation failed");
+  c->g = {dims[0], dims[1], dims[2], dims[3], Ls, (long long)dims[0] * dims[1] * dims[2] * dims[3], 0};
+  c->g.V4h = c->g.V4 / 2;
+  c->M5 = M5;
+  c->mf = mf;
+  c->prec = prec;
+  c->max_nrhs = max_nrhs;
+  c->max_cg_rhs = max_cg_rhs;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->ws = reinterpret_cast<char*>(workspace);
+  c->ws_bytes = ws_bytes;
+  carve(c, dims, Ls, prec, max_nrhs, max_cg_rhs, c->ws);
+  c->spb = 0;
+  c->timing = false;
+  c->ev_used = 0;
+  c->ev_ms = 0;
+  c->ev_launches = 0;
+  hipError_t e = launch_pack_links(c, U);
+  if (e == hipSuccess) e = launch_neighbours(c);
+  if (e == hipSuccess) e = hipMemsetAsync(c->scalars, 0, (size_t)(c->partial_count * NSCAL) * sizeof(double), c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(DWF_EHIP, "set-up launch failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return DWF_OK;
+}
+
+int dwf_update_links(dwf_handle h, const void* U) {
+  if (int r = check_h(h)) return r;
+  if (!U) return fail(DWF_EINVAL, "U is NULL");
+  HIP_TRY(launch_pack_links(h, U));
+  return DWF_OK;
+}
+
+int dwf_set_stream(dwf_handle h, void* stream) {
+  if (int r = check_h(h)) return r;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  return DWF_OK;
+}
+
+int dwf_destroy(dwf_handle h) {
+  if (!h) return DWF_OK;
+  for (auto& p : h->ev_pool) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  delete h;
+  return DWF_OK;
+}
+
+int dwf_pack(dwf_handle h, const void* natural, void* packed, int nrhs, int parity) {
+  if (int r = check_h(h)) return r;
+  if (!natural || !packed || nrhs < 1 || nrhs > 65535 || parity < 0 || parity > 2)
+    return fail(DWF_EINVAL, "dwf_pack: bad argument");
+  HIP_TRY(launch_pack(h, h->prec, natural, reinterpret_cast<char*>(packed), nrhs, parity, false));
+  return DWF_OK;
+}
+
+int dwf_unpack(dwf_handle h, const void* packed, void* natural, int nrhs, int parity) {
+  if (int r = check_h(h)) return r;
+  if (!natural || !packed || nrhs < 1 || nrhs > 65535 || parity < 0 || parity > 2)
+    return fail(DWF_EINVAL, "dwf_unpack: bad argument");
+  HIP_TRY(launch_pack(h, h->prec, natural, const_cast<char*>(reinterpret_cast<const char*>(packed)), nrhs, parity,
+                      true));
+  return DWF_OK;
+}
+
+static int check_io(const void* in, const void* out, int nrhs) {
+  if (!in || !out) return fail(DWF_EINVAL, "null field pointer");
+  if (in == out) return fail(DWF_EINVAL, "in and out must not alias");
+  if (nrhs < 1 || nrhs > 65535) return fail(DWF_EINVAL, "nrhs %d out of range", nrhs);
+  return DWF_OK;
+}
+
+int dwf_dhop(dwf_handle h, const void* in, void* out, int out_parity, int nrhs, int dagger) {
+  if (int r = check_h(h)) return r;
+  if (int r = check_io(in, out, nrhs)) return r;
+  if (out_parity != DWF_EVEN && out_parity != DWF_ODD) return fail(DWF_EINVAL, "out_parity must be 0 or 1");
+  HopArgs a{};
+  a.in = reinterpret_cast<const char*>(in);
+  a.out = reinterpret_cast<char*>(out);
+  a.alpha = 1.0;
+  HIP_TRY(launch_hop(h, h->prec, a, out_parity, dagger ? 1 : 0, EPI_LIN, nrhs));
+  return DWF_OK;
+}
+
+int dwf_m5d(dwf_handle h, const void* in, void* out, int nrhs, int dagger) {
+  if (int r = check_h(h)) return r;
+  if (int r = check_io(in, out, nrhs)) return r;
+  HIP_TRY(launch_site5(h, h->prec, reinterpret_cast<const char*>(in), reinterpret_cast<char*>(out), dagger ? 1 : 0, 0,
+                       nrhs));
+  return DWF_OK;
+}
+
+int dwf_m5d_inv(dwf_handle h, const void* in, void* out, int nrhs, int dagger) {
+  if (int r = check_h(h)) return r;
+  if (!in || !out || nrhs < 1 || nrhs > 65535) return fail(DWF_EINVAL, "dwf_m5d_inv: bad argument");
+  HIP_TRY(launch_site5(h, h->prec, reinterpret_cast<const char*>(in), reinterpret_cast<char*>(out), dagger ? 1 : 0, 1,
+                       nrhs));
+  return DWF_OK;
+}
+
+int dwf_ddw(dwf_handle h, const void* in, void* out, int nrhs, int dagger) {
+  if (int r = check_h(h)) return r;
+  if (int r = check_io(in, out, nrhs)) return r;
+  const size_t half = fbytes(h, h->prec) * nrhs;
+  const char* in_c = reinterpret_cast<const char*>(in);
+  char* out_c = reinterpret_cast<char*>(out);
+  for (int p = 0; p < 2; ++p) {
+    HopArgs a{};
+    a.in = in_c + (1 - p) * half;
+    a.x = in_c + p * half;
+    a.out = out_c + p * half;
+    a.alpha = -0.5;
+    HIP_TRY(launch_hop(h, h->prec, a, p, dagger ? 1 : 0, EPI_M5, nrhs));
+  }
+  return DWF_OK;
+}
+
+int dwf_mpc(dwf_handle h, const void* in_e, void* out_e, int nrhs, int dagger) {
+  if (int r = check_h(h)) return r;
+  if (int r = check_io(in_e, out_e, nrhs)) return r;
+  const size_t fb = fbytes(h, h->prec);
+  for (int r0 = 0; r0 < nrhs; r0 += h->max_nrhs) {
+    const int n = nrhs - r0 < h->max_nrhs ? nrhs - r0 : h->max_nrhs;
+    HIP_TRY(mpc_chunk(h, h->prec, reinterpret_cast<const char*>(in_e) + r0 * fb, reinterpret_cast<char*>(out_e) + r0 * fb,
+                      h->t_buf, n, dagger ? 1 : 0));
+  }
+  return DWF_OK;
+}
+
+int dwf_mpcdagmpc(dwf_handle h, const void* in_e, void* out_e, int nrhs) {
+  if (int r = check_h(h)) return r;
+  if (int r = check_io(in_e, out_e, nrhs)) return r;
+  const size_t fb = fbytes(h, h->prec);
+  for (int r0 = 0; r0 < nrhs; r0 += h->max_nrhs) {
+    const int n = nrhs - r0 < h->max_nrhs ? nrhs - r0 : h->max_nrhs;
+    HIP_TRY(mdagm_chunk(h, h->prec, reinterpret_cast<const char*>(in_e) + r0 * fb,
+                        reinterpret_cast<char*>(out_e) + r0 * fb, h->t_buf, h->u_buf, n));
+  }
+  return DWF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CG
+// ---------------------------------------------------------------------------
+static int finish_cg(dwf_handle h, int nrhs, int maxiter, int* iters, double* resid, const std::vector<double>& sc,
+                     const std::vector<double>& tr) {
+  bool nconv = false, brk = false;
+  for (int r = 0; r < nrhs; ++r) {
+    const double* s = &sc[(size_t)r * NSCAL];
+    if (iters) iters[r] = (int)s[S_ITERS];
+    const double bb = s[S_BB];
+    const double rel = bb > 0 ? std::sqrt(tr[r] / bb) : 0.0;
+    if (resid) resid[r] = rel;
+    if (s[S_FLAG] != 0.0 || !std::isfinite(rel)) brk = true;
+    if (s[S_ACTIVE] != 0.0) nconv = true;
+  }
+  if (brk) return fail(DWF_EBREAKDOWN, "CG breakdown (non-finite or non-positive curvature)");
+  if (nconv) return fail(DWF_ENOCONV, "CG did not converge in %d iterations", maxiter);
+  return DWF_OK;
+}
+
+// r = b - A x in FP64 and |r|^2 -> slot, using FP64 temporaries
+static hipError_t true_residual(dwf_handle h, const char* b, const char* x, char* r, int nrhs, int slot) {
+  hipError_t e = mdagm_chunk(h, DWF_F64, x, r, h->t64, h->u64, nrhs);  // r = A x
+  if (e != hipSuccess) return e;
+  e = blas_axpby(h, DWF_F64, b, DWF_F64, r, nrhs, 1.0, -1.0, -1, -1, 1);  // r = b - A x
+  if (e != hipSuccess) return e;
+  return blas_dot(h, DWF_F64, r, DWF_F64, r, nrhs, slot, false);
+}
+
+static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, int maxiter, int* iters, double* resid) {
+  const double tol2 = tol * tol;
+  char *r = h->r64, *p = h->p64, *q = h->q64;
+  HIP_TRY(true_residual(h, b, x, r, nrhs, S_RR));
+  HIP_TRY(blas_dot(h, DWF_F64, b, DWF_F64, b, nrhs, S_BB, false));
+  HIP_TRY(blas_copy(h, DWF_F64, r, DWF_F64, p, nrhs));
+  HIP_TRY(scal_set(h, nrhs, S_ACTIVE, 1.0));
+  HIP_TRY(scal_set(h, nrhs, S_FLAG, 0.0));
+  HIP_TRY(scal_set(h, nrhs, S_ITERS, 0.0));
+  HIP_TRY(scal_converge(h, nrhs, tol2, false));
+  std::vector<double> sc;
+  const int check = 8;
+  for (int it = 0; it < maxiter; ++it) {
+    if (it % check == 0) {
+      if (int rc = read_scalars(h, nrhs, sc)) return rc;
+      bool any = false;
+      for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
+      if (!any) break;
+    }
+    HIP_TRY(mdagm_chunk(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
+    HIP_TRY(blas_dot(h, DWF_F64, p, DWF_F64, q, nrhs, S_PAP, false));
+    HIP_TRY(scal_alpha(h, nrhs));
+    HIP_TRY(cg_update_xr(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, DWF_F64, q, nrhs));
+    HIP_TRY(scal_beta(h, nrhs));
+    HIP_TRY(cg_update_p(h, DWF_F64, r, DWF_F64, p, nrhs));
+    HIP_TRY(scal_converge(h, nrhs, tol2, true));
+  }
+  // true residual at exit
+  HIP_TRY(true_residual(h, b, x, q, nrhs, S_TRUE));
+  if (int rc = read_scalars(h, nrhs, sc)) return rc;
+  std::vector<double> tr(nrhs);
+  for (int rr = 0; rr < nrhs; ++rr) tr[rr] = sc[(size_t)rr * NSCAL + S_TRUE];
+  return finish_cg(h, nrhs, maxiter, iters, resid, sc, tr);
+}
+
+// Low-precision CG with FP64 reliable updates.
+static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, int maxiter, int* iters,
+                    double* resid) {
+  const int P = h->prec;
+  const double tol2 = tol * tol;
+  const double delta2 = 0.01;  // reliable update when |r| drops 10x
+  char* r64 = h->r64;
+  HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
+  HIP_TRY(blas_dot(h, DWF_F64, b, DWF_F64, b, nrhs, S_BB, false));
+  HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
+  HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
+  HIP_TRY(blas_copy(h, DWF_F64, r64, DWF_F32, h->lo_r, nrhs));
+  HIP_TRY(blas_copy(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+  HIP_TRY(blas_zero(h, DWF_F32, h->lo_x, nrhs));
+  HIP_TRY(scal_set(h, nrhs, S_ACTIVE, 1.0));
+  HIP_TRY(scal_set(h, nrhs, S_FLAG, 0.0));
+  HIP_TRY(scal_set(h, nrhs, S_ITERS, 0.0));
+  HIP_TRY(scal_converge(h, nrhs, tol2, false));
+  std::vector<double> sc;
+  if (int rc = read_scalars(h, nrhs, sc)) return rc;
+  bool pending = false;  // lo_x holds an update not yet folded into x
+  for (int it = 0; it < maxiter; ++it) {
+    bool any = false;
+    for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
+    if (!any) break;
+    HIP_TRY(mdagm_chunk(h, P, h->lo_p, h->lo_q, h->t_buf, h->u_buf, nrhs));
+    HIP_TRY(blas_dot(h, P, h->lo_p, P, h->lo_q, nrhs, S_PAP, false));
+    HIP_TRY(scal_alpha(h, nrhs));
+    HIP_TRY(cg_update_xr(h, DWF_F32, h->lo_x, DWF_F32, h->lo_r, P, h->lo_p, P, h->lo_q, nrhs));
+    pending = true;
+    if (int rc = read_scalars(h, nrhs, sc)) return rc;
+    bool update = false;
+    for (int rr = 0; rr < nrhs; ++rr) {
+      const double* s = &sc[(size_t)rr * NSCAL];
+      if (s[S_ACTIVE] == 0.0) continue;
+      if (s[S_RR] < delta2 * s[S_RRMAX] || s[S_RR] < tol2 * s[S_BB] || !std::isfinite(s[S_RR])) update = true;
+    }
+    if (update) {
+      HIP_TRY(blas_axpby(h, DWF_F32, h->lo_x, DWF_F64, x, nrhs, 1.0, 1.0, -1, -1, 1));
+      HIP_TRY(blas_zero(h, DWF_F32, h->lo_x, nrhs));
+      pending = false;
+      HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
+      HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
+      HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
+      HIP_TRY(blas_copy(h, DWF_F64, r64, DWF_F32, h->lo_r, nrhs));
+    }
+    HIP_TRY(scal_beta(h, nrhs));
+    HIP_TRY(cg_update_p(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+    HIP_TRY(scal_converge(h, nrhs, tol2, true, update ? 1 : 0));
+    if (update) {
+      if (int rc = read_scalars(h, nrhs, sc)) return rc;
+    }
+  }
+  if (pending) {
+    HIP_TRY(blas_axpby(h, DWF_F32, h->lo_x, DWF_F64, x, nrhs, 1.0, 1.0, -1, -1, 1));
+  }
+  HIP_TRY(true_residual(h, b, x, r64, nrhs, S_TRUE));
+  if (int rc = read_scalars(h, nrhs, sc)) return rc;
+  std::vector<double> tr(nrhs);
+  for (int rr = 0; rr < nrhs; ++rr) tr[rr] = sc[(size_t)rr * NSCAL + S_TRUE];
+  return finish_cg(h, nrhs, maxiter, iters, resid, sc, tr);
+}
+
+int dwf_cg(dwf_handle h, const void* b, void* x, int nrhs, double tol, int maxiter, int* iters,
+           double* true_rel_resid) {
+  if (int r = check_h(h)) return r;
+  if (!b || !x || b == x) return fail(DWF_EINVAL, "dwf_cg: b and x must be distinct device pointers");
+  if (nrhs < 1 || nrhs > h->max_cg_rhs) return fail(DWF_EINVAL, "dwf_cg: nrhs %d outside [1, %d]", nrhs, h->max_cg_rhs);
+  if (!(tol > 0) || maxiter < 0) return fail(DWF_EINVAL, "dwf_cg: tol must be > 0 and maxiter >= 0");
+  if (h->prec == DWF_F64)
+    return cg_f64(h, reinterpret_cast<const char*>(b), reinterpret_cast<char*>(x), nrhs, tol, maxiter, iters,
+                  true_rel_resid);
+  return cg_mixed(h, reinterpret_cast<const char*>(b), reinterpret_cast<char*>(x), nrhs, tol, maxiter, iters,
+                  true_rel_resid);
+}
+
+int dwf_solve_rb(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters, double* resid) {
+  if (int r = check_h(h)) return r;
+  if (!eta || !psi || eta == psi) return fail(DWF_EINVAL, "dwf_solve_rb: eta and psi must be distinct");
+  if (h->max_cg_rhs < 1) return fail(DWF_EINVAL, "dwf_solve_rb: handle was created without solver workspace");
+  const size_t fb = fbytes(h, DWF_F64);
+  const char* eta_e = reinterpret_cast<const char*>(eta);
+  const char* eta_o = eta_e + fb;
+  char* psi_e = reinterpret_cast<char*>(psi);
+  char* psi_o = psi_e + fb;
+  // t = M5D^{-1} eta_o ; eta' = eta_e + D_hop^{eo} t / 2 (into psi_o as scratch)
+  HIP_TRY(launch_site5(h, DWF_F64, eta_o, h->t64, 0, 1, 1));
+  HopArgs a{};
+  a.in = h->t64;
+  a.x = eta_e;
+  a.out = psi_o;
+  a.alpha = 0.5;
+  a.beta = 1.0;
+  HIP_TRY(launch_hop(h, DWF_F64, a, DWF_EVEN, 0, EPI_LIN, 1));
+  // b = M_pc^dag eta'
+  HIP_TRY(mpc_chunk(h, DWF_F64, psi_o, h->b64, h->t64, 1, 1));
+  int rc = dwf_cg(h, h->b64, psi_e, 1, tol, maxiter, iters, resid);
+  if (rc != DWF_OK && rc != DWF_ENOCONV) return rc;
+  // psi_o = M5D^{-1} (eta_o + D_hop^{oe} psi_e / 2)
+  HopArgs c{};
+  c.in = psi_e;
+  c.x = eta_o;
+  c.out = psi_o;
+  c.alpha = 0.5;
+  c.beta = 1.0;
+  HIP_TRY(launch_hop(h, DWF_F64, c, DWF_ODD, 0, EPI_M5INV, 1));
+  if (int r2 = sync(h)) return r2;
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Power method, Chebyshev filter and series, Gram-Schmidt
+// ---------------------------------------------------------------------------
+int dwf_power(dwf_handle h, void* v, int iters, double rtol, double* lambda_max, int* iters_done) {
+  if (int r = check_h(h)) return r;
+  if (!v || iters < 1) return fail(DWF_EINVAL, "dwf_power: bad argument");
+  const int P = h->prec;
+  char* vv = reinterpret_cast<char*>(v);
+  char* w = h->cheb_a;
+  std::vector<double> sc;
+  HIP_TRY(blas_dot(h, P, vv, P, vv, 1, S_TMP, false));
+  if (int rc = read_scalars(h, 1, sc)) return rc;
+  double nv = std::sqrt(sc[S_TMP]);
+  if (!(nv > 0)) return fail(DWF_EINVAL, "dwf_power: zero start vector");
+  HIP_TRY(blas_axpby(h, P, nullptr, P, vv, 1, 0.0, 1.0 / nv, -1, -1, 1));
+  double lam = 0;
+  int k = 0;
+  for (k = 0; k < iters; ++k) {
+    HIP_TRY(mdagm_chunk(h, P, vv, w, h->t_buf, h->u_buf, 1));
+    HIP_TRY(blas_dot(h, P, vv, P, w, 1, S_TMP, false));
+    HIP_TRY(blas_dot(h, P, w, P, w, 1, S_TRUE, false));
+    if (int rc = read_scalars(h, 1, sc)) return rc;
+    const double lam_new = sc[S_TMP];
+    const double nw = std::sqrt(sc[S_TRUE]);
+    if (!(nw > 0) || !std::isfinite(nw)) return fail(DWF_EBREAKDOWN, "dwf_power: non-finite iterate");
+    HIP_TRY(blas_axpby(h, P, w, P, vv, 1, 1.0 / nw, 0.0, -1, -1, 1));
+    if (k > 0 && std::fabs(lam_new - lam) < rtol * std::fabs(lam_new)) {
+      lam = lam_new;
+      ++k;
+      break;
+    }
+    lam = lam_new;
+  }
+  if (int rc = sync(h)) return rc;
+  if (lambda_max) *lambda_max = lam;
+  if (iters_done) *iters_done = k;
+  return DWF_OK;
+}
+
+// In place T_order(x(A)) on one chunk V of n rhs; partner buffer W.
+static int cheb_chunk(dwf_handle h, int order, double lo, double hi, char* V, char* W, int n) {
+  if (order == 0) return DWF_OK;
+  const int P = h->prec;
+  const double w = hi - lo;
+  // T1 = x(A) V = (2/w) A V - ((hi+lo)/w) V
+  HIP_TRY(cheb_step(h, P, V, W, V, V, 2.0 / w, -(hi + lo) / w, 0.0, h->t_buf, h->u_buf, n));
+  char* prev = V;
+  char* cur = W;
+  for (int k = 1; k < order; ++k) {
+    // T_{k+1} = (4/w) A T_k - (2(hi+lo)/w) T_k - T_{k-1}, written over T_{k-1}
+    HIP_TRY(cheb_step(h, P, cur, prev, cur, prev, 4.0 / w, -2.0 * (hi + lo) / w, -1.0, h->t_buf, h->u_buf, n));
+    char* t = prev;
+    prev = cur;
+    cur = t;
+  }
+  if (cur != V) HIP_TRY(blas_copy(h, P, cur, P, V, n));
+  return DWF_OK;
+}
+
+int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* vecs, int nvecs) {
+  if (int r = check_h(h)) return r;
+  if (!vecs || nvecs < 1 || order < 0 || !(hi > lo)) return fail(DWF_EINVAL, "dwf_chebyshev_filter: bad argument");
+  const size_t fb = fbytes(h, h->prec);
+  for (int r0 = 0; r0 < nvecs; r0 += h->max_nrhs) {
+    const int n = nvecs - r0 < h->max_nrhs ? nvecs - r0 : h->max_nrhs;
+    if (int rc = cheb_chunk(h, order, lo, hi, reinterpret_cast<char*>(vecs) + r0 * fb, h->cheb_a, n)) return rc;
+  }
+  return DWF_OK;
+}
+
+int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int delta, int nvec, const void* eta,
+                         void* out_series) {
+  if (int r = check_h(h)) return r;
+  if (!eta || !out_series || m < 0 || delta < 1 || nvec < 1 || !(lam_max > lam_lo) || !(lam_max > 0))
+    return fail(DWF_EINVAL, "dwf_chebyshev_series: bad argument");
+  const int P = h->prec;
+  const size_t fb = fbytes(h, P);
+  char* S = reinterpret_cast<char*>(out_series);
+  HIP_TRY(blas_copy(h, P, reinterpret_cast<const char*>(eta), P, S, 1));
+  if (int rc = cheb_chunk(h, m, lam_lo, lam_max, S, h->cheb_a, 1)) return rc;
+  if (nvec == 1) return DWF_OK;
+  // second recurrence over [0, lam_max]: x(A) = 2A/lam_max - 1
+  char* prev = h->cheb_a;
+  char* cur = h->cheb_a + fb;
+  HIP_TRY(blas_copy(h, P, S, P, prev, 1));
+  HIP_TRY(cheb_step(h, P, S, cur, S, S, 2.0 / lam_max, -1.0, 0.0, h->t_buf, h->u_buf, 1));
+  int recorded = 1;
+  for (int n = 1; recorded < nvec; ++n) {
+    if (n % delta == 0) {
+      HIP_TRY(blas_copy(h, P, cur, P, S + (size_t)recorded * fb, 1));
+      ++recorded;
+      if (recorded == nvec) break;
+    }
+    HIP_TRY(cheb_step(h, P, cur, prev, cur, prev, 4.0 / lam_max, -2.0, -1.0, h->t_buf, h->u_buf, 1));
+    char* t = prev;
+    prev = cur;
+    cur = t;
+  }
+  return DWF_OK;
+}
+
+int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host) {
+  if (int r = check_h(h)) return r;
+  if (!vecs || nvecs < 1 || nvecs > GS_MAX) return fail(DWF_EINVAL, "dwf_gram_schmidt: nvecs must be in [1, %d]", GS_MAX);
+  const int P = h->prec;
+  const size_t fb = fbytes(h, P);
+  char* Q = reinterpret_cast<char*>(vecs);
+  std::vector<double> R((size_t)nvecs * nvecs * 2, 0.0), cf(2 * (size_t)nvecs);
+  std::vector<double> sc;
+  const int chunk = (int)h->partial_count;
+  for (int j = 0; j < nvecs; ++j) {
+    char* v = Q + (size_t)j * fb;
+    for (int pass = 0; pass < 2 && j > 0; ++pass) {
+      for (int k0 = 0; k0 < j; k0 += chunk) {
+        const int nk = j - k0 < chunk ? j - k0 : chunk;
+        HIP_TRY(gs_multidot(h, P, Q + (size_t)k0 * fb, v, nk, h->coef + 2 * k0));
+      }
+      HIP_TRY(gs_multiaxpy(h, P, Q, v, j, h->coef));
+      HIP_TRY(hipMemcpyAsync(cf.data(), h->coef, 2 * (size_t)j * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+      if (int rc = sync(h)) return rc;
+      for (int k = 0; k < j; ++k) {
+        R[((size_t)k * nvecs + j) * 2] += cf[2 * k];
+        R[((size_t)k * nvecs + j) * 2 + 1] += cf[2 * k + 1];
+      }
+    }
+    HIP_TRY(blas_dot(h, P, v, P, v, 1, S_TMP, false));
+    if (int rc = read_scalars(h, 1, sc)) return rc;
+    const double nrm = std::sqrt(sc[S_TMP]);
+    if (!(nrm > 0) || !std::isfinite(nrm)) return fail(DWF_EBREAKDOWN, "dwf_gram_schmidt: vector %d is dependent", j);
+    R[((size_t)j * nvecs + j) * 2] = nrm;
+    HIP_TRY(blas_axpby(h, P, nullptr, P, v, 1, 0.0, 1.0 / nrm, -1, -1, 1));
+  }
+  if (int rc = sync(h)) return rc;
+  if (R_host) std::memcpy(R_host, R.data(), R.size() * sizeof(double));
+  return DWF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Force
+// ---------------------------------------------------------------------------
+int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U) {
+  if (int r = check_h(h)) return r;
+  if (!X_e || !Y_e || !grad_U) return fail(DWF_EINVAL, "dwf_force: null pointer");
+  if (h->max_cg_rhs < 1) return fail(DWF_EINVAL, "dwf_force: handle was created without solver workspace");
+  const char* X = reinterpret_cast<const char*>(X_e);
+  const char* Y = reinterpret_cast<const char*>(Y_e);
+  char* Z = h->t64;  // M5D^{-1} M_oe X      (odd)
+  char* W = h->r64;  // M5D^{-dag} M_eo^dag Y (odd)
+  HopArgs a{};
+  a.in = X;
+  a.out = Z;
+  a.alpha = -0.5;
+  HIP_TRY(launch_hop(h, DWF_F64, a, DWF_ODD, 0, EPI_M5INV, 1));
+  HopArgs b{};
+  b.in = Y;
+  b.out = W;
+  b.alpha = -0.5;
+  HIP_TRY(launch_hop(h, DWF_F64, b, DWF_ODD, 1, EPI_M5INV, 1));
+  HIP_TRY(launch_force(h, Y, W, X, Z, reinterpret_cast<double*>(grad_U)));
+  return DWF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Introspection
+// ---------------------------------------------------------------------------
+int dwf_set_tile(dwf_handle h, int sites_per_block, int rhs_per_block) {
+  if (int r = check_h(h)) return r;
+  if (sites_per_block < 0 || sites_per_block * h->g.Ls > 256) return fail(DWF_EINVAL, "sites_per_block * Ls must be <= 256");
+  h->spb = sites_per_block;
+  h->rhs_per_block = rhs_per_block;
+  return DWF_OK;
+}
+
+int dwf_enable_timing(dwf_handle h, int enable) {
+  if (int r = check_h(h)) return r;
+  if (enable && h->ev_pool.empty()) {
+    h->ev_pool.resize(4096);
+    for (auto& p : h->ev_pool) {
+      HIP_TRY(hipEventCreate(&p.a));
+      HIP_TRY(hipEventCreate(&p.b));
+    }
+  }
+  h->timing = enable != 0;
+  h->ev_used = 0;
+  h->ev_ms = 0;
+  h->ev_launches = 0;
+  return DWF_OK;
+}
+
+int dwf_kernel_time(dwf_handle h, double* ms_total, long long* launches) {
+  if (int r = check_h(h)) return r;
+  if (h->timing && h->ev_used > 0) {
+    if (int rc = sync(h)) return rc;
+    for (size_t i = 0; i < h->ev_used; ++i) {
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, h->ev_pool[i].a, h->ev_pool[i].b));
+      h->ev_ms += ms;
+    }
+    h->ev_launches += (long long)h->ev_used;
+    h->ev_used = 0;
+  }
+  if (ms_total) *ms_total = h->ev_ms;
+  if (launches) *launches = h->ev_launches;
+  return DWF_OK;
+}
+
+}  // extern "C"

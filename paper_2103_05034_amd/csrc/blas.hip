@@ -1,0 +1,441 @@
+// Vector kernels of the solvers: linear combinations across storage
+// precisions, CG updates with fused norms, and dot products.  Every dot and
+// norm accumulates in FP64 and is reduced in two fixed-order stages
+// (per-workgroup partials, then one workgroup per right-hand side), so
+// results are bitwise reproducible run to run.
+#include "dwf_internal.hpp"
+#include "kernels.hpp"
+
+namespace dwf {
+
+constexpr int BS = 256;
+
+struct VecGeom {
+  long long V4h;
+  int Ls;
+  long long n;  // spinors per rhs = V4h * Ls
+};
+
+static VecGeom vgeom(const dwf_context* ctx) { return {ctx->g.V4h, ctx->g.Ls, ctx->g.V4h * ctx->g.Ls}; }
+
+template <int P>
+__device__ __forceinline__ void vload(const char* base, const VecGeom& g, long long i, cplx<double> v[12]) {
+  using R = typename Store<P>::real;
+  cplx<R> t[12];
+  const long long h = i / g.Ls;
+  Store<P>::load(base, g.V4h, g.Ls, h, (int)(i - h * g.Ls), t);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) v[c] = {(double)t[c].re, (double)t[c].im};
+}
+
+template <int P>
+__device__ __forceinline__ void vstore(char* base, const VecGeom& g, long long i, const cplx<double> v[12]) {
+  using R = typename Store<P>::real;
+  cplx<R> t[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) t[c] = {(R)v[c].re, (R)v[c].im};
+  const long long h = i / g.Ls;
+  Store<P>::store(base, g.V4h, g.Ls, h, (int)(i - h * g.Ls), t);
+}
+
+// fixed-shape tree reduction of 2 doubles over a workgroup of BS threads
+__device__ __forceinline__ void block_reduce2(double& a, double& b) {
+  __shared__ double sa[BS], sb[BS];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] += sa[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  a = sa[0];
+  b = sb[0];
+}
+
+// partials[(rhs * RED_BLOCKS + blk) * 2 + {0,1}] -> out[rhs * ostride + {0, 1}]
+__global__ void finalize_kernel(const double* __restrict__ partials, double* __restrict__ out, int ostride,
+                                int write_imag) {
+  const int rhs = blockIdx.x;
+  double a = 0, b = 0;
+  for (int k = threadIdx.x; k < RED_BLOCKS; k += BS) {
+    a += partials[((size_t)rhs * RED_BLOCKS + k) * 2];
+    b += partials[((size_t)rhs * RED_BLOCKS + k) * 2 + 1];
+  }
+  block_reduce2(a, b);
+  if (threadIdx.x == 0) {
+    out[(size_t)rhs * ostride] = a;
+    if (write_imag) out[(size_t)rhs * ostride + 1] = b;
+  }
+}
+
+// <a, b> per rhs; rhs stride given per argument (GS uses Q_k as "rhs" of a
+// batch against one fixed vector b with b_stride = 0)
+template <int PA, int PB>
+__global__ void dot_kernel(VecGeom g, const char* __restrict__ a, size_t a_stride, const char* __restrict__ b,
+                           size_t b_stride, double* __restrict__ partials) {
+  const int rhs = blockIdx.y;
+  const char* ab = a + rhs * a_stride;
+  const char* bb = b + rhs * b_stride;
+  double re = 0, im = 0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < g.n; i += (long long)RED_BLOCKS * BS) {
+    cplx<double> va[12], vb[12];
+    vload<PA>(ab, g, i, va);
+    vload<PB>(bb, g, i, vb);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      re = fma(va[c].re, vb[c].re, re);
+      re = fma(va[c].im, vb[c].im, re);
+      im = fma(va[c].re, vb[c].im, im);
+      im = fma(-va[c].im, vb[c].re, im);
+    }
+  }
+  block_reduce2(re, im);
+  if (threadIdx.x == 0) {
+    partials[((size_t)rhs * RED_BLOCKS + blockIdx.x) * 2] = re;
+    partials[((size_t)rhs * RED_BLOCKS + blockIdx.x) * 2 + 1] = im;
+  }
+}
+
+// y = ca' x + cb' y, ca' = (slot_a >= 0 ? sign_a * scal[rhs][slot_a] : ca), same for b
+template <int PX, int PY>
+__global__ void axpby_kernel(VecGeom g, const char* __restrict__ x, char* __restrict__ y, size_t sx, size_t sy,
+                             double ca, double cb, int slot_a, int slot_b, int sign_a,
+                             const double* __restrict__ scal) {
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double a = slot_a >= 0 ? sign_a * scal[rhs * NSCAL + slot_a] : ca;
+  const double b = slot_b >= 0 ? scal[rhs * NSCAL + slot_b] : cb;
+  cplx<double> vx[12], vy[12];
+  if (x && a != 0.0) vload<PX>(x + rhs * sx, g, i, vx);
+  if (b != 0.0) vload<PY>(y + rhs * sy, g, i, vy);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    cplx<double> o = {0, 0};
+    if (x && a != 0.0) o = {a * vx[c].re, a * vx[c].im};
+    if (b != 0.0) o = {o.re + b * vy[c].re, o.im + b * vy[c].im};
+    vy[c] = o;
+  }
+  vstore<PY>(y + rhs * sy, g, i, vy);
+}
+
+// x += alpha p ; r -= alpha q ; partial |r|^2
+template <int PX, int PR, int PP, int PQ>
+__global__ void cg_xr_kernel(VecGeom g, char* __restrict__ x, char* __restrict__ r, const char* __restrict__ p,
+                             const char* __restrict__ q, size_t sx, size_t sr, size_t sp, size_t sq,
+                             const double* __restrict__ scal, double* __restrict__ partials) {
+  const int rhs = blockIdx.y;
+  const double alpha = scal[rhs * NSCAL + S_ALPHA];
+  double rr = 0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < g.n; i += (long long)RED_BLOCKS * BS) {
+    cplx<double> vx[12], vr[12], vp[12], vq[12];
+    vload<PR>(r + rhs * sr, g, i, vr);
+    if (alpha != 0.0) {
+      vload<PX>(x + rhs * sx, g, i, vx);
+      vload<PP>(p + rhs * sp, g, i, vp);
+      vload<PQ>(q + rhs * sq, g, i, vq);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) {
+        vx[c] = {fma(alpha, vp[c].re, vx[c].re), fma(alpha, vp[c].im, vx[c].im)};
+        vr[c] = {fma(-alpha, vq[c].re, vr[c].re), fma(-alpha, vq[c].im, vr[c].im)};
+      }
+      vstore<PX>(x + rhs * sx, g, i, vx);
+      vstore<PR>(r + rhs * sr, g, i, vr);
+      if (PR == DWF_F16S) vload<PR>(r + rhs * sr, g, i, vr);  // norm of what is stored
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rr += vr[c].re * vr[c].re + vr[c].im * vr[c].im;
+  }
+  double dummy = 0;
+  block_reduce2(rr, dummy);
+  if (threadIdx.x == 0) {
+    partials[((size_t)rhs * RED_BLOCKS + blockIdx.x) * 2] = rr;
+    partials[((size_t)rhs * RED_BLOCKS + blockIdx.x) * 2 + 1] = 0;
+  }
+}
+
+// p = r + beta p
+template <int PR, int PP>
+__global__ void cg_p_kernel(VecGeom g, const char* __restrict__ r, char* __restrict__ p, size_t sr, size_t sp,
+                            const double* __restrict__ scal) {
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double beta = scal[rhs * NSCAL + S_BETA];
+  cplx<double> vr[12], vp[12];
+  vload<PR>(r + rhs * sr, g, i, vr);
+  if (beta != 0.0) {
+    vload<PP>(p + rhs * sp, g, i, vp);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
+  }
+  vstore<PP>(p + rhs * sp, g, i, vr);
+}
+
+// scalar bookkeeping: one thread per rhs
+__global__ void scal_alpha_kernel(double* scal, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double* s = scal + r * NSCAL;
+  s[S_RR_OLD] = s[S_RR];
+  if (s[S_ACTIVE] == 0.0) {
+    s[S_ALPHA] = 0.0;
+    return;
+  }
+  const double pap = s[S_PAP];
+  const double a = s[S_RR] / pap;
+  if (!(pap > 0.0) || !isfinite(a)) {
+    s[S_ALPHA] = 0.0;
+    s[S_ACTIVE] = 0.0;
+    if (s[S_RR] != 0.0) s[S_FLAG] = 1.0;  // breakdown (zero residual is convergence)
+    return;
+  }
+  s[S_ALPHA] = a;
+}
+
+__global__ void scal_beta_kernel(double* scal, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double* s = scal + r * NSCAL;
+  if (s[S_ACTIVE] == 0.0) {
+    s[S_BETA] = 0.0;
+    return;
+  }
+  const double b = s[S_RR] / s[S_RR_OLD];
+  if (!isfinite(b) || !isfinite(s[S_RR])) {
+    s[S_BETA] = 0.0;
+    s[S_ACTIVE] = 0.0;
+    s[S_FLAG] = 1.0;
+    return;
+  }
+  s[S_BETA] = b;
+}
+
+__global__ void scal_set_kernel(double* scal, int nrhs, int slot, double v) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) scal[r * NSCAL + slot] = v;
+}
+
+__global__ void scal_converge_kernel(double* scal, int nrhs, double tol2, int count, int allow_stop) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrhs) return;
+  double* s = scal + r * NSCAL;
+  if (s[S_ACTIVE] == 0.0) return;
+  if (count) s[S_ITERS] += 1.0;
+  const double rr = s[S_RR], bb = s[S_BB];
+  if (!isfinite(rr) || !isfinite(bb)) {
+    s[S_FLAG] = 1.0;
+    s[S_ACTIVE] = 0.0;
+    return;
+  }
+  if (allow_stop && rr <= tol2 * bb) s[S_ACTIVE] = 0.0;
+}
+
+__global__ void scal_copy_kernel(double* scal, int nrhs, int dst, int src) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) scal[r * NSCAL + dst] = scal[r * NSCAL + src];
+}
+
+// v -= sum_{k<j} coef[k] Q_k   (coef complex, interleaved)
+template <int P>
+__global__ void multiaxpy_kernel(VecGeom g, const char* __restrict__ Q, char* __restrict__ v, size_t stride, int j,
+                                 const double* __restrict__ coef) {
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  cplx<double> vv[12], q[12];
+  vload<P>(v, g, i, vv);
+  for (int k = 0; k < j; ++k) {
+    vload<P>(Q + k * stride, g, i, q);
+    const cplx<double> cf = {coef[2 * k], coef[2 * k + 1]};
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      vv[c].re -= cf.re * q[c].re - cf.im * q[c].im;
+      vv[c].im -= cf.re * q[c].im + cf.im * q[c].re;
+    }
+  }
+  vstore<P>(v, g, i, vv);
+}
+
+template <int P>
+__global__ void scale_kernel(VecGeom g, char* __restrict__ v, const double* __restrict__ f) {
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double a = *f;
+  cplx<double> vv[12];
+  vload<P>(v, g, i, vv);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) vv[c] = {a * vv[c].re, a * vv[c].im};
+  vstore<P>(v, g, i, vv);
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers
+// ---------------------------------------------------------------------------
+#define DWF_DISPATCH1(p, F, ...)                      \
+  switch (p) {                                         \
+    case DWF_F64: F<DWF_F64>(__VA_ARGS__); break;      \
+    case DWF_F32: F<DWF_F32>(__VA_ARGS__); break;      \
+    default: F<DWF_F16S>(__VA_ARGS__); break;          \
+  }
+
+static unsigned grid_n(long long n) { return (unsigned)((n + BS - 1) / BS); }
+
+template <int PA, int PB>
+static void dot_l(dwf_context* ctx, VecGeom g, const char* a, size_t sa, const char* b, size_t sb, int nrhs) {
+  hipLaunchKernelGGL((dot_kernel<PA, PB>), dim3(RED_BLOCKS, nrhs), dim3(BS), 0, ctx->stream, g, a, sa, b, sb,
+                     ctx->partials);
+}
+template <int PA>
+static void dot_la(dwf_context* ctx, int pb, VecGeom g, const char* a, size_t sa, const char* b, size_t sb,
+                   int nrhs) {
+  switch (pb) {
+    case DWF_F64: dot_l<PA, DWF_F64>(ctx, g, a, sa, b, sb, nrhs); break;
+    case DWF_F32: dot_l<PA, DWF_F32>(ctx, g, a, sa, b, sb, nrhs); break;
+    default: dot_l<PA, DWF_F16S>(ctx, g, a, sa, b, sb, nrhs); break;
+  }
+}
+
+hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot, bool imag) {
+  VecGeom g = vgeom(ctx);
+  const size_t sa = field_bytes_rhs(ctx, pa), sb = field_bytes_rhs(ctx, pb);
+  DWF_DISPATCH1(pa, dot_la, ctx, pb, g, a, sa, b, sb, nrhs);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, ctx->partials, ctx->scalars + slot,
+                     NSCAL, imag ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int PX, int PY>
+static void axpby_l(dwf_context* ctx, VecGeom g, const char* x, char* y, size_t sx, size_t sy, int nrhs, double ca,
+                    double cb, int slot_a, int slot_b, int sign_a) {
+  hipLaunchKernelGGL((axpby_kernel<PX, PY>), dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, x, y, sx, sy, ca,
+                     cb, slot_a, slot_b, sign_a, ctx->scalars);
+}
+template <int PX>
+static void axpby_lx(dwf_context* ctx, int py, VecGeom g, const char* x, char* y, size_t sx, size_t sy, int nrhs,
+                     double ca, double cb, int slot_a, int slot_b, int sign_a) {
+  switch (py) {
+    case DWF_F64: axpby_l<PX, DWF_F64>(ctx, g, x, y, sx, sy, nrhs, ca, cb, slot_a, slot_b, sign_a); break;
+    case DWF_F32: axpby_l<PX, DWF_F32>(ctx, g, x, y, sx, sy, nrhs, ca, cb, slot_a, slot_b, sign_a); break;
+    default: axpby_l<PX, DWF_F16S>(ctx, g, x, y, sx, sy, nrhs, ca, cb, slot_a, slot_b, sign_a); break;
+  }
+}
+
+hipError_t blas_axpby(dwf_context* ctx, int px, const char* x, int py, char* y, int nrhs, double ca, double cb,
+                      int slot_a, int slot_b, int sign_a) {
+  VecGeom g = vgeom(ctx);
+  const size_t sx = field_bytes_rhs(ctx, px), sy = field_bytes_rhs(ctx, py);
+  DWF_DISPATCH1(px, axpby_lx, ctx, py, g, x, y, sx, sy, nrhs, ca, cb, slot_a, slot_b, sign_a);
+  return hipGetLastError();
+}
+
+hipError_t blas_copy(dwf_context* ctx, int pin, const char* in, int pout, char* out, int nrhs) {
+  return blas_axpby(ctx, pin, in, pout, out, nrhs, 1.0, 0.0, -1, -1, 1);
+}
+
+hipError_t blas_zero(dwf_context* ctx, int prec, char* out, int nrhs) {
+  return blas_axpby(ctx, prec, nullptr, prec, out, nrhs, 0.0, 0.0, -1, -1, 1);
+}
+
+template <int PX, int PR, int PP, int PQ>
+static void xr_l(dwf_context* ctx, VecGeom g, char* x, char* r, const char* p, const char* q, int nrhs) {
+  hipLaunchKernelGGL((cg_xr_kernel<PX, PR, PP, PQ>), dim3(RED_BLOCKS, nrhs), dim3(BS), 0, ctx->stream, g, x, r, p, q,
+                     field_bytes_rhs(ctx, PX), field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP),
+                     field_bytes_rhs(ctx, PQ), ctx->scalars, ctx->partials);
+}
+
+hipError_t cg_update_xr(dwf_context* ctx, int px, char* x, int pr, char* r, int pp, const char* p, int pq,
+                        const char* q, int nrhs) {
+  VecGeom g = vgeom(ctx);
+  // supported combinations: all-F64; x/r F32 with p/q F32 or F16S
+  if (px == DWF_F64 && pr == DWF_F64 && pp == DWF_F64 && pq == DWF_F64)
+    xr_l<DWF_F64, DWF_F64, DWF_F64, DWF_F64>(ctx, g, x, r, p, q, nrhs);
+  else if (px == DWF_F32 && pr == DWF_F32 && pp == DWF_F32 && pq == DWF_F32)
+    xr_l<DWF_F32, DWF_F32, DWF_F32, DWF_F32>(ctx, g, x, r, p, q, nrhs);
+  else if (px == DWF_F32 && pr == DWF_F32 && pp == DWF_F16S && pq == DWF_F16S)
+    xr_l<DWF_F32, DWF_F32, DWF_F16S, DWF_F16S>(ctx, g, x, r, p, q, nrhs);
+  else
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, ctx->partials, ctx->scalars + S_RR,
+                     NSCAL, 0);
+  return hipGetLastError();
+}
+
+template <int PR, int PP>
+static void p_l(dwf_context* ctx, VecGeom g, const char* r, char* p, int nrhs) {
+  hipLaunchKernelGGL((cg_p_kernel<PR, PP>), dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, r, p,
+                     field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP), ctx->scalars);
+}
+
+hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs) {
+  VecGeom g = vgeom(ctx);
+  if (pr == DWF_F64 && pp == DWF_F64)
+    p_l<DWF_F64, DWF_F64>(ctx, g, r, p, nrhs);
+  else if (pr == DWF_F32 && pp == DWF_F32)
+    p_l<DWF_F32, DWF_F32>(ctx, g, r, p, nrhs);
+  else if (pr == DWF_F32 && pp == DWF_F16S)
+    p_l<DWF_F32, DWF_F16S>(ctx, g, r, p, nrhs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t scal_alpha(dwf_context* ctx, int nrhs) {
+  hipLaunchKernelGGL(scal_alpha_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, ctx->stream, ctx->scalars, nrhs);
+  return hipGetLastError();
+}
+hipError_t scal_beta(dwf_context* ctx, int nrhs) {
+  hipLaunchKernelGGL(scal_beta_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, ctx->stream, ctx->scalars, nrhs);
+  return hipGetLastError();
+}
+hipError_t scal_set(dwf_context* ctx, int nrhs, int slot, double v) {
+  hipLaunchKernelGGL(scal_set_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, ctx->stream, ctx->scalars, nrhs, slot, v);
+  return hipGetLastError();
+}
+hipError_t scal_copy(dwf_context* ctx, int nrhs, int dst, int src) {
+  hipLaunchKernelGGL(scal_copy_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, ctx->stream, ctx->scalars, nrhs, dst,
+                     src);
+  return hipGetLastError();
+}
+
+hipError_t scal_converge(dwf_context* ctx, int nrhs, double tol2, bool count_iter, int allow_stop) {
+  hipLaunchKernelGGL(scal_converge_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, ctx->stream, ctx->scalars, nrhs, tol2,
+                     count_iter ? 1 : 0, allow_stop);
+  return hipGetLastError();
+}
+
+hipError_t gs_multidot(dwf_context* ctx, int prec, const char* Q, const char* v, int j, double* coef) {
+  VecGeom g = vgeom(ctx);
+  const size_t st = field_bytes_rhs(ctx, prec);
+  // <Q_k, v> for k < j : Q_k is the batch index, v has stride 0
+  DWF_DISPATCH1(prec, dot_la, ctx, prec, g, Q, st, v, 0, j);
+  hipLaunchKernelGGL(finalize_kernel, dim3(j), dim3(BS), 0, ctx->stream, ctx->partials, coef, 2, 1);
+  return hipGetLastError();
+}
+
+template <int P>
+static void maxpy_l(dwf_context* ctx, VecGeom g, const char* Q, char* v, size_t st, int j, const double* coef) {
+  hipLaunchKernelGGL((multiaxpy_kernel<P>), dim3(grid_n(g.n)), dim3(BS), 0, ctx->stream, g, Q, v, st, j, coef);
+}
+
+hipError_t gs_multiaxpy(dwf_context* ctx, int prec, const char* Q, char* v, int j, const double* coef) {
+  VecGeom g = vgeom(ctx);
+  const size_t st = field_bytes_rhs(ctx, prec);
+  DWF_DISPATCH1(prec, maxpy_l, ctx, g, Q, v, st, j, coef);
+  return hipGetLastError();
+}
+
+template <int P>
+static void scale_l(dwf_context* ctx, VecGeom g, char* v, const double* f) {
+  hipLaunchKernelGGL((scale_kernel<P>), dim3(grid_n(g.n)), dim3(BS), 0, ctx->stream, g, v, f);
+}
+
+hipError_t gs_scale(dwf_context* ctx, int prec, char* v, const double* inv_norm) {
+  VecGeom g = vgeom(ctx);
+  DWF_DISPATCH1(prec, scale_l, ctx, g, v, inv_norm);
+  return hipGetLastError();
+}
+
+}  // namespace dwf

@@ -1,0 +1,301 @@
+// Internal definitions shared by the libdwf translation units: the handle,
+// field storage traits, complex arithmetic and the spin algebra of the
+// hopping term in the chiral basis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dwf.h"
+
+namespace dwf {
+
+// ---------------------------------------------------------------------------
+// Complex numbers (plain structs; HIP has no device std::complex).
+// ---------------------------------------------------------------------------
+template <class R>
+struct cplx {
+  R re, im;
+};
+
+template <class R>
+__device__ __forceinline__ cplx<R> cadd(cplx<R> a, cplx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__device__ __forceinline__ cplx<R> csub(cplx<R> a, cplx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__device__ __forceinline__ cplx<R> cscale(R s, cplx<R> a) { return {s * a.re, s * a.im}; }
+// a * b
+template <class R>
+__device__ __forceinline__ cplx<R> cmul(cplx<R> a, cplx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// acc + a * b
+template <class R>
+__device__ __forceinline__ cplx<R> cfma(cplx<R> a, cplx<R> b, cplx<R> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+  return acc;
+}
+// acc + conj(a) * b
+template <class R>
+__device__ __forceinline__ cplx<R> cfma_conj(cplx<R> a, cplx<R> b, cplx<R> acc) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+  return acc;
+}
+// i * a
+template <class R>
+__device__ __forceinline__ cplx<R> ctimesi(cplx<R> a) { return {-a.im, a.re}; }
+
+// ---------------------------------------------------------------------------
+// Field storage.  A packed half field of one right-hand side holds
+// [V4h][12][Ls] complex values (s fastest, then spin-colour, then site).
+// ---------------------------------------------------------------------------
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+template <int PREC>
+struct Store;
+
+template <>
+struct Store<DWF_F64> {
+  using real = double;
+  static constexpr size_t bytes_per_spinor = 192;
+  __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<double> v[12]) {
+    const double2* p = reinterpret_cast<const double2*>(base) + h * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      double2 t = p[(size_t)c * Ls];
+      v[c] = {t.x, t.y};
+    }
+  }
+  __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<double> v[12]) {
+    double2* p = reinterpret_cast<double2*>(base) + h * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[(size_t)c * Ls] = make_double2(v[c].re, v[c].im);
+  }
+};
+
+template <>
+struct Store<DWF_F32> {
+  using real = float;
+  static constexpr size_t bytes_per_spinor = 96;
+  __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
+    const float2* p = reinterpret_cast<const float2*>(base) + h * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      float2 t = p[(size_t)c * Ls];
+      v[c] = {t.x, t.y};
+    }
+  }
+  __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
+    float2* p = reinterpret_cast<float2*>(base) + h * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) p[(size_t)c * Ls] = make_float2(v[c].re, v[c].im);
+  }
+};
+
+// FP16 values v / scale (round to nearest even) plus one FP32 scale = max |v|
+// per (site, s).  The scale array follows the half data of the same rhs.
+template <>
+struct Store<DWF_F16S> {
+  using real = float;
+  static constexpr size_t bytes_per_spinor = 52;
+  __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
+    const half2v* p = reinterpret_cast<const half2v*>(base) + h * 12 * Ls + s;
+    const float* sc = reinterpret_cast<const float*>(base + V4h * Ls * 48) + h * Ls + s;
+    float scale = *sc;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      half2v t = p[(size_t)c * Ls];
+      v[c] = {(float)t.x * scale, (float)t.y * scale};
+    }
+  }
+  __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    half2v* p = reinterpret_cast<half2v*>(base) + h * 12 * Ls + s;
+    float* sc = reinterpret_cast<float*>(base + V4h * Ls * 48) + h * Ls + s;
+    *sc = m;
+    const float d = (m > 0.f) ? m : 1.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      half2v t;
+      t.x = (_Float16)(v[c].re / d);
+      t.y = (_Float16)(v[c].im / d);
+      p[(size_t)c * Ls] = t;
+    }
+  }
+};
+
+__host__ __device__ inline size_t spinor_bytes(int prec) {
+  return prec == DWF_F64 ? 192 : prec == DWF_F32 ? 96 : 52;
+}
+
+// ---------------------------------------------------------------------------
+// Spin algebra of the hopping term.  In the chiral basis each gamma_mu is
+// [[0, B_mu], [B_mu^dag, 0]] with 2x2 blocks, so for sigma = +-1
+//   (1 + sigma g_mu) psi = (h, sigma B_mu^dag h),  h = u + sigma B_mu l,
+// with u = spins (0,1) and l = spins (2,3).  B_x = [[0,i],[i,0]],
+// B_y = [[0,-1],[1,0]], B_z = diag(i,-i), B_t = 1.
+// ---------------------------------------------------------------------------
+template <int MU, int SIGMA, class R>
+__device__ __forceinline__ void project(const cplx<R> p[12], cplx<R> h[6]) {
+  const R sg = (R)SIGMA;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<R> u0 = p[a], u1 = p[3 + a], l0 = p[6 + a], l1 = p[9 + a];
+    if (MU == 0) {  // B l = (i l1, i l0)
+      h[a] = cadd(u0, cscale(sg, ctimesi(l1)));
+      h[3 + a] = cadd(u1, cscale(sg, ctimesi(l0)));
+    } else if (MU == 1) {  // B l = (-l1, l0)
+      h[a] = csub(u0, cscale(sg, l1));
+      h[3 + a] = cadd(u1, cscale(sg, l0));
+    } else if (MU == 2) {  // B l = (i l0, -i l1)
+      h[a] = cadd(u0, cscale(sg, ctimesi(l0)));
+      h[3 + a] = csub(u1, cscale(sg, ctimesi(l1)));
+    } else {  // B l = l
+      h[a] = cadd(u0, cscale(sg, l0));
+      h[3 + a] = cadd(u1, cscale(sg, l1));
+    }
+  }
+}
+
+// acc += (chi, sigma B^dag chi) for the colour-rotated half spinor chi.
+template <int MU, int SIGMA, class R>
+__device__ __forceinline__ void reconstruct(const cplx<R> chi[6], cplx<R> acc[12]) {
+  const R sg = (R)SIGMA;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    cplx<R> c0 = chi[a], c1 = chi[3 + a];
+    acc[a] = cadd(acc[a], c0);
+    acc[3 + a] = cadd(acc[3 + a], c1);
+    if (MU == 0) {  // B^dag chi = (-i c1, -i c0)
+      acc[6 + a] = csub(acc[6 + a], cscale(sg, ctimesi(c1)));
+      acc[9 + a] = csub(acc[9 + a], cscale(sg, ctimesi(c0)));
+    } else if (MU == 1) {  // B^dag chi = (c1, -c0)
+      acc[6 + a] = cadd(acc[6 + a], cscale(sg, c1));
+      acc[9 + a] = csub(acc[9 + a], cscale(sg, c0));
+    } else if (MU == 2) {  // B^dag chi = (-i c0, i c1)
+      acc[6 + a] = csub(acc[6 + a], cscale(sg, ctimesi(c0)));
+      acc[9 + a] = cadd(acc[9 + a], cscale(sg, ctimesi(c1)));
+    } else {  // B^dag chi = chi
+      acc[6 + a] = cadd(acc[6 + a], cscale(sg, c0));
+      acc[9 + a] = cadd(acc[9 + a], cscale(sg, c1));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lattice geometry shared by host and device.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int X, Y, Z, T;
+  int Ls;
+  long long V4, V4h;
+};
+
+// Coordinates of half-lattice site h of parity p.
+__host__ __device__ inline void site_coords(const Geom& g, int p, long long h, int& x, int& y, int& z,
+                                            int& t) {
+  int Xh = g.X / 2;
+  long long xh = h % Xh;
+  long long rest = h / Xh;
+  y = (int)(rest % g.Y);
+  rest /= g.Y;
+  z = (int)(rest % g.Z);
+  t = (int)(rest / g.Z);
+  x = 2 * (int)xh + ((p + y + z + t) & 1);
+}
+
+__host__ __device__ inline long long half_index(const Geom& g, int x, int y, int z, int t) {
+  return ((long long)x + (long long)g.X * (y + (long long)g.Y * (z + (long long)g.Z * t))) / 2;
+}
+
+// ---------------------------------------------------------------------------
+// Kernel parameter blocks.
+// ---------------------------------------------------------------------------
+enum Epilogue {
+  EPI_LIN = 0,    // out = alpha * Dhop(in) + beta * x             (x optional)
+  EPI_M5INV = 1,  // out = M5D^{-1} [alpha * Dhop(in) + beta * x]  (x optional)
+  EPI_M5 = 2,     // out = M5D x + alpha * Dhop(in)
+  EPI_CHEB = 3,   // out = ca * (M5D x + alpha * Dhop(in)) + cb * y + cc * z
+};
+
+struct HopArgs {
+  const char* in;     // other parity, rhs stride in_stride
+  char* out;          // out parity
+  const char* x;      // out parity (EPI_LIN/M5INV optional, EPI_M5/EPI_CHEB required)
+  const char* y;      // EPI_CHEB
+  const char* z;      // EPI_CHEB (may alias out)
+  const void* links;  // packed links of out parity: [dir][9][V4h] complex
+  const int* nbr;     // neighbour table of out parity: [dir][V4h]
+  size_t stride;      // bytes per rhs of every field argument
+  long long V4h;
+  int Ls;
+  int spb;            // sites per workgroup
+  int nblocks;        // workgroups along the site axis (before XCD padding)
+  int nb8;            // workgroups per XCD slot
+  double alpha, beta, ca, cb, cc;
+  double d, inv_d, corner;  // 5 - M5, 1/d, -mf / (1 + mf d^{-Ls})
+  double mf;
+  double* partial;    // optional per-workgroup FP64 partial sums (reductions)
+};
+
+// ---------------------------------------------------------------------------
+// The handle.
+// ---------------------------------------------------------------------------
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace dwf
+
+struct dwf_context {
+  dwf::Geom g;
+  double M5, mf;
+  int prec;
+  int max_nrhs;
+  int max_cg_rhs;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  // carved workspace
+  void* links64;     // [2][8][9][V4h] complex128
+  void* links32;     // [2][8][9][V4h] complex64 (prec != F64)
+  int* nbr;          // [2][8][V4h]
+  char* t_buf;       // odd half field, max_nrhs, handle precision
+  char* u_buf;       // even half field, max_nrhs, handle precision
+  char* t64;         // FP64 odd temporary (aliases t_buf for F64 handles)
+  char* u64;         // FP64 even temporary (aliases u_buf for F64 handles)
+  char* r64;         // FP64 CG vectors, max_nrhs
+  char* p64;
+  char* q64;
+  char* b64;         // FP64 even field for the red-black source
+  char* lo_r;        // low-precision CG vectors (F32/F16S handles)
+  char* lo_p;
+  char* lo_q;
+  char* lo_x;        // FP32 accumulator of the low-precision solution
+  char* cheb_a;      // Chebyshev partner set, handle precision, max(max_nrhs, 2)
+  double* partials;  // reduction partials
+  double* scalars;   // device scalars (per rhs)
+  double* coef;      // Gram-Schmidt projection coefficients
+  size_t partial_count;
+  // launch shape
+  int spb;
+  int rhs_per_block;
+  // timing of hopping kernels
+  bool timing;
+  std::vector<dwf::EventPair> ev_pool;
+  size_t ev_used;
+  double ev_ms;
+  long long ev_launches;
+};

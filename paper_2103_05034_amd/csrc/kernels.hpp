@@ -1,0 +1,78 @@
+// Launchers exported between the libdwf translation units (internal).
+#pragma once
+
+#include "dwf_internal.hpp"
+
+namespace dwf {
+
+// bytes of one right-hand side of a packed half field at `prec`
+inline size_t field_bytes_rhs(const dwf_context* ctx, int prec) {
+  return spinor_bytes(prec) * (size_t)ctx->g.Ls * (size_t)ctx->g.V4h;
+}
+
+void timing_begin(dwf_context* ctx);
+void timing_end(dwf_context* ctx);
+
+// hop.hip
+void fill_shape(const dwf_context* ctx, HopArgs& a);
+hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int dag, int epi, int nrhs);
+hipError_t launch_site5(dwf_context* ctx, int prec, const char* in, char* out, int dag, int inv, int nrhs);
+
+// setup.hip
+hipError_t launch_pack_links(dwf_context* ctx, const void* U);
+hipError_t launch_neighbours(dwf_context* ctx);
+hipError_t launch_pack(dwf_context* ctx, int prec, const void* natural, char* packed, int nrhs, int parity,
+                       bool unpack);
+
+// blas.hip -- per-rhs reductions land in ctx->scalars[rhs * NSCAL + slot]
+constexpr int NSCAL = 16;
+constexpr int RED_BLOCKS = 256;  // partial sums per rhs
+enum Slot {
+  S_RR = 0,      // |r|^2 (recursive)
+  S_RR_OLD = 1,
+  S_PAP = 2,
+  S_ALPHA = 3,
+  S_BETA = 4,
+  S_BB = 5,
+  S_ACTIVE = 6,  // 1 while the rhs iterates, 0 once converged
+  S_RRMAX = 7,   // |r|^2 at the last reliable update
+  S_TMP = 8,     // scratch dot result (re)
+  S_TMPI = 9,    // scratch dot result (im)
+  S_TRUE = 10,   // true |r|^2
+  S_FLAG = 11,   // breakdown flag
+  S_ITERS = 12,  // iterations done while active
+};
+
+// result[rhs] = <a, b> (complex, FP64 accumulation) into scalars[rhs*NSCAL + slot (+1 imag)]
+hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot,
+                    bool imag);
+// y <- alpha x + beta y with per-rhs or constant coefficients; any storage mix
+//  coef_mode 0: constants; 1: alpha = scalars[slot_a], beta = cb (device coefficients)
+hipError_t blas_axpby(dwf_context* ctx, int px, const char* x, int py, char* y, int nrhs, double ca,
+                      double cb, int slot_a, int slot_b, int sign_a);
+// out <- in (conversion between precisions)
+hipError_t blas_copy(dwf_context* ctx, int pin, const char* in, int pout, char* out, int nrhs);
+hipError_t blas_zero(dwf_context* ctx, int prec, char* out, int nrhs);
+// CG step: x += alpha p; r -= alpha q; |r|^2 -> slot S_RR (new), per rhs
+hipError_t cg_update_xr(dwf_context* ctx, int px, char* x, int pr, char* r, int pp, const char* p, int pq,
+                        const char* q, int nrhs);
+// p = r + beta p
+hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs);
+// scalar bookkeeping kernels
+hipError_t scal_alpha(dwf_context* ctx, int nrhs);  // alpha = rr / pAp  (0 if inactive)
+hipError_t scal_beta(dwf_context* ctx, int nrhs);   // beta = rr_new / rr_old
+hipError_t scal_set(dwf_context* ctx, int nrhs, int slot, double v);
+hipError_t scal_copy(dwf_context* ctx, int nrhs, int dst, int src);
+// per active rhs: count the iteration, flag non-finite residuals, and retire
+// the rhs once |r|^2 <= tol2 |b|^2 (only if allow_stop)
+hipError_t scal_converge(dwf_context* ctx, int nrhs, double tol2, bool count_iter, int allow_stop = 1);
+// GS helpers: dots of v against Q_k (k < j) into coef[k]; v -= sum_k coef[k] Q_k
+hipError_t gs_multidot(dwf_context* ctx, int prec, const char* Q, const char* v, int j, double* coef);
+hipError_t gs_multiaxpy(dwf_context* ctx, int prec, const char* Q, char* v, int j, const double* coef);
+hipError_t gs_scale(dwf_context* ctx, int prec, char* v, const double* inv_norm);
+
+// force.hip
+hipError_t launch_force(dwf_context* ctx, const char* a_even, const char* a_odd, const char* b_even,
+                        const char* b_odd, double* grad_U);
+
+}  // namespace dwf

@@ -1,0 +1,159 @@
+"""GPU parity of the operators (through the C ABI) against the FP64 oracle.
+
+Shapes span several workgroups with a ragged last one, the L = 2 extents
+where x + mu and x - mu coincide, a non-cubic lattice and the Ls values of
+the workloads.  Bars: FP64 relative 2-norm error <= 1e-13; FP32 <= 1e-6 and
+FP16 + scale <= 2e-3 against the oracle applied to the stored input.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import codec, lattice as L
+from tests.gpu_util import M5, MF, make_operator, pack, rel, rel_per_rhs, unpack
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [((2, 2, 2, 2), 4), ((4, 4, 4, 4), 8), ((4, 4, 6, 8), 5), ((6, 4, 2, 4), 12)]
+F64, F32, F16S = 0, 1, 2
+EVEN, ODD, BOTH = 0, 1, 2
+
+
+def fields(dims, Ls, nrhs, seed):
+    return synth.gaussian_fermion_batch(dims, Ls, nrhs, seed)
+
+
+def stored(op, nat, parity):
+    """What the handle's precision stores for ``nat`` (round trip through pack)."""
+    return unpack(op, pack(op, nat, parity), nat.shape[0], parity)
+
+
+@pytest.mark.parametrize("prec", [F64, F32, F16S])
+@pytest.mark.parametrize("dims,Ls", SHAPES[:3])
+def test_pack_unpack_roundtrip(dims, Ls, prec):
+    op, _ = make_operator(dims, Ls, prec=prec)
+    nat = fields(dims, Ls, 2, seed=1)
+    back = unpack(op, pack(op, nat, BOTH), 2, BOTH)
+    if prec == F64:
+        assert np.array_equal(back, nat)
+    elif prec == F32:
+        assert np.array_equal(back, nat.astype(np.complex64).astype(np.complex128))
+    else:
+        q, s = codec.encode(nat)
+        assert np.array_equal(back, codec.decode(q, s))
+    # one parity only: the other parity of the output is untouched (zero)
+    even = unpack(op, pack(op, nat, EVEN), 2, EVEN)
+    expect = np.stack([L.on_parity(back[k], EVEN) for k in range(2)])
+    assert np.array_equal(even, expect)
+
+
+@pytest.mark.parametrize("dims,Ls", SHAPES)
+@pytest.mark.parametrize("dagger", [False, True])
+@pytest.mark.parametrize("out_parity", [EVEN, ODD])
+def test_dhop_f64(dims, Ls, dagger, out_parity):
+    nrhs = 3 if Ls <= 8 else 1
+    op, U = make_operator(dims, Ls, eps=0.5, seed=2)
+    nat = fields(dims, Ls, nrhs, seed=3)
+    inp = pack(op, nat, 1 - out_parity)
+    out = op.new_field(nrhs)
+    op.dhop(inp, out, out_parity, nrhs, dagger)
+    got = unpack(op, out, nrhs, out_parity)
+    exp = np.stack([L.on_parity(L.dhop(U, L.on_parity(nat[k], 1 - out_parity), dagger), out_parity) for k in range(nrhs)])
+    assert rel_per_rhs(got, exp) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [(F32, 1e-6), (F16S, 2e-3)])
+@pytest.mark.parametrize("dims,Ls", SHAPES[1:3])
+def test_dhop_low_precision(dims, Ls, prec, tol):
+    op, U = make_operator(dims, Ls, eps=0.5, seed=2, prec=prec)
+    nat = fields(dims, Ls, 2, seed=4)
+    inp = pack(op, nat, EVEN)
+    src = unpack(op, inp, 2, EVEN)  # the values the kernel actually reads
+    for dagger in (False, True):
+        out = op.new_field(2)
+        op.dhop(inp, out, ODD, 2, dagger)
+        got = unpack(op, out, 2, ODD)
+        exp = np.stack([L.on_parity(L.dhop(U, src[k], dagger), ODD) for k in range(2)])
+        assert rel_per_rhs(got, exp) < tol
+
+
+@pytest.mark.parametrize("dims,Ls", SHAPES)
+@pytest.mark.parametrize("dagger", [False, True])
+def test_m5d_and_inverse_f64(dims, Ls, dagger):
+    op, U = make_operator(dims, Ls, seed=5, mf=0.03)
+    nat = fields(dims, Ls, 2, seed=6)
+    inp = pack(op, nat, EVEN)
+    out = op.new_field(2)
+    op.m5d(inp, out, 2, dagger)
+    got = unpack(op, out, 2, EVEN)
+    exp = np.stack([L.m5d(L.on_parity(nat[k], EVEN), M5, 0.03, dag=dagger) for k in range(2)])
+    assert rel_per_rhs(got, exp) < 1e-14
+    op.m5d_inv(inp, out, 2, dagger)
+    got = unpack(op, out, 2, EVEN)
+    exp = np.stack([L.m5d_inv(L.on_parity(nat[k], EVEN), M5, 0.03, dag=dagger) for k in range(2)])
+    assert rel_per_rhs(got, exp) < 1e-13
+
+
+@pytest.mark.parametrize("dims,Ls", SHAPES)
+@pytest.mark.parametrize("dagger", [False, True])
+def test_ddw_f64(dims, Ls, dagger):
+    op, U = make_operator(dims, Ls, seed=7)
+    nat = fields(dims, Ls, 1, seed=8)
+    inp = pack(op, nat, BOTH)
+    out = op.new_field(1, both=True)
+    op.ddw(inp, out, 1, dagger)
+    got = unpack(op, out, 1, BOTH)[0]
+    assert rel(got, L.ddw(U, nat[0], M5, MF, dag=dagger)) < 1e-13
+
+
+@pytest.mark.parametrize("dims,Ls", SHAPES)
+def test_mpc_and_normal_operator_f64(dims, Ls):
+    nrhs = 2
+    op, U = make_operator(dims, Ls, seed=9)
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, nrhs, seed=10)])
+    inp = pack(op, nat, EVEN)
+    out = op.new_field(nrhs)
+    op.mpc(inp, out, nrhs, False)
+    assert rel_per_rhs(unpack(op, out, nrhs, EVEN), np.stack([L.mpc(U, v, M5, MF) for v in nat])) < 1e-13
+    op.mpc(inp, out, nrhs, True)
+    assert rel_per_rhs(unpack(op, out, nrhs, EVEN), np.stack([L.mpc_dag(U, v, M5, MF) for v in nat])) < 1e-13
+    op.mpcdagmpc(inp, out, nrhs)
+    assert rel_per_rhs(unpack(op, out, nrhs, EVEN), np.stack([L.mpcdagmpc(U, v, M5, MF) for v in nat])) < 1e-13
+
+
+def test_mpc_chunking_beyond_temporaries():
+    """nrhs larger than the operator temporaries: processed in chunks, same result."""
+    dims, Ls = (4, 4, 4, 4), 8
+    op, U = make_operator(dims, Ls, seed=11, max_nrhs=2)
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 5, seed=12)])
+    out = op.new_field(5)
+    op.mpcdagmpc(pack(op, nat, EVEN), out, 5)
+    assert rel_per_rhs(unpack(op, out, 5, EVEN), np.stack([L.mpcdagmpc(U, v, M5, MF) for v in nat])) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [(F32, 1e-6), (F16S, 3e-3)])
+def test_mpcdagmpc_low_precision(prec, tol):
+    dims, Ls = (4, 4, 4, 4), 8
+    op, U = make_operator(dims, Ls, seed=13, prec=prec)
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 2, seed=14)])
+    inp = pack(op, nat, EVEN)
+    src = unpack(op, inp, 2, EVEN)
+    out = op.new_field(2)
+    op.mpcdagmpc(inp, out, 2)
+    assert rel_per_rhs(unpack(op, out, 2, EVEN), np.stack([L.mpcdagmpc(U, v, M5, MF) for v in src])) < tol
+
+
+def test_repeat_is_bitwise_deterministic():
+    dims, Ls = (4, 4, 6, 8), 5
+    op, U = make_operator(dims, Ls, seed=15)
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 1, seed=16)])
+    inp = pack(op, nat, EVEN)
+    a, b = op.new_field(1), op.new_field(1)
+    op.mpcdagmpc(inp, a, 1)
+    op.set_tile(8)  # different workgroup shape, same per-site arithmetic
+    op.mpcdagmpc(inp, b, 1)
+    import torch
+
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)

@@ -1,0 +1,173 @@
+"""GPU parity of the solver, filters and orthonormalisation against the oracle.
+
+CG has many correct answers: the GPU solution must satisfy the residual
+bound when the oracle measures it, and sit within kappa * tol of the oracle's
+CG solution.  The Chebyshev filter, the series, Gram-Schmidt and the power
+method with a fixed iteration count are unique up to rounding and are
+compared directly.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import krylov, lattice as L
+from tests.gpu_util import M5, MF, make_operator, pack, rel, rel_per_rhs, unpack
+
+pytestmark = pytest.mark.gpu
+
+F64, F32, F16S = 0, 1, 2
+EVEN, ODD, BOTH = 0, 1, 2
+C1 = ((4, 4, 4, 4), 8)
+
+
+def even_fields(dims, Ls, n, seed):
+    return np.stack([L.on_parity(f, EVEN) for f in synth.gaussian_fermion_batch(dims, Ls, n, seed)])
+
+
+def oracle_A(U):
+    return lambda v: L.mpcdagmpc(U, v, M5, MF)
+
+
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_cg_f64_c1(nrhs):
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, eps=0.3, seed=0)
+    b = even_fields(dims, Ls, nrhs, seed=1)
+    x = op.new_field(nrhs)
+    code, iters, res = op.cg(pack(op, b, EVEN), x, nrhs, tol=1e-10, maxiter=5000)
+    xg = unpack(op, x, nrhs, EVEN)
+    A = oracle_A(U)
+    for k in range(nrhs):
+        true = np.linalg.norm((b[k] - A(xg[k])).ravel()) / np.linalg.norm(b[k].ravel())
+        assert true < 1e-10 * 1.5
+        assert abs(true - res[k]) < 1e-11
+        ref = krylov.cg(A, b[k], tol=1e-10, maxiter=5000)
+        assert rel(xg[k], ref.x) < 1e-6  # kappa(C1) ~ 1e3: both within kappa * tol of the solution
+        assert abs(iters[k] - ref.iterations) <= 3
+
+
+def test_cg_initial_guess_is_used():
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0)
+    b = even_fields(dims, Ls, 1, seed=2)
+    A = oracle_A(U)
+    ref = krylov.cg(A, b[0], tol=1e-10)
+    x = pack(op, ref.x[None], EVEN)
+    code, iters, res = op.cg(pack(op, b, EVEN), x, 1, tol=1e-8)
+    assert iters[0] == 0 and res[0] < 1e-8
+
+
+def test_solve_rb_c1():
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0)
+    eta = synth.gaussian_fermion(dims, Ls, seed=1)
+    psi = op.new_field(1, both=True)
+    iters, res = op.solve_rb(pack(op, eta[None], BOTH), psi, tol=1e-10)
+    got = unpack(op, psi, 1, BOTH)[0]
+    assert res < 1e-10 * 1.5
+    # full-operator residual measured by the oracle
+    r = np.linalg.norm((L.ddw(U, got, M5, MF) - eta).ravel()) / np.linalg.norm(eta.ravel())
+    assert r < 1e-7
+    # the oracle's own red-black solve
+    b = L.mpc_dag(U, L.schur_source(U, eta, M5, MF), M5, MF)
+    xe = krylov.cg(oracle_A(U), b, tol=1e-12).x
+    ref = xe + L.reconstruct_odd(U, xe, eta, M5, MF)
+    assert rel(got, ref) < 1e-6
+
+
+@pytest.mark.parametrize("prec", [F32, F16S])
+def test_mixed_precision_cg_reaches_fp64_residual(prec):
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=prec)
+    b = even_fields(dims, Ls, 2, seed=3)
+    x = op.new_field(2, prec=F64)
+    b_dev = op.new_field(2, prec=F64)
+    # b in FP64 packed layout: pack through an FP64 handle
+    op64, _ = make_operator(dims, Ls, seed=0, prec=F64)
+    b_dev = pack(op64, b, EVEN)
+    code, iters, res = op.cg(b_dev, x, 2, tol=1e-10, maxiter=20000)
+    xg = unpack(op64, x, 2, EVEN)
+    A = oracle_A(U)
+    for k in range(2):
+        true = np.linalg.norm((b[k] - A(xg[k])).ravel()) / np.linalg.norm(b[k].ravel())
+        assert true < 1.5e-10
+        assert res[k] < 1.5e-10
+
+
+def test_cg_status_codes():
+    import paper_2103_05034_amd as dwf
+
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0)
+    b = even_fields(dims, Ls, 1, seed=4)
+    x = op.new_field(1)
+    code, iters, res = op.cg(pack(op, b, EVEN), x, 1, tol=1e-12, maxiter=1, allow_noconv=True)
+    assert code == dwf.DWF_ENOCONV and iters[0] == 1
+    bad = b.copy()
+    bad.reshape(-1)[5] = np.nan
+    x = op.new_field(1)
+    with pytest.raises(dwf.DWFError) as e:
+        op.cg(pack(op, bad, EVEN), x, 1, tol=1e-10, maxiter=50)
+    assert e.value.code == dwf.DWF_EBREAKDOWN
+    zero = np.zeros_like(b)
+    x = op.new_field(1)
+    code, iters, res = op.cg(pack(op, zero, EVEN), x, 1, tol=1e-10)
+    assert code == 0 and iters[0] == 0
+    assert not unpack(op, x, 1, EVEN).any()
+
+
+def test_power_method_fixed_iterations():
+    dims, Ls = (2, 2, 2, 2), 4
+    op, U = make_operator(dims, Ls, eps=0.6, seed=12)
+    v0 = even_fields(dims, Ls, 1, seed=5)
+    v = pack(op, v0, EVEN)
+    lam, it = op.power(v, iters=40, rtol=0.0)
+    ref, it_ref = krylov.power_method(oracle_A(U), v0[0], iters=40, rtol=0.0)
+    assert it == 40
+    assert abs(lam - ref) < 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("prec,tol", [(F64, 1e-11), (F32, 1e-5)])
+def test_chebyshev_filter(prec, tol):
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=prec, max_nrhs=2)
+    v = even_fields(dims, Ls, 3, seed=6)
+    buf = pack(op, v, EVEN)
+    src = unpack(op, buf, 3, EVEN)
+    op.chebyshev_filter(buf, 3, order=16, lo=0.1, hi=60.0)  # 3 vectors, chunks of 2
+    got = unpack(op, buf, 3, EVEN)
+    exp = np.stack([krylov.chebyshev_filter(oracle_A(U), s, 16, 0.1, 60.0)[0] for s in src])
+    assert rel_per_rhs(got, exp) < tol
+
+
+def test_chebyshev_series():
+    dims, Ls = (2, 2, 2, 2), 4
+    op, U = make_operator(dims, Ls, eps=0.6, seed=12)
+    eta = even_fields(dims, Ls, 1, seed=7)
+    m, lo, lmax, delta, nvec = 20, 0.05, 30.0, 5, 4
+    out = op.new_field(nvec)
+    op.chebyshev_series(pack(op, eta, EVEN), out, m, lo, lmax, delta, nvec)
+    got = unpack(op, out, nvec, EVEN)
+    phis, _ = krylov.chebyshev_series(oracle_A(U), eta[0], m, lo, lmax, delta, nvec)
+    for k in range(nvec):
+        assert rel(got[k], phis[k]) < 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [(F64, 1e-12), (F32, 2e-5)])
+def test_gram_schmidt(prec, tol):
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=prec)
+    n = 6
+    v = even_fields(dims, Ls, n, seed=8)
+    v[3] = v[3] + 30.0 * v[0]  # poorly conditioned set
+    buf = pack(op, v, EVEN)
+    src = unpack(op, buf, n, EVEN)
+    R = op.gram_schmidt(buf, n)
+    Q = unpack(op, buf, n, EVEN)
+    Qo, Ro = krylov.gram_schmidt(list(src))
+    for k in range(n):
+        assert rel(Q[k], Qo[k]) < tol
+    assert np.max(np.abs(R - Ro)) < tol * np.max(np.abs(Ro))
+    G = np.array([[np.vdot(Q[i].ravel(), Q[j].ravel()) for j in range(n)] for i in range(n)])
+    assert np.max(np.abs(G - np.eye(n))) < (1e-13 if prec == F64 else 1e-5)
