@@ -1,0 +1,491 @@
+#!/usr/bin/env python3
+"""Benchmark of the red-black domain-wall path on one MI355X.
+
+Default workload (FP64, the 16^3 x 32 lattice with Ls = 16, M5 = 1.8,
+mf = 0.01, links exp(0.2 i H), Gaussian source): one *step* is a full
+red-black solve of D_DW psi = eta to a relative residual of 1e-10 -- the
+Schur source, CG on M_pc^dag M_pc, and the odd-site reconstruction -- with
+the source already resident in HBM.
+
+Printed (one JSON line): 5D site-updates/s counted as in the paper (one CG
+iteration = two full matrix multiplies, M_pc = one, i.e. 2 * V5
+site-updates per iteration), the roofline of the hopping kernels measured
+with HIP events over the timed region, and the FP64 oracle timed on the
+host on a bounded sample.
+
+Other workloads (``--workload``): ``batched`` (40 complex64 vectors,
+order-32 Chebyshev filter over [0.05, 60] and FP64-accumulated
+Gram-Schmidt), ``mixed`` (24^3 x 48, Ls = 24, mf = 0.00078: Chebyshev setup
+of 24 vectors + 2 CG solves, FP64 against FP16+scale storage), ``force``
+(8^3 x 16, Ls = 12: dS/dU of the pseudofermion action).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MdagM 5D site-updates/s + HBM GB/s; Chebyshev setup vecs/s, FP64 vs mixed/batched"
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "rb_solve": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2),
+    "batched": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, nvec=40, order=32, lo=0.05, hi=60.0),
+    "mixed": dict(dims=(24, 24, 24, 48), Ls=24, M5=1.8, mf=0.00078, eps=0.15, nvec=24, order=32, lo=0.05, hi=60.0),
+    "force": dict(dims=(8, 8, 8, 16), Ls=12, M5=1.8, mf=0.01, eps=0.2),
+}
+
+SPINOR_BYTES = {0: 192, 1: 96, 2: 52}
+LINK_BYTES = {0: 144, 1: 72, 2: 72}
+
+
+def hop_bytes_per_site(prec, Ls, nrhs=1):
+    """Algorithmic HBM bytes per output even 5D site and rhs of the two hop passes of M_pc.
+
+    pass 1 (t = M5D^-1 D_hop in): read in, write t      -> 2 S + 8 L / (Ls nrhs)
+    pass 2 (out = M5D in - D_hop t / 4): read t, in, write out -> 3 S + 8 L / (Ls nrhs)
+    """
+    S, Lb = SPINOR_BYTES[prec], LINK_BYTES[prec]
+    link = 8.0 * Lb / (Ls * nrhs)
+    return 2 * S + link, 3 * S + link
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def cpu_baseline_rb(cfg):
+    """The oracle as it stands, one M_pc application on the workload's lattice."""
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import lattice as L
+
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    U = synth.gauge_links(dims, cfg["eps"], seed=0)
+    psi = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=1), L.EVEN)
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        L.mpc(U, psi, cfg["M5"], cfg["mf"])
+        dt = time.perf_counter() - t0
+    X, Y, Z, T = dims
+    V5 = X * Y * Z * T * Ls
+    return {
+        "value": V5 / dt,
+        "unit": "5D site-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"one M_pc application (= {V5} site-updates by the paper's counting) of the FP64 NumPy oracle "
+        f"on the {X}x{Y}x{Z}x{T}, Ls={Ls} lattice, BLAS limited to 1 thread; {dt:.1f} s",
+    }
+
+
+def run_rb_solve(args):
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["rb_solve"]
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    X, Y, Z, T = dims
+    V5 = X * Y * Z * T * Ls
+    V5h = V5 // 2
+    log("building inputs")
+    U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
+    eta_nat = torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=1)[None]).to("cuda")
+    op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=1)
+    if args.tile:
+        op.set_tile(args.tile)
+    eta = op.pack(eta_nat, dwf.DWF_BOTH)
+    del eta_nat
+    psi = op.new_field(1, both=True)
+    torch.cuda.synchronize()
+
+    # pure operator throughput (outside the timed region): M_pc^dag M_pc applications
+    v = op.new_field(1)
+    w = op.new_field(1)
+    op.pack(torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=2)[None]).to("cuda"), dwf.DWF_EVEN, out=v)
+    for _ in range(3):
+        op.mpcdagmpc(v, w)
+    torch.cuda.synchronize()
+    napp = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(napp):
+        op.mpcdagmpc(v, w)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_app = e0.elapsed_time(e1) / napp
+    log(f"M_pc^dag M_pc: {ms_app:.3f} ms per application")
+
+    iters_all, res_all = [], []
+    for k in range(args.warmup):
+        psi.zero_()
+        it, res = op.solve_rb(eta, psi, tol=1e-10, maxiter=20000)
+        log(f"warmup {k}: {it} iterations, true residual {res:.2e}")
+    torch.cuda.synchronize()
+    op.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        psi.zero_()
+        it, res = op.solve_rb(eta, psi, tol=1e-10, maxiter=20000)
+        iters_all.append(it)
+        res_all.append(res)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    hop_ms, hop_launches = op.kernel_time()
+    op.enable_timing(False)
+    log(f"timed {args.steps} solves: {dt:.3f} s, iterations {iters_all}, residuals {res_all}")
+
+    site_updates = sum(2 * V5 * it for it in iters_all)
+    value = site_updates / dt
+    b1, b2 = hop_bytes_per_site(0, Ls)
+    bytes_per_launch = V5h * (b1 + b2) / 2  # CG launches alternate pass 1 and pass 2
+    avg_ms = hop_ms / max(hop_launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "5D site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "red-black CG solve to 1e-10, FP64, 16^3x32 Ls=16 M5=1.8 mf=0.01, links exp(0.2iH)",
+            "lattice": [X, Y, Z, T],
+            "Ls": Ls,
+            "M5": cfg["M5"],
+            "mf": cfg["mf"],
+            "tol": 1e-10,
+            "cg_iterations": iters_all,
+            "true_rel_residual": max(res_all),
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "kernel": "hop_kernel (all M_pc passes of the timed solves)",
+            "bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": avg_ms,
+            "launches": hop_launches,
+        },
+        "operator": {
+            "mpcdagmpc_ms": ms_app,
+            "mpcdagmpc_site_updates_per_s": 2 * V5 / (ms_app * 1e-3),
+            "mpcdagmpc_algorithmic_GBs": 2 * V5h * (b1 + b2) / (ms_app * 1e-3) / 1e9,
+        },
+    }
+    op.close()
+    return out
+
+
+def _timed(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, r
+
+
+def _fill_gaussian(op, buf, nvec, dims, Ls, seed, chunk=4):
+    """Pack nvec complex Gaussian even fields into buf, a few at a time."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    fb = op.field_bytes(1)
+    rng_fields = synth.gaussian_fermion_batch(dims, Ls, nvec, seed) if nvec * Ls * np.prod(dims) * 192 < 2**31 else None
+    for k0 in range(0, nvec, chunk):
+        n = min(chunk, nvec - k0)
+        if rng_fields is not None:
+            nat = rng_fields[k0 : k0 + n]
+        else:
+            nat = synth.gaussian_fermion_batch(dims, Ls, n, seed * 1000 + k0)
+        op.pack(torch.from_numpy(nat).to("cuda"), dwf.DWF_EVEN, out=buf[k0 * fb : (k0 + n) * fb])
+        torch.cuda.synchronize()
+
+
+def _setup_time(op, vecs, pristine, nvec, order, lo, hi, steps):
+    """Chebyshev filter of nvec vectors + FP64-accumulated Gram-Schmidt, per step from the same input."""
+    total = 0.0
+    R = None
+    for _ in range(steps):
+        vecs.copy_(pristine)
+        dt, R = _timed(lambda: (op.chebyshev_filter(vecs, nvec, order, lo, hi), op.gram_schmidt(vecs, nvec))[1])
+        total += dt
+    return total, R
+
+
+def run_batched(args):
+    """40 complex64 subspace vectors through the order-32 filter in one multi-rhs launch per pass,
+    then FP64-accumulated Gram-Schmidt; compared with the same work in FP64 one vector at a time."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["batched"]
+    dims, Ls, nvec = cfg["dims"], cfg["Ls"], cfg["nvec"]
+    order, lo, hi = cfg["order"], cfg["lo"], cfg["hi"]
+    X, Y, Z, T = dims
+    V5h = X * Y * Z * T * Ls // 2
+    U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
+    op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F32, max_nrhs=nvec, max_cg_rhs=0)
+    spb, depth, _ = op.autotune(nvec, 3)
+    log(f"batched FP32 autotune: spb={spb} depth={depth}")
+    vecs = op.new_field(nvec)
+    _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
+    pristine = vecs.clone()
+    _setup_time(op, vecs, pristine, nvec, order, lo, hi, args.warmup)
+    op.enable_timing(True)
+    t_b, R_b = _setup_time(op, vecs, pristine, nvec, order, lo, hi, args.steps)
+    hop_ms, hop_n = op.kernel_time()
+    op.enable_timing(False)
+    q_b = vecs[: op.field_bytes(2)].clone()
+    S, Lb = SPINOR_BYTES[1], LINK_BYTES[1]
+    # per filter step: 4 launches; pass bytes per site and rhs: 2S, 3S, 2S, 5S (last reads T_k, T_{k-1}) + links
+    link = 8.0 * Lb / (Ls * nvec)
+    step_bytes = V5h * nvec * (12 * S + 4 * link)
+    achieved = step_bytes / 4 / (hop_ms / max(hop_n, 1) * 1e-3) / 1e9
+    del op, vecs, pristine
+    torch.cuda.empty_cache()
+    log(f"batched: {args.steps} setups in {t_b:.3f} s")
+
+    # FP64, one vector at a time
+    op64 = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=0)
+    op64.autotune(1, 3)
+    v64 = op64.new_field(nvec)
+    _fill_gaussian(op64, v64, nvec, dims, Ls, seed=2)
+    p64 = v64.clone()
+    _setup_time(op64, v64, p64, nvec, order, lo, hi, 1 if args.warmup else 0)
+    t_64, R_64 = _setup_time(op64, v64, p64, nvec, order, lo, hi, max(1, args.steps // 2))
+    t_64 /= max(1, args.steps // 2)
+    # agreement of the orthonormalised vectors (FP32 storage vs FP64)
+    a = op64.unpack(v64[: op64.field_bytes(2)], 2, dwf.DWF_EVEN)
+    op32 = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F32, max_nrhs=2, max_cg_rhs=0)
+    b = op32.unpack(q_b, 2, dwf.DWF_EVEN)
+    agree = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a))
+    per_step = t_b / args.steps
+    return {
+        "metric": METRIC,
+        "value": nvec / per_step,
+        "unit": "Chebyshev setup vecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "40 complex64 vectors, order-32 Chebyshev filter [0.05,60] of M_pc^dag M_pc in one "
+            "multi-rhs launch per pass + FP64-accumulated Gram-Schmidt, 16^3x32 Ls=16",
+            "autotuned_tile": {"sites_per_block": spb, "pipeline_depth": depth},
+            "fp64_one_at_a_time_vecs_per_s": nvec / t_64,
+            "speedup_vs_fp64_unbatched": t_64 / per_step,
+            "fp32_vs_fp64_rel_diff_first_two_vectors": agree,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "kernel": "hop_kernel, FP32, 40 rhs per launch",
+            "avg_launch_ms": hop_ms / max(hop_n, 1),
+            "launches": hop_n,
+        },
+    }
+
+
+def run_mixed(args):
+    """Chebyshev setup of 24 vectors + 2 CG solves to 1e-10 at near-physical mass:
+    FP16 + per-site scale storage (FP32 arithmetic, FP64 reliable updates, batched)
+    against plain FP64 (one rhs at a time)."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["mixed"]
+    dims, Ls, nvec = cfg["dims"], cfg["Ls"], cfg["nvec"]
+    order, lo, hi = cfg["order"], cfg["lo"], cfg["hi"]
+    U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
+    results = {}
+    for name, prec, nb in (("mixed_f16s", dwf.DWF_F16S, nvec), ("plain_f64", dwf.DWF_F64, 1)):
+        op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=prec, max_nrhs=nb, max_cg_rhs=2 if prec else 1)
+        spb, depth, _ = op.autotune(min(nb, 8), 2)
+        vecs = op.new_field(nvec)
+        _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
+        pristine = vecs.clone()
+        # two Gaussian sources, FP64 packed
+        opb = op if prec == dwf.DWF_F64 else None
+        b64 = torch.zeros(2 * op.field_bytes(1, dwf.DWF_F64), dtype=torch.uint8, device="cuda")
+        src_op = op if prec == dwf.DWF_F64 else dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=0)
+        _fill_gaussian(src_op, b64, 2, dims, Ls, seed=5, chunk=1)
+        if src_op is not op:
+            src_op.close()
+            del src_op
+        x64 = torch.zeros_like(b64)
+        t_setup, _ = _setup_time(op, vecs, pristine, nvec, order, lo, hi, 1)
+        fb = op.field_bytes(1, dwf.DWF_F64)
+        iters, res = [], []
+
+        def solves():
+            if prec == dwf.DWF_F64:
+                for k in range(2):
+                    _, it, r = op.cg(b64[k * fb : (k + 1) * fb], x64[k * fb : (k + 1) * fb], 1, tol=1e-10, maxiter=100000)
+                    iters.extend(it)
+                    res.extend(r)
+            else:
+                _, it, r = op.cg(b64, x64, 2, tol=1e-10, maxiter=100000)
+                iters.extend(it)
+                res.extend(r)
+
+        t_solve, _ = _timed(solves)
+        results[name] = {
+            "setup_s": t_setup,
+            "solve_s": t_solve,
+            "total_s": t_setup + t_solve,
+            "cg_iterations": iters,
+            "true_rel_residual": res,
+            "tile": [spb, depth],
+        }
+        log(f"{name}: setup {t_setup:.3f} s, 2 solves {t_solve:.3f} s, iterations {iters}, residuals {res}")
+        op.close()
+        del op, vecs, pristine, b64, x64
+        torch.cuda.empty_cache()
+    speed = results["plain_f64"]["total_s"] / results["mixed_f16s"]["total_s"]
+    return {
+        "metric": METRIC,
+        "value": speed,
+        "unit": "x (plain FP64 time / mixed FP16+scale time), setup of 24 vectors + 2 CG solves to 1e-10",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": results["mixed_f16s"]["total_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16+scale storage, f32 arithmetic, f64 reliable updates",
+        "data": "synthetic",
+        "config": {
+            "workload": "24^3x48 Ls=24 M5=1.8 mf=0.00078 links exp(0.15iH): Chebyshev setup of 24 vectors "
+            "(order 32 [0.05,60]) + FP64 Gram-Schmidt + 2 CG solves to 1e-10",
+            **results,
+        },
+    }
+
+
+def run_force(args):
+    """dS/dU of S = phi^dag (M_pc^dag M_pc)^-1 phi on 8^3 x 16, Ls = 12, FP64: CG, M_pc, force kernel."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["force"]
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
+    op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=1)
+    op.autotune(1, 5)
+    phi = op.new_field(1)
+    _fill_gaussian(op, phi, 1, dims, Ls, seed=3)
+    X, Y = op.new_field(1), op.new_field(1)
+
+    def step():
+        X.zero_()
+        _, it, res = op.cg(phi, X, 1, tol=1e-12, maxiter=100000, allow_noconv=True)
+        op.mpc(X, Y, 1, False)
+        return op.force(X, Y), it, res
+
+    for _ in range(args.warmup):
+        step()
+    t, (G, it, res) = _timed(lambda: [step() for _ in range(args.steps)][-1])
+    # force kernel alone
+    torch.cuda.synchronize()
+    tk, _ = _timed(lambda: [op.force(X, Y, G) for _ in range(20)])
+    return {
+        "metric": METRIC,
+        "value": args.steps / t,
+        "unit": "force evaluations/s (CG to 1e-12 + M_pc + force kernel)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "pseudofermion force dS/dU, 8^3x16 Ls=12 mf=0.01, FP64",
+            "cg_iterations": it,
+            "true_rel_residual": res,
+            "force_kernel_ms": tk / 20 * 1e3,
+        },
+    }
+
+
+RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rb_solve", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="sites per workgroup of the hop kernels (0 = default)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(
+            json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not built"}),
+            flush=True,
+        )
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no HIP device visible"}), flush=True)
+        sys.exit(1)
+    if args.workload != "rb_solve":
+        out = RUNNERS[args.workload](args)
+    else:
+        out = run_rb_solve(args)
+        if not args.no_cpu_baseline:
+            log("timing the oracle (cpu baseline)")
+            out["cpu_baseline"] = cpu_baseline_rb(WORKLOADS["rb_solve"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,6 +77,9 @@ _PROTOS = {
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_set_tile": (_i, [_vp, _i, _i]),
+    "dwf_set_order": (_i, [_vp, _i]),
+    "dwf_set_occupancy": (_i, [_vp, _i]),
+    "dwf_autotune": (_i, [_vp, _i, _i, _c_int_p, _c_int_p, _c_dbl_p]),
     "dwf_enable_timing": (_i, [_vp, _i]),
     "dwf_kernel_time": (_i, [_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong)]),
 }
@@ -121,6 +124,20 @@ def dwf_workspace_bytes(dims, Ls, prec, max_nrhs, max_cg_rhs):
 
 def dwf_field_bytes(dims, Ls, prec, nrhs):
     return load_library().dwf_field_bytes(_dims(dims), Ls, prec, nrhs)
+
+
+def _thin(name):
+    def call(*args):
+        return getattr(load_library(), name)(*args)
+
+    call.__name__ = name
+    call.__doc__ = f"Direct call of {name} from libdwf.so (ctypes arguments, see include/dwf.h)."
+    return call
+
+
+for _name in _PROTOS:
+    if _name not in globals():
+        globals()[_name] = _thin(_name)
 
 
 def _ptr(t):
@@ -294,8 +311,21 @@ class Operator:
         _check(self.lib.dwf_force(self.h, _ptr(X_e), _ptr(Y_e), _ptr(grad)))
         return grad
 
-    def set_tile(self, sites_per_block, rhs_per_block=0):
-        _check(self.lib.dwf_set_tile(self.h, sites_per_block, rhs_per_block))
+    def set_tile(self, sites_per_block, pipeline_depth=0):
+        _check(self.lib.dwf_set_tile(self.h, sites_per_block, pipeline_depth))
+
+    def set_order(self, mode):
+        _check(self.lib.dwf_set_order(self.h, int(mode)))
+
+    def set_occupancy(self, workgroups_per_cu):
+        _check(self.lib.dwf_set_occupancy(self.h, int(workgroups_per_cu)))
+
+    def autotune(self, nrhs=1, reps=10):
+        """Pick the fastest hop launch shape by timing M_pc^dag M_pc; returns (spb, depth, ms)."""
+        spb, depth, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        self._sync_stream()
+        _check(self.lib.dwf_autotune(self.h, nrhs, reps, ctypes.byref(spb), ctypes.byref(depth), ctypes.byref(ms)))
+        return spb.value, depth.value, ms.value
 
     def enable_timing(self, on=True):
         _check(self.lib.dwf_enable_timing(self.h, int(on)))

@@ -1,6 +1,7 @@
 // extern "C" entry points of libdwf: argument checks, workspace carving and the
 // host-side drivers of the red-black operator, CG, the Chebyshev filter, the
 // power method, Gram-Schmidt and the force.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,6 +107,9 @@ size_t carve(dwf_context* c, const int dims[4], int Ls, int prec, int max_nrhs, 
       d->u64 = d->u_buf;
     }
   }
+  d->order = reinterpret_cast<int*>(take((size_t)2 * V4h * sizeof(int)));
+  d->hop_partials = max_cg_rhs > 0 ? reinterpret_cast<double*>(take((size_t)max_cg_rhs * V4h * sizeof(double)))
+                                    : nullptr;
   int pc = chunk;
   d->partial_count = (size_t)pc;
   d->partials = reinterpret_cast<double*>(take((size_t)pc * RED_BLOCKS * 2 * sizeof(double)));
@@ -124,7 +128,9 @@ size_t fbytes(const dwf_context* c, int prec) { return field_bytes_rhs(c, prec);
 // ---------------------------------------------------------------------------
 // Operator compositions (one chunk of at most the temporaries' capacity).
 // ---------------------------------------------------------------------------
-hipError_t mpc_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, int n, int dag) {
+// t_o = M5D^{-1} D_hop^{oe} in ; out = M5D in - D_hop^{eo} t / 4  (optionally |out|^2 partials)
+hipError_t mpc_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, int n, int dag,
+                     double* partial = nullptr) {
   HopArgs a{};
   a.in = in;
   a.out = t;
@@ -136,7 +142,17 @@ hipError_t mpc_chunk(dwf_context* c, int prec, const char* in, char* out, char* 
   b.x = in;
   b.out = out;
   b.alpha = -0.25;
+  b.partial = partial;
   return launch_hop(c, prec, b, DWF_EVEN, dag, EPI_M5, n);
+}
+
+// q = M_pc^dag M_pc p with p.q = |M_pc p|^2 reduced into slot S_PAP
+hipError_t mdagm_pap(dwf_context* c, int prec, const char* p, char* q, char* t, char* u, int n) {
+  hipError_t e = mpc_chunk(c, prec, p, u, t, n, 0, c->hop_partials);
+  if (e != hipSuccess) return e;
+  e = reduce_partials(c, c->hop_partials, hop_blocks(c), n, S_PAP);
+  if (e != hipSuccess) return e;
+  return mpc_chunk(c, prec, u, q, t, n, 1);
 }
 
 hipError_t mdagm_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, char* u, int n) {
@@ -256,6 +272,9 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   c->ws_bytes = ws_bytes;
   carve(c, dims, Ls, prec, max_nrhs, max_cg_rhs, c->ws);
   c->spb = 0;
+  c->depth[0] = c->depth[1] = c->depth[2] = 2;
+  c->order_mode = 0;
+  c->lds_floor = 0;
   c->timing = false;
   c->ev_used = 0;
   c->ev_ms = 0;
@@ -435,8 +454,7 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
       for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
       if (!any) break;
     }
-    HIP_TRY(mdagm_chunk(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
-    HIP_TRY(blas_dot(h, DWF_F64, p, DWF_F64, q, nrhs, S_PAP, false));
+    HIP_TRY(mdagm_pap(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
     HIP_TRY(scal_alpha(h, nrhs));
     HIP_TRY(cg_update_xr(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, DWF_F64, q, nrhs));
     HIP_TRY(scal_beta(h, nrhs));
@@ -476,8 +494,7 @@ static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, 
     bool any = false;
     for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
     if (!any) break;
-    HIP_TRY(mdagm_chunk(h, P, h->lo_p, h->lo_q, h->t_buf, h->u_buf, nrhs));
-    HIP_TRY(blas_dot(h, P, h->lo_p, P, h->lo_q, nrhs, S_PAP, false));
+    HIP_TRY(mdagm_pap(h, P, h->lo_p, h->lo_q, h->t_buf, h->u_buf, nrhs));
     HIP_TRY(scal_alpha(h, nrhs));
     HIP_TRY(cg_update_xr(h, DWF_F32, h->lo_x, DWF_F32, h->lo_r, P, h->lo_p, P, h->lo_q, nrhs));
     pending = true;
@@ -726,11 +743,117 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U) {
 // ---------------------------------------------------------------------------
 // Introspection
 // ---------------------------------------------------------------------------
-int dwf_set_tile(dwf_handle h, int sites_per_block, int rhs_per_block) {
+int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth) {
   if (int r = check_h(h)) return r;
   if (sites_per_block < 0 || sites_per_block * h->g.Ls > 256) return fail(DWF_EINVAL, "sites_per_block * Ls must be <= 256");
+  if (pipeline_depth < 0 || pipeline_depth > 3) return fail(DWF_EINVAL, "pipeline_depth must be 0 (keep), 1, 2 or 3");
   h->spb = sites_per_block;
-  h->rhs_per_block = rhs_per_block;
+  if (pipeline_depth > 0) h->depth[h->prec] = h->depth[DWF_F64] = pipeline_depth;
+  return DWF_OK;
+}
+
+// Host-built traversal orders of the half-lattice sites of each parity.
+//  mode 1: the (x, y, z) box is split into 8 equal boxes (2 x 2 x 2), one per
+//  XCD (workgroups are dealt round-robin over the XCDs and the hop kernels
+//  remap them so that XCD k runs the k-th eighth of the processing order);
+//  inside a box the sites run with t slowest, then z, y, x.  The ±t
+//  neighbours of a site are then read again while its box's few t-slices are
+//  still in that XCD's L2.
+static bool build_order(const Geom& g, int mode, std::vector<int>& ord) {
+  ord.assign((size_t)2 * g.V4h, 0);
+  if (mode == 1) {
+    if (g.X % 4 || g.Y % 4 || g.Z % 4) return false;
+    const int bx = g.X / 2, by = g.Y / 2, bz = g.Z / 2;
+    for (int p = 0; p < 2; ++p) {
+      size_t k = (size_t)p * g.V4h;
+      for (int r = 0; r < 8; ++r) {
+        const int ox = (r & 1) * bx, oy = ((r >> 1) & 1) * by, oz = ((r >> 2) & 1) * bz;
+        for (int t = 0; t < g.T; ++t)
+          for (int z = oz; z < oz + bz; ++z)
+            for (int y = oy; y < oy + by; ++y)
+              for (int x = ox; x < ox + bx; ++x)
+                if (((x + y + z + t) & 1) == p) ord[k++] = (int)half_index(g, x, y, z, t);
+      }
+      if (k != (size_t)(p + 1) * g.V4h) return false;
+    }
+    return true;
+  }
+  return false;
+}
+
+int dwf_set_order(dwf_handle h, int mode) {
+  if (int r = check_h(h)) return r;
+  if (mode == 0) {
+    h->order_mode = 0;
+    return DWF_OK;
+  }
+  std::vector<int> ord;
+  if (!build_order(h->g, mode, ord)) return fail(DWF_EINVAL, "traversal order %d not available for this lattice", mode);
+  HIP_TRY(hipMemcpyAsync(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  h->order_mode = mode;
+  return DWF_OK;
+}
+
+int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu) {
+  if (int r = check_h(h)) return r;
+  if (workgroups_per_cu < 0 || workgroups_per_cu > 64) return fail(DWF_EINVAL, "workgroups_per_cu must be in [0, 64]");
+  // 160 KiB of LDS per CU on gfx950; a launch asking for more than a 1/n share keeps at most n resident
+  h->lds_floor = workgroups_per_cu ? (160 * 1024) / workgroups_per_cu - 1024 : 0;
+  if (h->lds_floor > 64 * 1024) h->lds_floor = 64 * 1024;
+  return DWF_OK;
+}
+
+int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, double* best_ms) {
+  if (int r = check_h(h)) return r;
+  if (nrhs < 1 || nrhs > h->max_nrhs || reps < 1) return fail(DWF_EINVAL, "dwf_autotune: nrhs in [1, max_nrhs], reps >= 1");
+  const int P = h->prec;
+  const int Ls = h->g.Ls;
+  char* v = h->cheb_a;  // zero field; M_pc^dag M_pc maps it onto itself
+  HIP_TRY(blas_zero(h, P, v, nrhs));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const bool was_timing = h->timing;
+  h->timing = false;
+  const int old_spb = h->spb, old_depth = h->depth[P];
+  int bs = 0, bd = 0;
+  double bms = 1e30;
+  for (int threads = 256; threads >= 64; threads /= 2) {
+    const int spb = threads / Ls;
+    if (spb < 1) continue;
+    for (int depth = 1; depth <= 3; ++depth) {
+      h->spb = spb;
+      h->depth[P] = depth;
+      for (int w = 0; w < 2; ++w) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
+      HIP_TRY(hipEventRecord(e0, h->stream));
+      for (int k = 0; k < reps; ++k) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
+      HIP_TRY(hipEventRecord(e1, h->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      const double per = ms / reps;
+      if (per < bms) {
+        bms = per;
+        bs = spb;
+        bd = depth;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->timing = was_timing;
+  if (bs == 0) {
+    h->spb = old_spb;
+    h->depth[P] = old_depth;
+    return fail(DWF_EINVAL, "dwf_autotune: no candidate shape for Ls = %d", Ls);
+  }
+  h->spb = bs;
+  h->depth[P] = bd;
+  if (P != DWF_F64) h->depth[DWF_F64] = bd;
+  if (best_spb) *best_spb = bs;
+  if (best_depth) *best_depth = bd;
+  if (best_ms) *best_ms = bms;
   return DWF_OK;
 }
 

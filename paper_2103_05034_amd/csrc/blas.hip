@@ -71,6 +71,16 @@ __global__ void finalize_kernel(const double* __restrict__ partials, double* __r
   }
 }
 
+// out[rhs * ostride] = sum_k partials[rhs * count + k]
+__global__ void sum_partials_kernel(const double* __restrict__ partials, int count, double* __restrict__ out,
+                                    int ostride) {
+  const int rhs = blockIdx.x;
+  double a = 0, b = 0;
+  for (int k = threadIdx.x; k < count; k += BS) a += partials[(size_t)rhs * count + k];
+  block_reduce2(a, b);
+  if (threadIdx.x == 0) out[(size_t)rhs * ostride] = a;
+}
+
 // <a, b> per rhs; rhs stride given per argument (GS uses Q_k as "rhs" of a
 // batch against one fixed vector b with b_stride = 0)
 template <int PA, int PB>
@@ -296,6 +306,12 @@ static void dot_la(dwf_context* ctx, int pb, VecGeom g, const char* a, size_t sa
     case DWF_F32: dot_l<PA, DWF_F32>(ctx, g, a, sa, b, sb, nrhs); break;
     default: dot_l<PA, DWF_F16S>(ctx, g, a, sa, b, sb, nrhs); break;
   }
+}
+
+hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, partials, count, ctx->scalars + slot,
+                     NSCAL);
+  return hipGetLastError();
 }
 
 hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot, bool imag) {

@@ -248,6 +248,8 @@ struct HopArgs {
   double d, inv_d, corner;  // 5 - M5, 1/d, -mf / (1 + mf d^{-Ls})
   double mf;
   double* partial;    // optional per-workgroup FP64 partial sums (reductions)
+  const int* order;   // optional traversal order of the out parity: processing index -> site h
+  int lds_floor;      // minimum dynamic LDS of the launch (occupancy cap), bytes
 };
 
 // ---------------------------------------------------------------------------
@@ -289,9 +291,13 @@ struct dwf_context {
   double* scalars;   // device scalars (per rhs)
   double* coef;      // Gram-Schmidt projection coefficients
   size_t partial_count;
-  // launch shape
+  // launch shape of the hop kernels (sites per workgroup; load-pipeline depth per precision)
   int spb;
-  int rhs_per_block;
+  int depth[3];
+  double* hop_partials;  // per-workgroup |M_pc p|^2 sums of CG, [max_cg_rhs][V4h]
+  int* order;            // site traversal order per out parity, [2][V4h] (device)
+  int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
+  int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
   // timing of hopping kernels
   bool timing;
   std::vector<dwf::EventPair> ev_pool;

@@ -9,11 +9,15 @@
 //
 // Thread mapping: a workgroup owns `spb` consecutive half-lattice sites and
 // all Ls slices of each; lane = site_local * Ls + s.  Loads of a spinor
-// component are contiguous along s, the Ls lanes of a site read the same link
-// entries, and the M5D / M5D^{-1} epilogues see whole s-columns of a site.
+// component are contiguous along s; the workgroup's links (shared by the Ls
+// lanes of a site) are staged once in LDS; the M5D / M5D^{-1} epilogues see
+// whole s-columns of a site.  The eight neighbour-spinor loads are software
+// pipelined DEPTH directions deep, so a wave keeps several directions of
+// loads in flight instead of draining the memory queue per direction.
 // Workgroups are remapped so that each XCD (workgroups are dealt round-robin
 // over the 8 XCDs) sweeps one contiguous range of sites, which keeps the
 // stencil's neighbour reuse inside one L2.
+#include <algorithm>
 #include <cmath>
 
 #include "dwf_internal.hpp"
@@ -32,63 +36,107 @@ struct LinkT<float> {
   using vec = float2;
 };
 
-template <int PREC, bool DAG, int MU, int BACK>
-__device__ __forceinline__ void hop_dir(const HopArgs& a, const char* in, long long h, int s,
-                                        cplx<typename Store<PREC>::real> acc[12]) {
-  using R = typename Store<PREC>::real;
-  using V = typename LinkT<R>::vec;
-  constexpr int DIR = 2 * MU + BACK;
+// One direction: project the neighbour spinor, rotate by the link (read from
+// the LDS copy, layout [dir*9 + k][spb]) and reconstruct into acc.
+template <class R, bool DAG, int D>
+__device__ __forceinline__ void hop_compute(const cplx<R> psi[12], const cplx<R>* __restrict__ ll, int spb, int sl,
+                                            cplx<R> acc[12]) {
+  constexpr int MU = D / 2;
+  constexpr int BACK = D % 2;
   constexpr int SIGMA = DAG ? (BACK ? -1 : +1) : (BACK ? +1 : -1);
-  const long long V4h = a.V4h;
-  const long long nh = a.nbr[DIR * V4h + h];
-  cplx<R> psi[12];
-  Store<PREC>::load(in, V4h, a.Ls, nh, s, psi);
   cplx<R> hs[6];
   project<MU, SIGMA>(psi, hs);
-  const V* lp = reinterpret_cast<const V*>(a.links) + (size_t)DIR * 9 * V4h + h;
-  cplx<R> u[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    V t = lp[(size_t)k * V4h];
-    u[k] = {t.x, t.y};
-  }
   cplx<R> chi[6];
 #pragma unroll
-  for (int sp = 0; sp < 2; ++sp) {
+  for (int i = 0; i < 3; ++i) {
+    const cplx<R> u0 = ll[(D * 9 + 3 * i + 0) * spb + sl];
+    const cplx<R> u1 = ll[(D * 9 + 3 * i + 1) * spb + sl];
+    const cplx<R> u2 = ll[(D * 9 + 3 * i + 2) * spb + sl];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      cplx<R> v = cmul(u[3 * i + 0], hs[3 * sp + 0]);
-      v = cfma(u[3 * i + 1], hs[3 * sp + 1], v);
-      v = cfma(u[3 * i + 2], hs[3 * sp + 2], v);
+    for (int sp = 0; sp < 2; ++sp) {
+      cplx<R> v = cmul(u0, hs[3 * sp + 0]);
+      v = cfma(u1, hs[3 * sp + 1], v);
+      v = cfma(u2, hs[3 * sp + 2], v);
       chi[3 * sp + i] = v;
     }
   }
   reconstruct<MU, SIGMA>(chi, acc);
 }
 
-// (M5D x)_s or (M5D^dag x)_s for one lane, from x at s, s-1 and s+1 (cyclic).
-template <class R, bool DAG>
-__device__ __forceinline__ void m5d_lane(const cplx<R> xs[12], const cplx<R> xlo[12], const cplx<R> xhi[12],
-                                         int s, int Ls, R d, R mf, cplx<R> out[12]) {
-  const R c_lo = (s == 0) ? mf : (R)-1;       // coefficient of x_{s-1} (wraps with +m)
-  const R c_hi = (s == Ls - 1) ? mf : (R)-1;  // coefficient of x_{s+1}
+// compute direction D from its buffer slot, then refill the slot with D + DEPTH
+template <int PREC, bool DAG, int D, int DEPTH>
+__device__ __forceinline__ void hop_pipeline(const char* in, long long V4h, int Ls, int s, const int nh[8],
+                                             const cplx<typename Store<PREC>::real>* __restrict__ ll, int spb,
+                                             int sl, cplx<typename Store<PREC>::real> (&buf)[DEPTH][12],
+                                             cplx<typename Store<PREC>::real> acc[12]) {
+  if constexpr (D < 8) {
+    hop_compute<typename Store<PREC>::real, DAG, D>(buf[D % DEPTH], ll, spb, sl, acc);
+    if constexpr (D + DEPTH < 8) Store<PREC>::load(in, V4h, Ls, nh[D + DEPTH], s, buf[D % DEPTH]);
+    hop_pipeline<PREC, DAG, D + 1, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+  }
+}
+
+template <int PREC, int J, int DEPTH>
+__device__ __forceinline__ void hop_prologue(const char* in, long long V4h, int Ls, int s, const int nh[8],
+                                             cplx<typename Store<PREC>::real> (&buf)[DEPTH][12]) {
+  if constexpr (J < DEPTH) {
+    Store<PREC>::load(in, V4h, Ls, nh[J], s, buf[J]);
+    hop_prologue<PREC, J + 1, DEPTH>(in, V4h, Ls, s, nh, buf);
+  }
+}
+
+// (M5D x)_s or (M5D^dag x)_s for one lane.  Per chirality only one neighbour
+// slice enters: P_+ couples to s-1 (s+1 for the adjoint), P_- to s+1 (s-1),
+// with the wrapped coupling +m instead of -1.  `up` holds the six upper-spin
+// components of the P_+ neighbour, `lo` the six lower-spin components of the
+// P_- neighbour.
+template <class R>
+__device__ __forceinline__ void m5d_combine(const cplx<R> xs[12], const cplx<R> up[6], const cplx<R> lo[6], R cu,
+                                            R cl, R d, cplx<R> out[12]) {
 #pragma unroll
-  for (int c = 0; c < 12; ++c) {
-    const bool upper = c < 6;  // P_+ spins
-    const bool use_lo = DAG ? !upper : upper;
-    const cplx<R> nb = use_lo ? xlo[c] : xhi[c];
-    const R cf = use_lo ? c_lo : c_hi;
-    out[c] = {d * xs[c].re + cf * nb.re, d * xs[c].im + cf * nb.im};
+  for (int c = 0; c < 6; ++c) {
+    out[c] = {d * xs[c].re + cu * up[c].re, d * xs[c].im + cu * up[c].im};
+    out[6 + c] = {d * xs[6 + c].re + cl * lo[c].re, d * xs[6 + c].im + cl * lo[c].im};
+  }
+}
+
+// load the six components c0..c0+5 of the spinor at (h, s)
+template <int PREC>
+__device__ __forceinline__ void load_half(const char* base, long long V4h, int Ls, long long h, int s, int c0,
+                                          cplx<typename Store<PREC>::real> v[6]) {
+  using R = typename Store<PREC>::real;
+  if constexpr (PREC == DWF_F64) {
+    const double2* p = reinterpret_cast<const double2*>(base) + (h * 12 + c0) * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      double2 t = p[(size_t)c * Ls];
+      v[c] = {t.x, t.y};
+    }
+  } else if constexpr (PREC == DWF_F32) {
+    const float2* p = reinterpret_cast<const float2*>(base) + (h * 12 + c0) * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      float2 t = p[(size_t)c * Ls];
+      v[c] = {t.x, t.y};
+    }
+  } else {
+    const half2v* p = reinterpret_cast<const half2v*>(base) + (h * 12 + c0) * Ls + s;
+    const float scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      half2v t = p[(size_t)c * Ls];
+      v[c] = {(R)t.x * scale, (R)t.y * scale};
+    }
   }
 }
 
 // In-LDS inverse of M5D (or M5D^dag) on the columns of a workgroup.  buf is
 // [spb][12][LP] with LP = Ls + 1.  Per chirality the matrix is d - S with S a
 // cyclic shift whose wrap carries -m (lower shift for P_+, upper for P_-;
-// transposed for the adjoint), so the solve is the recursion
-// y_j = (v_j + y_{j-1}) / d along the shift direction, started from
-// y_{-1} = -m y_{Ls-1}; a first pass with zero start gives y_{Ls-1}'s
-// dependence and fixes y_{-1} = corner * z_{Ls-1}, corner = -m / (1 + m d^-Ls).
+// transposed for the adjoint).  With y_{-1} := -m y_{Ls-1} the solve is the
+// recursion y_j = (v_j + y_{j-1}) / d along the shift direction; the start
+// value follows from Z = sum_j d^{-(Ls-j)} v_j as y_{-1} = corner * Z with
+// corner = -m / (1 + m d^{-Ls}).
 template <class R, bool DAG>
 __device__ __forceinline__ void m5inv_columns(cplx<R>* buf, int spb, int Ls, long long h0, long long V4h,
                                               R inv_d, R corner) {
@@ -101,9 +149,11 @@ __device__ __forceinline__ void m5inv_columns(cplx<R>* buf, int spb, int Ls, lon
     const bool fwd = DAG ? !upper : upper;
     cplx<R>* col = buf + (size_t)(sl * 12 + c) * LP;
     cplx<R> z = {0, 0};
-    for (int j = 0; j < Ls; ++j) {
+    R w = inv_d;  // d^{-(Ls - j)} for j = Ls-1, Ls-2, ...
+    for (int j = Ls - 1; j >= 0; --j) {
       const int sj = fwd ? j : Ls - 1 - j;
-      z = {(col[sj].re + z.re) * inv_d, (col[sj].im + z.im) * inv_d};
+      z = {fma(w, col[sj].re, z.re), fma(w, col[sj].im, z.im)};
+      w *= inv_d;
     }
     cplx<R> y = {corner * z.re, corner * z.im};
     for (int j = 0; j < Ls; ++j) {
@@ -114,93 +164,129 @@ __device__ __forceinline__ void m5inv_columns(cplx<R>* buf, int spb, int Ls, lon
   }
 }
 
-template <int PREC, bool DAG, int EPI>
+// sum over the workgroup of v (FP64), written by thread 0; scratch holds blockDim doubles
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  scratch[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w && (int)threadIdx.x + w < (int)blockDim.x) scratch[threadIdx.x] += scratch[threadIdx.x + w];
+    __syncthreads();
+  }
+  return scratch[0];
+}
+
+template <int PREC, bool DAG, int EPI, int DEPTH>
 __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
   using R = typename Store<PREC>::real;
+  using V = typename LinkT<R>::vec;
   extern __shared__ char smem_raw[];
+  cplx<R>* ll = reinterpret_cast<cplx<R>*>(smem_raw);  // links [72][spb], later reused
   const int Ls = a.Ls;
+  const int spb = a.spb;
   const int b = blockIdx.x;
   const int logical = (b & 7) * a.nb8 + (b >> 3);
   if (logical >= a.nblocks) return;  // whole workgroup leaves together
   const int tid = threadIdx.x;
   const int sl = tid / Ls;
   const int s = tid - sl * Ls;
-  const long long h0 = (long long)logical * a.spb;
-  const long long h = h0 + sl;
-  const bool valid = (sl < a.spb) && (h < a.V4h);
+  const long long V4h = a.V4h;
+  const long long h0 = (long long)logical * spb;  // first processing index of the workgroup
+  const bool valid = (sl < spb) && (h0 + sl < V4h);
+  const long long h = a.order ? (valid ? (long long)a.order[h0 + sl] : 0) : h0 + sl;
   const size_t off = (size_t)blockIdx.y * a.stride;
   const char* in = a.in + off;
 
+  // neighbour indices and the first DEPTH directions' spinors
+  int nh[8];
+#pragma unroll
+  for (int d = 0; d < 8; ++d) nh[d] = valid ? a.nbr[(size_t)d * V4h + h] : 0;
+  cplx<R> buf[DEPTH][12];
+  if (valid) hop_prologue<PREC, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
+  // stage this workgroup's links
+  {
+    const V* lg = reinterpret_cast<const V*>(a.links);
+    for (int idx = tid; idx < spb * 72; idx += blockDim.x) {
+      const int dk = idx / spb;
+      const int sl2 = idx - dk * spb;
+      const long long i2 = h0 + sl2;
+      const long long h2 = (i2 < V4h) ? (a.order ? (long long)a.order[i2] : i2) : -1;
+      V t = (h2 >= 0) ? lg[(size_t)dk * V4h + h2] : V{0, 0};
+      ll[idx] = {t.x, t.y};
+    }
+  }
+  __syncthreads();
   cplx<R> acc[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-  if (valid) {
-    hop_dir<PREC, DAG, 0, 0>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 0, 1>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 1, 0>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 1, 1>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 2, 0>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 2, 1>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 3, 0>(a, in, h, s, acc);
-    hop_dir<PREC, DAG, 3, 1>(a, in, h, s, acc);
-  }
+  if (valid) hop_pipeline<PREC, DAG, 0, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+
   const R alpha = (R)a.alpha;
   char* out = a.out + off;
-
+  cplx<R> v[12];
   if (EPI == EPI_LIN || EPI == EPI_M5INV) {
-    cplx<R> v[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[c] = cscale(alpha, acc[c]);
     if (a.x != nullptr && valid) {
       cplx<R> xv[12];
-      Store<PREC>::load(a.x + off, a.V4h, Ls, h, s, xv);
+      Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
       const R beta = (R)a.beta;
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = {v[c].re + beta * xv[c].re, v[c].im + beta * xv[c].im};
     }
-    if (EPI == EPI_LIN) {
-      if (valid) Store<PREC>::store(out, a.V4h, Ls, h, s, v);
-      return;
-    }
-    cplx<R>* buf = reinterpret_cast<cplx<R>*>(smem_raw);
-    const int LP = Ls + 1;
-    if (valid) {
+    if (EPI == EPI_M5INV) {
+      __syncthreads();  // every lane is done with the link copy
+      cplx<R>* col = ll;
+      const int LP = Ls + 1;
+      if (valid) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) buf[(size_t)(sl * 12 + c) * LP + s] = v[c];
-    }
-    __syncthreads();
-    m5inv_columns<R, DAG>(buf, a.spb, Ls, h0, a.V4h, (R)a.inv_d, (R)a.corner);
-    __syncthreads();
-    if (valid) {
+        for (int c = 0; c < 12; ++c) col[(size_t)(sl * 12 + c) * LP + s] = v[c];
+      }
+      __syncthreads();
+      m5inv_columns<R, DAG>(col, spb, Ls, h0, V4h, (R)a.inv_d, (R)a.corner);
+      __syncthreads();
+      if (valid) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = buf[(size_t)(sl * 12 + c) * LP + s];
-      Store<PREC>::store(out, a.V4h, Ls, h, s, v);
-    }
-    return;
-  } else {  // EPI_M5, EPI_CHEB
-    if (!valid) return;
-    const char* x = a.x + off;
-    const int s_lo = (s == 0) ? Ls - 1 : s - 1;
-    const int s_hi = (s == Ls - 1) ? 0 : s + 1;
-    cplx<R> xs[12], xlo[12], xhi[12], v[12];
-    Store<PREC>::load(x, a.V4h, Ls, h, s, xs);
-    Store<PREC>::load(x, a.V4h, Ls, h, s_lo, xlo);
-    Store<PREC>::load(x, a.V4h, Ls, h, s_hi, xhi);
-    m5d_lane<R, DAG>(xs, xlo, xhi, s, Ls, (R)a.d, (R)a.mf, v);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) v[c] = {v[c].re + alpha * acc[c].re, v[c].im + alpha * acc[c].im};
-    if (EPI == EPI_CHEB) {
-      cplx<R> yv[12], zv[12];
-      Store<PREC>::load(a.y + off, a.V4h, Ls, h, s, yv);
-      Store<PREC>::load(a.z + off, a.V4h, Ls, h, s, zv);
-      const R ca = (R)a.ca, cb = (R)a.cb, cc = (R)a.cc;
-#pragma unroll
-      for (int c = 0; c < 12; ++c) {
-        v[c].re = ca * v[c].re + cb * yv[c].re + cc * zv[c].re;
-        v[c].im = ca * v[c].im + cb * yv[c].im + cc * zv[c].im;
+        for (int c = 0; c < 12; ++c) v[c] = col[(size_t)(sl * 12 + c) * LP + s];
       }
     }
-    Store<PREC>::store(out, a.V4h, Ls, h, s, v);
+  } else {  // EPI_M5, EPI_CHEB
+    if (valid) {
+      const char* x = a.x + off;
+      const int s_lo = (s == 0) ? Ls - 1 : s - 1;
+      const int s_hi = (s == Ls - 1) ? 0 : s + 1;
+      const R m_lo = (s == 0) ? (R)a.mf : (R)-1;       // coupling to slice s-1
+      const R m_hi = (s == Ls - 1) ? (R)a.mf : (R)-1;  // coupling to slice s+1
+      cplx<R> xs[12], up[6], lo[6];
+      Store<PREC>::load(x, V4h, Ls, h, s, xs);
+      // M5D: P_+ from s-1, P_- from s+1; M5D^dag: P_+ from s+1, P_- from s-1
+      load_half<PREC>(x, V4h, Ls, h, DAG ? s_hi : s_lo, 0, up);
+      load_half<PREC>(x, V4h, Ls, h, DAG ? s_lo : s_hi, 6, lo);
+      m5d_combine<R>(xs, up, lo, DAG ? m_hi : m_lo, DAG ? m_lo : m_hi, (R)a.d, v);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[c] = {v[c].re + alpha * acc[c].re, v[c].im + alpha * acc[c].im};
+      if (EPI == EPI_CHEB) {
+        cplx<R> yv[12], zv[12];
+        Store<PREC>::load(a.y + off, V4h, Ls, h, s, yv);
+        Store<PREC>::load(a.z + off, V4h, Ls, h, s, zv);
+        const R ca = (R)a.ca, cb = (R)a.cb, cc = (R)a.cc;
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          v[c].re = ca * v[c].re + cb * yv[c].re + cc * zv[c].re;
+          v[c].im = ca * v[c].im + cb * yv[c].im + cc * zv[c].im;
+        }
+      }
+    }
+  }
+  if (valid) Store<PREC>::store(out, V4h, Ls, h, s, v);
+  if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64), for CG's p.Ap = |M_pc p|^2
+    double n2 = 0;
+    if (valid) {
+#pragma unroll
+      for (int c = 0; c < 12; ++c) n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+    }
+    __syncthreads();  // the LDS region becomes reduction scratch
+    const double tot = block_sum(n2, reinterpret_cast<double*>(smem_raw));
+    if (tid == 0) a.partial[(size_t)blockIdx.y * a.nblocks + logical] = tot;
   }
 }
 
@@ -227,11 +313,13 @@ __global__ void __launch_bounds__(256) site5_kernel(HopArgs a) {
     if (!valid) return;
     const int s_lo = (s == 0) ? Ls - 1 : s - 1;
     const int s_hi = (s == Ls - 1) ? 0 : s + 1;
-    cplx<R> xs[12], xlo[12], xhi[12], v[12];
+    const R m_lo = (s == 0) ? (R)a.mf : (R)-1;
+    const R m_hi = (s == Ls - 1) ? (R)a.mf : (R)-1;
+    cplx<R> xs[12], up[6], lo[6], v[12];
     Store<PREC>::load(in, a.V4h, Ls, h, s, xs);
-    Store<PREC>::load(in, a.V4h, Ls, h, s_lo, xlo);
-    Store<PREC>::load(in, a.V4h, Ls, h, s_hi, xhi);
-    m5d_lane<R, DAG>(xs, xlo, xhi, s, Ls, (R)a.d, (R)a.mf, v);
+    load_half<PREC>(in, a.V4h, Ls, h, DAG ? s_hi : s_lo, 0, up);
+    load_half<PREC>(in, a.V4h, Ls, h, DAG ? s_lo : s_hi, 6, lo);
+    m5d_combine<R>(xs, up, lo, DAG ? m_hi : m_lo, DAG ? m_lo : m_hi, (R)a.d, v);
     Store<PREC>::store(out, a.V4h, Ls, h, s, v);
     return;
   }
@@ -256,6 +344,17 @@ __global__ void __launch_bounds__(256) site5_kernel(HopArgs a) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+static size_t cplx_bytes(int prec) { return prec == DWF_F64 ? 16 : 8; }
+
+// LDS bytes of a hop launch: the link copy, the M5D^{-1} columns and the
+// reduction scratch share one region
+static size_t hop_lds(int prec, int spb, int Ls, int epi, bool reduce) {
+  size_t n = (size_t)spb * 72 * cplx_bytes(prec);
+  if (epi == EPI_M5INV) n = std::max(n, (size_t)spb * 12 * (Ls + 1) * cplx_bytes(prec));
+  if (reduce) n = std::max(n, (size_t)256 * sizeof(double));
+  return n;
+}
+
 void fill_shape(const dwf_context* ctx, HopArgs& a) {
   const int Ls = ctx->g.Ls;
   int spb = ctx->spb;
@@ -265,8 +364,8 @@ void fill_shape(const dwf_context* ctx, HopArgs& a) {
   }
   if (spb * Ls > 256) spb = 256 / Ls;
   if (spb < 1) spb = 1;
-  // the M5D^{-1} epilogue stages spb * 12 * (Ls + 1) FP64 complex values in LDS: keep it <= 64 KiB
-  while (spb > 1 && (size_t)spb * 12 * (Ls + 1) * 16 > 65536) --spb;
+  // every staging buffer must fit 64 KiB of LDS
+  while (spb > 1 && hop_lds(DWF_F64, spb, Ls, EPI_M5INV, true) > 65536) --spb;
   a.spb = spb;
   a.Ls = Ls;
   a.V4h = ctx->g.V4h;
@@ -279,27 +378,35 @@ void fill_shape(const dwf_context* ctx, HopArgs& a) {
   a.corner = -ctx->mf / (1.0 + ctx->mf * std::pow(d, -(double)Ls));
 }
 
-template <int PREC, bool DAG, int EPI>
+template <int PREC, bool DAG, int EPI, int DEPTH>
 static hipError_t launch_hop_t(const HopArgs& a, int nrhs, hipStream_t st) {
-  using R = typename Store<PREC>::real;
   dim3 grid(a.nb8 * 8, nrhs);
   dim3 block(a.spb * a.Ls);
-  size_t lds = (EPI == EPI_M5INV) ? (size_t)a.spb * 12 * (a.Ls + 1) * sizeof(cplx<R>) : 0;
-  hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI>), grid, block, lds, st, a);
+  const size_t lds = std::max(hop_lds(PREC, a.spb, a.Ls, EPI, a.partial != nullptr), (size_t)a.lds_floor);
+  hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH>), grid, block, lds, st, a);
   return hipGetLastError();
 }
 
+template <int PREC, bool DAG, int EPI>
+static hipError_t launch_hop_d(const HopArgs& a, int depth, int nrhs, hipStream_t st) {
+  switch (depth) {
+    case 1: return launch_hop_t<PREC, DAG, EPI, 1>(a, nrhs, st);
+    case 3: return launch_hop_t<PREC, DAG, EPI, 3>(a, nrhs, st);
+    default: return launch_hop_t<PREC, DAG, EPI, 2>(a, nrhs, st);
+  }
+}
+
 template <int PREC>
-static hipError_t launch_hop_p(const HopArgs& a, int dag, int epi, int nrhs, hipStream_t st) {
+static hipError_t launch_hop_p(const HopArgs& a, int dag, int epi, int depth, int nrhs, hipStream_t st) {
   switch (epi * 2 + (dag ? 1 : 0)) {
-    case EPI_LIN * 2 + 0: return launch_hop_t<PREC, false, EPI_LIN>(a, nrhs, st);
-    case EPI_LIN * 2 + 1: return launch_hop_t<PREC, true, EPI_LIN>(a, nrhs, st);
-    case EPI_M5INV * 2 + 0: return launch_hop_t<PREC, false, EPI_M5INV>(a, nrhs, st);
-    case EPI_M5INV * 2 + 1: return launch_hop_t<PREC, true, EPI_M5INV>(a, nrhs, st);
-    case EPI_M5 * 2 + 0: return launch_hop_t<PREC, false, EPI_M5>(a, nrhs, st);
-    case EPI_M5 * 2 + 1: return launch_hop_t<PREC, true, EPI_M5>(a, nrhs, st);
-    case EPI_CHEB * 2 + 0: return launch_hop_t<PREC, false, EPI_CHEB>(a, nrhs, st);
-    case EPI_CHEB * 2 + 1: return launch_hop_t<PREC, true, EPI_CHEB>(a, nrhs, st);
+    case EPI_LIN * 2 + 0: return launch_hop_d<PREC, false, EPI_LIN>(a, depth, nrhs, st);
+    case EPI_LIN * 2 + 1: return launch_hop_d<PREC, true, EPI_LIN>(a, depth, nrhs, st);
+    case EPI_M5INV * 2 + 0: return launch_hop_d<PREC, false, EPI_M5INV>(a, depth, nrhs, st);
+    case EPI_M5INV * 2 + 1: return launch_hop_d<PREC, true, EPI_M5INV>(a, depth, nrhs, st);
+    case EPI_M5 * 2 + 0: return launch_hop_d<PREC, false, EPI_M5>(a, depth, nrhs, st);
+    case EPI_M5 * 2 + 1: return launch_hop_d<PREC, true, EPI_M5>(a, depth, nrhs, st);
+    case EPI_CHEB * 2 + 0: return launch_hop_d<PREC, false, EPI_CHEB>(a, depth, nrhs, st);
+    case EPI_CHEB * 2 + 1: return launch_hop_d<PREC, true, EPI_CHEB>(a, depth, nrhs, st);
   }
   return hipErrorInvalidValue;
 }
@@ -314,23 +421,31 @@ hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int
   else
     a.links = reinterpret_cast<const float2*>(ctx->links32) + link_elems;
   a.stride = field_bytes_rhs(ctx, prec);
+  a.order = ctx->order_mode ? ctx->order + (size_t)out_parity * V4h : nullptr;
+  a.lds_floor = ctx->lds_floor;
+  const int depth = ctx->depth[prec];
   timing_begin(ctx);
   hipError_t e;
   switch (prec) {
-    case DWF_F64: e = launch_hop_p<DWF_F64>(a, dag, epi, nrhs, ctx->stream); break;
-    case DWF_F32: e = launch_hop_p<DWF_F32>(a, dag, epi, nrhs, ctx->stream); break;
-    default: e = launch_hop_p<DWF_F16S>(a, dag, epi, nrhs, ctx->stream); break;
+    case DWF_F64: e = launch_hop_p<DWF_F64>(a, dag, epi, depth, nrhs, ctx->stream); break;
+    case DWF_F32: e = launch_hop_p<DWF_F32>(a, dag, epi, depth, nrhs, ctx->stream); break;
+    default: e = launch_hop_p<DWF_F16S>(a, dag, epi, depth, nrhs, ctx->stream); break;
   }
   timing_end(ctx);
   return e;
 }
 
+int hop_blocks(const dwf_context* ctx) {
+  HopArgs a{};
+  fill_shape(ctx, a);
+  return a.nblocks;
+}
+
 template <int PREC, bool DAG, bool INV>
 static hipError_t launch_site5_t(const HopArgs& a, int nrhs, hipStream_t st) {
-  using R = typename Store<PREC>::real;
   dim3 grid(a.nb8 * 8, nrhs);
   dim3 block(a.spb * a.Ls);
-  size_t lds = INV ? (size_t)a.spb * 12 * (a.Ls + 1) * sizeof(cplx<R>) : 0;
+  size_t lds = INV ? (size_t)a.spb * 12 * (a.Ls + 1) * cplx_bytes(PREC) : 0;
   hipLaunchKernelGGL((site5_kernel<PREC, DAG, INV>), grid, block, lds, st, a);
   return hipGetLastError();
 }

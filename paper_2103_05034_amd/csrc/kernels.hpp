@@ -16,6 +16,7 @@ void timing_end(dwf_context* ctx);
 // hop.hip
 void fill_shape(const dwf_context* ctx, HopArgs& a);
 hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int dag, int epi, int nrhs);
+int hop_blocks(const dwf_context* ctx);  // workgroups per rhs of a hop launch
 hipError_t launch_site5(dwf_context* ctx, int prec, const char* in, char* out, int dag, int inv, int nrhs);
 
 // setup.hip
@@ -26,7 +27,7 @@ hipError_t launch_pack(dwf_context* ctx, int prec, const void* natural, char* pa
 
 // blas.hip -- per-rhs reductions land in ctx->scalars[rhs * NSCAL + slot]
 constexpr int NSCAL = 16;
-constexpr int RED_BLOCKS = 256;  // partial sums per rhs
+constexpr int RED_BLOCKS = 1024;  // partial sums per rhs
 enum Slot {
   S_RR = 0,      // |r|^2 (recursive)
   S_RR_OLD = 1,
@@ -43,6 +44,8 @@ enum Slot {
   S_ITERS = 12,  // iterations done while active
 };
 
+// out[rhs * NSCAL + slot] = sum_k partials[rhs * count + k] (fixed order)
+hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot);
 // result[rhs] = <a, b> (complex, FP64 accumulation) into scalars[rhs*NSCAL + slot (+1 imag)]
 hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot,
                     bool imag);

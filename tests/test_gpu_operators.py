@@ -157,3 +157,23 @@ def test_repeat_is_bitwise_deterministic():
 
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", [F64, F32, F16S])
+def test_traversal_order_gives_identical_results(prec):
+    """The XCD-octant traversal only permutes which workgroup computes a site."""
+    dims, Ls = (8, 4, 4, 6), 6
+    op, U = make_operator(dims, Ls, seed=17, prec=prec)
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 2, seed=18)])
+    inp = pack(op, nat, EVEN)
+    a, b = op.new_field(2), op.new_field(2)
+    op.mpcdagmpc(inp, a, 2)
+    op.set_order(1)
+    op.mpcdagmpc(inp, b, 2)
+    import torch
+
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    if prec == F64:
+        exp = np.stack([L.mpcdagmpc(U, v, M5, MF) for v in nat])
+        assert rel_per_rhs(unpack(op, b, 2, EVEN), exp) < 1e-13
