@@ -18,14 +18,14 @@
  * Layouts (all device memory, owned by the caller):
  *  - natural gauge field  U[T][Z][Y][X][mu][a][b], complex128 (re, im interleaved);
  *  - natural 5D fermion   psi[rhs][Ls][T][Z][Y][X][spin][colour], complex128;
- *  - packed half field (one parity) per right-hand side: [V4h][12][Ls] complex
- *    values, spin-colour index c = 3*spin + colour, s fastest, site index
- *    h = (x + X*(y + Y*(z + Z*t))) / 2; right-hand sides are consecutive blocks.
- *      DWF_F64 : complex128, 192 * Ls * V4h bytes per rhs
- *      DWF_F32 : complex64,   96 * Ls * V4h bytes per rhs
- *      DWF_F16S: per rhs, [V4h][12][Ls] pairs of IEEE halves (v / scale, round to
- *                nearest even) followed by [V4h][Ls] float scales = max |v| over
- *                the 24 reals of the spinor; 52 * Ls * V4h bytes per rhs
+ *  - packed half field (one parity) per right-hand side, site index
+ *    h = (x + X*(y + Y*(z + Z*t))) / 2, spin-colour index c = 3*spin + colour,
+ *    slice s; right-hand sides are consecutive blocks:
+ *      DWF_F64 : [V4h][12][Ls] complex128, 192 * Ls * V4h bytes per rhs
+ *      DWF_F32 : [V4h][6][Ls][2] complex64 (c = 2j + k), 96 * Ls * V4h bytes per rhs
+ *      DWF_F16S: [V4h][3][Ls][4] pairs of IEEE halves (c = 4j + k; value / scale,
+ *                round to nearest even) followed by [V4h][Ls] float scales
+ *                = max |v| over the 24 reals of the spinor; 52 * Ls * V4h bytes per rhs
  *  - packed "both parities" field: the even half field of all rhs, then the odd.
  *
  * Every call that takes device pointers is asynchronous on the handle's stream

@@ -45,7 +45,7 @@ def solve_normal(U, phi, M5, mf, tol=1e-14, maxiter=100000, dense=False):
     if dense:
         mask = L.parity_entry_mask(phi.shape, L.EVEN)
         M = L.dense_matrix(A, phi.shape, mask)
-        x = np.zeros_like(phi)
+        x = np.zeros(phi.shape, dtype=np.complex128)  # C-contiguous: reshape(-1) is a view
         flat = x.reshape(-1)
         idx = np.flatnonzero(mask.ravel())
         flat[idx] = np.linalg.solve(M, phi.ravel()[idx])

@@ -15,6 +15,10 @@
   k = 0..N-1, all from one recurrence (Deflation basis setup section).
 * ``gram_schmidt`` -- classical Gram-Schmidt applied twice (CGS2), FP64,
   in vector-index order, giving Q R = V with a positive real diagonal of R.
+* ``chebyshev_smoother`` -- S_cheb([a,b],N) r = [c_0/2 + sum_{j=1}^N c_j
+  T_j(x(M^dag M))] M^dag r with the coefficients of the Chebyshev
+  approximation of 1/y at theta_k = pi (k + 1/2) / N (Chebyshev smoothers
+  section); evaluated term by term with T_j from the three-term recurrence.
 
 Vectors are NumPy arrays of any shape; operators are callables.
 """
@@ -164,3 +168,31 @@ def gram_schmidt(vectors):
         R[j, j] = rjj
         Q[:, j] = w / rjj
     return [Q[:, j].reshape(shape) for j in range(k)], R
+
+
+def chebyshev_smoother_coeffs(a: float, b: float, N: int):
+    """c_j = (2/N) sum_{k<N} f(y(cos theta_k)) cos(j theta_k), j = 0..N, f(y) = 1/y,
+    theta_k = pi (k + 1/2) / N, y(x) = a + (b - a)(x + 1)/2 (the inverse of the interval map)."""
+    theta = np.pi * (np.arange(N) + 0.5) / N
+    y = a + (b - a) * (np.cos(theta) + 1.0) / 2.0
+    f = 1.0 / y
+    return np.array([2.0 / N * np.sum(f * np.cos(j * theta)) for j in range(N + 1)])
+
+
+def chebyshev_smoother(apply_A, apply_Mdag, r, a: float, b: float, N: int):
+    """S_cheb([a,b],N) r: the polynomial sum_j c_j T_j(x(A)) (c_0 halved) applied to M^dag r."""
+    c = chebyshev_smoother_coeffs(a, b, N)
+    w = apply_Mdag(r)
+
+    def xA(v):
+        return (2.0 * apply_A(v) - (b + a) * v) / (b - a)
+
+    t_prev = w
+    out = 0.5 * c[0] * w
+    if N >= 1:
+        t_cur = xA(w)
+        out = out + c[1] * t_cur
+        for j in range(2, N + 1):
+            t_prev, t_cur = t_cur, 2.0 * xA(t_cur) - t_prev
+            out = out + c[j] * t_cur
+    return out

@@ -153,7 +153,7 @@ def apply_fifth(K: np.ndarray, psi: np.ndarray) -> np.ndarray:
     x = np.moveaxis(psi, -2, 1)  # [Ls, 4, ..., 3]
     flat = x.reshape(Ls * 4, -1)
     y = (K @ flat).reshape((Ls, 4) + rest + (3,))
-    return np.moveaxis(y, 1, -2)
+    return np.ascontiguousarray(np.moveaxis(y, 1, -2))
 
 
 def m5d(psi, M5, mf, dag=False):

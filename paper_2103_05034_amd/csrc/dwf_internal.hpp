@@ -56,10 +56,17 @@ template <class R>
 __device__ __forceinline__ cplx<R> ctimesi(cplx<R> a) { return {-a.im, a.re}; }
 
 // ---------------------------------------------------------------------------
-// Field storage.  A packed half field of one right-hand side holds
-// [V4h][12][Ls] complex values (s fastest, then spin-colour, then site).
+// Field storage.  A packed half field of one right-hand side holds the 12
+// spin-colour components (c = 3 spin + colour) of every (site h, slice s),
+// grouped so that one lane moves 16 bytes per load:
+//   FP64 : [V4h][12][Ls]      complex128            (1 component per 16 B)
+//   FP32 : [V4h][6][Ls][2]    complex64, c = 2j + k (2 components per 16 B)
+//   FP16S: [V4h][3][Ls][4]    half pairs, c = 4j + k (4 components per 16 B),
+//          then [V4h][Ls] FP32 scales
+// In each case s runs fastest across lanes, so a wave's load is contiguous.
 // ---------------------------------------------------------------------------
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+typedef _Float16 half8v __attribute__((ext_vector_type(8)));
 
 template <int PREC>
 struct Store;
@@ -88,17 +95,18 @@ struct Store<DWF_F32> {
   using real = float;
   static constexpr size_t bytes_per_spinor = 96;
   __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
-    const float2* p = reinterpret_cast<const float2*>(base) + h * 12 * Ls + s;
+    const float4* p = reinterpret_cast<const float4*>(base) + h * 6 * Ls + s;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      float2 t = p[(size_t)c * Ls];
-      v[c] = {t.x, t.y};
+    for (int j = 0; j < 6; ++j) {
+      float4 t = p[(size_t)j * Ls];
+      v[2 * j] = {t.x, t.y};
+      v[2 * j + 1] = {t.z, t.w};
     }
   }
   __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
-    float2* p = reinterpret_cast<float2*>(base) + h * 12 * Ls + s;
+    float4* p = reinterpret_cast<float4*>(base) + h * 6 * Ls + s;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) p[(size_t)c * Ls] = make_float2(v[c].re, v[c].im);
+    for (int j = 0; j < 6; ++j) p[(size_t)j * Ls] = make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
   }
 };
 
@@ -109,29 +117,35 @@ struct Store<DWF_F16S> {
   using real = float;
   static constexpr size_t bytes_per_spinor = 52;
   __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
-    const half2v* p = reinterpret_cast<const half2v*>(base) + h * 12 * Ls + s;
+    const half8v* p = reinterpret_cast<const half8v*>(base) + h * 3 * Ls + s;
     const float* sc = reinterpret_cast<const float*>(base + V4h * Ls * 48) + h * Ls + s;
     float scale = *sc;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      half2v t = p[(size_t)c * Ls];
-      v[c] = {(float)t.x * scale, (float)t.y * scale};
+    for (int j = 0; j < 3; ++j) {
+      half8v t = p[(size_t)j * Ls];
+      v[4 * j + 0] = {(float)t[0] * scale, (float)t[1] * scale};
+      v[4 * j + 1] = {(float)t[2] * scale, (float)t[3] * scale};
+      v[4 * j + 2] = {(float)t[4] * scale, (float)t[5] * scale};
+      v[4 * j + 3] = {(float)t[6] * scale, (float)t[7] * scale};
     }
   }
   __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    half2v* p = reinterpret_cast<half2v*>(base) + h * 12 * Ls + s;
+    half8v* p = reinterpret_cast<half8v*>(base) + h * 3 * Ls + s;
     float* sc = reinterpret_cast<float*>(base + V4h * Ls * 48) + h * Ls + s;
     *sc = m;
     const float d = (m > 0.f) ? m : 1.f;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      half2v t;
-      t.x = (_Float16)(v[c].re / d);
-      t.y = (_Float16)(v[c].im / d);
-      p[(size_t)c * Ls] = t;
+    for (int j = 0; j < 3; ++j) {
+      half8v t;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        t[2 * k] = (_Float16)(v[4 * j + k].re / d);
+        t[2 * k + 1] = (_Float16)(v[4 * j + k].im / d);
+      }
+      p[(size_t)j * Ls] = t;
     }
   }
 };

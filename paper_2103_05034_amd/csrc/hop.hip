@@ -113,19 +113,29 @@ __device__ __forceinline__ void load_half(const char* base, long long V4h, int L
       v[c] = {t.x, t.y};
     }
   } else if constexpr (PREC == DWF_F32) {
-    const float2* p = reinterpret_cast<const float2*>(base) + (h * 12 + c0) * Ls + s;
+    const float4* p = reinterpret_cast<const float4*>(base) + (h * 6 + c0 / 2) * Ls + s;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      float2 t = p[(size_t)c * Ls];
-      v[c] = {t.x, t.y};
+    for (int j = 0; j < 3; ++j) {
+      float4 t = p[(size_t)j * Ls];
+      v[2 * j] = {t.x, t.y};
+      v[2 * j + 1] = {t.z, t.w};
     }
   } else {
-    const half2v* p = reinterpret_cast<const half2v*>(base) + (h * 12 + c0) * Ls + s;
+    // c0 = 0: groups 0 and 1 (components 0..3, 4..5); c0 = 6: groups 1 and 2 (6..7, 8..11)
+    const half8v* p = reinterpret_cast<const half8v*>(base) + h * 3 * Ls + s;
     const float scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
+    const half8v g0 = p[(size_t)(c0 == 0 ? 0 : 1) * Ls];
+    const half8v g1 = p[(size_t)(c0 == 0 ? 1 : 2) * Ls];
+    if (c0 == 0) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      half2v t = p[(size_t)c * Ls];
-      v[c] = {(R)t.x * scale, (R)t.y * scale};
+      for (int k = 0; k < 4; ++k) v[k] = {(R)g0[2 * k] * scale, (R)g0[2 * k + 1] * scale};
+#pragma unroll
+      for (int k = 0; k < 2; ++k) v[4 + k] = {(R)g1[2 * k] * scale, (R)g1[2 * k + 1] * scale};
+    } else {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) v[k] = {(R)g0[4 + 2 * k] * scale, (R)g0[4 + 2 * k + 1] * scale};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[2 + k] = {(R)g1[2 * k] * scale, (R)g1[2 * k + 1] * scale};
     }
   }
 }

@@ -49,3 +49,40 @@ def rel(a, b):
 
 def rel_per_rhs(a, b):
     return max(rel(a[k], b[k]) for k in range(a.shape[0]))
+
+
+def patch_indices(dims, centre, radius):
+    """Index arrays (t, z, y, x order) of a periodic patch of side 2*radius+2
+    around ``centre`` = (x, y, z, t), with the origin's coordinate sum even so
+    the patch's own checkerboard parity equals the lattice's."""
+    X, Y, Z, T = dims
+    side = 2 * radius + 2
+    origin = [c - radius for c in centre]
+    if sum(origin) % 2:
+        origin[0] -= 1  # keep parity; the centre stays >= radius from both ends
+    idx = [np.arange(o, o + side) % L for o, L in zip(origin, (X, Y, Z, T))]
+    local = tuple(c - o for c, o in zip(centre, origin))
+    return idx, local
+
+
+def take_patch(field, idx, lattice_axes_from_end):
+    """Sub-array of a natural-layout field at the patch indices (periodic)."""
+    ix, iy, iz, it = idx
+    a = lattice_axes_from_end  # axis of x counted from the end (fermions: -3, links: -3)
+    out = np.take(field, it, axis=a - 3)
+    out = np.take(out, iz, axis=a - 2)
+    out = np.take(out, iy, axis=a - 1)
+    out = np.take(out, ix, axis=a)
+    return out
+
+
+def sample_sites(dims, n, seed, parity=0):
+    """n distinct lattice sites (x, y, z, t) of one parity."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z, T = dims
+    out = []
+    while len(out) < n:
+        c = (int(rng.integers(X)), int(rng.integers(Y)), int(rng.integers(Z)), int(rng.integers(T)))
+        if sum(c) % 2 == parity and c not in out:
+            out.append(c)
+    return out

@@ -52,7 +52,7 @@ def dense_A():
     idx = np.flatnonzero(even.ravel())
 
     def apply(v):
-        out = np.zeros_like(v)
+        out = np.zeros(v.shape, dtype=np.complex128)  # C-contiguous, so reshape(-1) is a view
         out.reshape(-1)[idx] = A @ v.reshape(-1)[idx]
         return out
 
@@ -169,3 +169,39 @@ def test_rb_counting_golden():
     assert g["rb_cgnr_form1_matmuls"] == g["full_matmuls_per_rb_iteration"] * g["rb_cgnr_form1_iterations"]
     assert g["rb_cgnr_form2_matmuls"] == g["full_matmuls_per_rb_iteration"] * g["rb_cgnr_form2_iterations"]
     assert g["half_dhop_per_rb_iteration"] == 2 * g["full_matmuls_per_rb_iteration"]
+
+
+def test_smoother_coefficients_match_numpy_interpolation():
+    """The coefficients are Chebyshev interpolation of 1/y at the first-kind nodes:
+    numpy's chebinterpolate on the same N nodes gives c_0/2, c_1, ..., c_{N-1}, and c_N = 0."""
+    a, b, N = 0.5, 60.0, 12
+    c = krylov.chebyshev_smoother_coeffs(a, b, N)
+    ref = np.polynomial.chebyshev.chebinterpolate(lambda x: 1.0 / (a + (b - a) * (x + 1) / 2), N - 1)
+    assert np.allclose(c[0] / 2, ref[0], rtol=1e-13, atol=0)
+    assert np.allclose(c[1:N], ref[1:], rtol=1e-10, atol=1e-15)
+    assert abs(c[N]) < 1e-14 * abs(c[0])
+
+
+def test_smoother_vs_eigendecomposition_and_inverse(dense_A):
+    """S_cheb r = V p(Lambda) V^dag M^dag r with p the interpolant of 1/y, and on a
+    spectrum inside [a, b] it approaches (M^dag M)^{-1} M^dag r = M^{-1} r as N grows."""
+    d = dense_A
+    U = d["U"]
+    r = L.on_parity(synth.gaussian_fermion(d["dims"], d["Ls"], seed=26), L.EVEN)
+    mdag = lambda v: L.mpc_dag(U, v, M5, MF)
+    a, b = 0.9 * d["w"].min(), 1.1 * d["w"].max()
+    N = 24
+    got = krylov.chebyshev_smoother(d["apply"], mdag, r, a, b, N)
+    c = krylov.chebyshev_smoother_coeffs(a, b, N)
+    x = 2 * (d["w"] - a) / (b - a) - 1
+    poly = 0.5 * c[0] + sum(c[j] * cheb_closed(j, x) for j in range(1, N + 1))
+    wv = d["V"].conj().T @ mdag(r).reshape(-1)[d["idx"]]
+    expect = d["V"] @ (poly * wv)
+    assert np.linalg.norm(got.reshape(-1)[d["idx"]] - expect) < 1e-11 * np.linalg.norm(expect)
+    # accuracy of the polynomial approximation to 1/y improves with N on [a, b]
+    errs = []
+    for N in (8, 32, 128):
+        s = krylov.chebyshev_smoother(d["apply"], mdag, r, a, b, N)
+        exact = d["V"] @ (wv / d["w"])
+        errs.append(np.linalg.norm(s.reshape(-1)[d["idx"]] - exact) / np.linalg.norm(exact))
+    assert errs[0] > errs[1] > errs[2]
