@@ -156,6 +156,17 @@ int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* ve
 int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int delta, int nvec,
                          const void* eta, void* out_series);
 
+/* The Chebyshev smoother of the normal residual system (Chebyshev smoothers
+ * section): out = [c_0/2 + sum_{j=1}^{order} c_j T_j(x(A))] M_pc^dag in,
+ * A = M_pc^dag M_pc, x(A) = 2 (A - lo) / (hi - lo) - 1, with c_j the Chebyshev
+ * interpolation coefficients of 1/y on [lo, hi] at the nodes
+ * theta_k = pi (k + 1/2) / order.  A polynomial approximation of
+ * (M_pc^dag M_pc)^{-1} M_pc^dag = M_pc^{-1} on [lo, hi]; order applications
+ * of A plus one of M_pc^dag.  in, out: nrhs packed even fields (handle
+ * precision), distinct.  Requires order >= 1 and 0 < lo < hi. */
+int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const void* in_e, void* out_e,
+                           int nrhs);
+
 /* SYNCHRONOUS.  In place Q R = V for nvecs packed even fields (handle
  * precision) by classical Gram-Schmidt applied twice with FP64 dot products;
  * R (nvecs x nvecs complex128, row-major, upper triangular, positive real

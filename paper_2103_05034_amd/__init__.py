@@ -74,6 +74,7 @@ _PROTOS = {
     "dwf_power": (_i, [_vp, _vp, _i, _d, _c_dbl_p, _c_int_p]),
     "dwf_chebyshev_filter": (_i, [_vp, _i, _d, _d, _vp, _i]),
     "dwf_chebyshev_series": (_i, [_vp, _i, _d, _d, _i, _i, _vp, _vp]),
+    "dwf_chebyshev_smoother": (_i, [_vp, _i, _d, _d, _vp, _vp, _i]),
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_set_tile": (_i, [_vp, _i, _i]),
@@ -291,6 +292,11 @@ class Operator:
         self._sync_stream()
         _check(self.lib.dwf_chebyshev_series(self.h, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out_series)))
         return out_series
+
+    def chebyshev_smoother(self, inp, out, order, lo, hi, nrhs=1):
+        self._sync_stream()
+        _check(self.lib.dwf_chebyshev_smoother(self.h, order, lo, hi, _ptr(inp), _ptr(out), nrhs))
+        return out
 
     def gram_schmidt(self, vecs, nvecs):
         import numpy as np

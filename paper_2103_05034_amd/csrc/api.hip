@@ -161,9 +161,9 @@ hipError_t mdagm_chunk(dwf_context* c, int prec, const char* in, char* out, char
   return mpc_chunk(c, prec, u, out, t, n, 1);
 }
 
-// out = ca * A in + cb * y + cc * z   (A = M_pc^dag M_pc; out may alias z)
+// out = ca * A in + cb * y + cc * z + cw * w   (A = M_pc^dag M_pc; out may alias z or w)
 hipError_t cheb_step(dwf_context* c, int prec, const char* in, char* out, const char* y, const char* z, double ca,
-                     double cb, double cc, char* t, char* u, int n) {
+                     double cb, double cc, char* t, char* u, int n, const char* w = nullptr, double cw = 0.0) {
   hipError_t e = mpc_chunk(c, prec, in, u, t, n, 0);
   if (e != hipSuccess) return e;
   HopArgs a{};
@@ -182,6 +182,8 @@ hipError_t cheb_step(dwf_context* c, int prec, const char* in, char* out, const 
   b.ca = ca;
   b.cb = cb;
   b.cc = cc;
+  b.w = w;
+  b.cw = cw;
   return launch_hop(c, prec, b, DWF_EVEN, 1, EPI_CHEB, n);
 }
 
@@ -456,9 +458,9 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
     }
     HIP_TRY(mdagm_pap(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
     HIP_TRY(scal_alpha(h, nrhs));
-    HIP_TRY(cg_update_xr(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, DWF_F64, q, nrhs));
+    HIP_TRY(cg_update_r(h, DWF_F64, r, DWF_F64, q, nrhs));
     HIP_TRY(scal_beta(h, nrhs));
-    HIP_TRY(cg_update_p(h, DWF_F64, r, DWF_F64, p, nrhs));
+    HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, nrhs));
     HIP_TRY(scal_converge(h, nrhs, tol2, true));
   }
   // true residual at exit
@@ -675,6 +677,54 @@ int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int
     char* t = prev;
     prev = cur;
     cur = t;
+  }
+  return DWF_OK;
+}
+
+// Chebyshev smoother of the normal system: out = [c_0/2 + sum_{j=1}^N c_j T_j(x(A))] M_pc^dag in,
+// x(A) = (2A - (lo+hi)) / (hi - lo), c_j the Chebyshev interpolation coefficients of 1/y on
+// [lo, hi] at theta_k = pi (k + 1/2) / N.  Evaluated by Clenshaw's recurrence
+// b_k = 2 x(A) b_{k+1} - b_{k+2} + c_k w, result = x(A) b_1 - b_2 + c_0 w / 2, w = M_pc^dag in,
+// with the recurrence and the c_k w term fused into the last hop pass.
+static void smoother_coeffs(double lo, double hi, int N, std::vector<double>& c) {
+  c.assign((size_t)N + 1, 0.0);
+  for (int j = 0; j <= N; ++j) {
+    double sum = 0.0;
+    for (int k = 0; k < N; ++k) {
+      const double th = M_PI * (k + 0.5) / N;
+      const double y = lo + (hi - lo) * (std::cos(th) + 1.0) / 2.0;
+      sum += std::cos(j * th) / y;
+    }
+    c[j] = 2.0 / N * sum;
+  }
+}
+
+int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const void* in_e, void* out_e, int nrhs) {
+  if (int r = check_h(h)) return r;
+  if (int r = check_io(in_e, out_e, nrhs)) return r;
+  if (order < 1 || !(lo > 0) || !(hi > lo)) return fail(DWF_EINVAL, "dwf_chebyshev_smoother: order >= 1 and 0 < lo < hi");
+  const int P = h->prec;
+  const size_t fb = fbytes(h, P);
+  std::vector<double> c;
+  smoother_coeffs(lo, hi, order, c);
+  const double wdt = hi - lo;
+  const int cap = std::max(1, (h->max_nrhs > 2 ? h->max_nrhs : 2) / 2);  // two Clenshaw buffers per rhs
+  for (int r0 = 0; r0 < nrhs; r0 += cap) {
+    const int n = std::min(cap, nrhs - r0);
+    const char* in = reinterpret_cast<const char*>(in_e) + r0 * fb;
+    char* W = reinterpret_cast<char*>(out_e) + r0 * fb;  // w = M_pc^dag in, kept until the last step
+    char* B1 = h->cheb_a;
+    char* B2 = h->cheb_a + (size_t)n * fb;
+    HIP_TRY(mpc_chunk(h, P, in, W, h->t_buf, n, 1));
+    HIP_TRY(blas_axpby(h, P, W, P, B1, n, c[order], 0.0, -1, -1, 1));  // b_N = c_N w
+    HIP_TRY(blas_zero(h, P, B2, n));                                   // b_{N+1} = 0
+    for (int k = order - 1; k >= 1; --k) {
+      // b_k = (4/w) A b_{k+1} - (2(lo+hi)/w) b_{k+1} - b_{k+2} + c_k w, over b_{k+2}
+      HIP_TRY(cheb_step(h, P, B1, B2, B1, B2, 4.0 / wdt, -2.0 * (hi + lo) / wdt, -1.0, h->t_buf, h->u_buf, n, W, c[k]));
+      std::swap(B1, B2);
+    }
+    // out = x(A) b_1 - b_2 + c_0 w / 2 (written over w)
+    HIP_TRY(cheb_step(h, P, B1, W, B1, B2, 2.0 / wdt, -(hi + lo) / wdt, -1.0, h->t_buf, h->u_buf, n, W, 0.5 * c[0]));
   }
   return DWF_OK;
 }

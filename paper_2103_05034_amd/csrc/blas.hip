@@ -167,6 +167,56 @@ __global__ void cg_xr_kernel(VecGeom g, char* __restrict__ x, char* __restrict__
   }
 }
 
+// r -= alpha q ; partial |r|^2
+template <int PR, int PQ>
+__global__ void cg_r_kernel(VecGeom g, char* __restrict__ r, const char* __restrict__ q, size_t sr, size_t sq,
+                            const double* __restrict__ scal, double* __restrict__ partials) {
+  const int rhs = blockIdx.y;
+  const double alpha = scal[rhs * NSCAL + S_ALPHA];
+  double rr = 0;
+  for (long long i = (long long)blockIdx.x * BS + threadIdx.x; i < g.n; i += (long long)RED_BLOCKS * BS) {
+    cplx<double> vr[12], vq[12];
+    vload<PR>(r + rhs * sr, g, i, vr);
+    if (alpha != 0.0) {
+      vload<PQ>(q + rhs * sq, g, i, vq);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) vr[c] = {fma(-alpha, vq[c].re, vr[c].re), fma(-alpha, vq[c].im, vr[c].im)};
+      vstore<PR>(r + rhs * sr, g, i, vr);
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) rr += vr[c].re * vr[c].re + vr[c].im * vr[c].im;
+  }
+  double dummy = 0;
+  block_reduce2(rr, dummy);
+  if (threadIdx.x == 0) {
+    partials[((size_t)rhs * RED_BLOCKS + blockIdx.x) * 2] = rr;
+    partials[((size_t)rhs * RED_BLOCKS + blockIdx.x) * 2 + 1] = 0;
+  }
+}
+
+// x += alpha p ; p = r + beta p   (both with the old p)
+template <int PX, int PR, int PP>
+__global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __restrict__ r, char* __restrict__ p,
+                             size_t sx, size_t sr, size_t sp, const double* __restrict__ scal) {
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double alpha = scal[rhs * NSCAL + S_ALPHA];
+  const double beta = scal[rhs * NSCAL + S_BETA];
+  cplx<double> vx[12], vr[12], vp[12];
+  vload<PP>(p + rhs * sp, g, i, vp);
+  if (alpha != 0.0) {
+    vload<PX>(x + rhs * sx, g, i, vx);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vx[c] = {fma(alpha, vp[c].re, vx[c].re), fma(alpha, vp[c].im, vx[c].im)};
+    vstore<PX>(x + rhs * sx, g, i, vx);
+  }
+  vload<PR>(r + rhs * sr, g, i, vr);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
+  vstore<PP>(p + rhs * sp, g, i, vr);
+}
+
 // p = r + beta p
 template <int PR, int PP>
 __global__ void cg_p_kernel(VecGeom g, const char* __restrict__ r, char* __restrict__ p, size_t sr, size_t sp,
@@ -393,6 +443,46 @@ hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p,
     p_l<DWF_F32, DWF_F32>(ctx, g, r, p, nrhs);
   else if (pr == DWF_F32 && pp == DWF_F16S)
     p_l<DWF_F32, DWF_F16S>(ctx, g, r, p, nrhs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int PR, int PQ>
+static void r_l(dwf_context* ctx, VecGeom g, char* r, const char* q, int nrhs) {
+  hipLaunchKernelGGL((cg_r_kernel<PR, PQ>), dim3(RED_BLOCKS, nrhs), dim3(BS), 0, ctx->stream, g, r, q,
+                     field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PQ), ctx->scalars, ctx->partials);
+}
+
+hipError_t cg_update_r(dwf_context* ctx, int pr, char* r, int pq, const char* q, int nrhs) {
+  VecGeom g = vgeom(ctx);
+  if (pr == DWF_F64 && pq == DWF_F64)
+    r_l<DWF_F64, DWF_F64>(ctx, g, r, q, nrhs);
+  else if (pr == DWF_F32 && pq == DWF_F32)
+    r_l<DWF_F32, DWF_F32>(ctx, g, r, q, nrhs);
+  else if (pr == DWF_F32 && pq == DWF_F16S)
+    r_l<DWF_F32, DWF_F16S>(ctx, g, r, q, nrhs);
+  else
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, ctx->partials, ctx->scalars + S_RR,
+                     NSCAL, 0);
+  return hipGetLastError();
+}
+
+template <int PX, int PR, int PP>
+static void xp_l(dwf_context* ctx, VecGeom g, char* x, const char* r, char* p, int nrhs) {
+  hipLaunchKernelGGL((cg_xp_kernel<PX, PR, PP>), dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, x, r, p,
+                     field_bytes_rhs(ctx, PX), field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP), ctx->scalars);
+}
+
+hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r, int pp, char* p, int nrhs) {
+  VecGeom g = vgeom(ctx);
+  if (px == DWF_F64 && pr == DWF_F64 && pp == DWF_F64)
+    xp_l<DWF_F64, DWF_F64, DWF_F64>(ctx, g, x, r, p, nrhs);
+  else if (px == DWF_F32 && pr == DWF_F32 && pp == DWF_F32)
+    xp_l<DWF_F32, DWF_F32, DWF_F32>(ctx, g, x, r, p, nrhs);
+  else if (px == DWF_F32 && pr == DWF_F32 && pp == DWF_F16S)
+    xp_l<DWF_F32, DWF_F32, DWF_F16S>(ctx, g, x, r, p, nrhs);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

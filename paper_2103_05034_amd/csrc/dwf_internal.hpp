@@ -241,7 +241,7 @@ enum Epilogue {
   EPI_LIN = 0,    // out = alpha * Dhop(in) + beta * x             (x optional)
   EPI_M5INV = 1,  // out = M5D^{-1} [alpha * Dhop(in) + beta * x]  (x optional)
   EPI_M5 = 2,     // out = M5D x + alpha * Dhop(in)
-  EPI_CHEB = 3,   // out = ca * (M5D x + alpha * Dhop(in)) + cb * y + cc * z
+  EPI_CHEB = 3,   // out = ca * (M5D x + alpha * Dhop(in)) + cb * y + cc * z (+ cw * w)
 };
 
 struct HopArgs {
@@ -250,6 +250,7 @@ struct HopArgs {
   const char* x;      // out parity (EPI_LIN/M5INV optional, EPI_M5/EPI_CHEB required)
   const char* y;      // EPI_CHEB
   const char* z;      // EPI_CHEB (may alias out)
+  const char* w;      // EPI_CHEB optional fourth term (may alias out)
   const void* links;  // packed links of out parity: [dir][9][V4h] complex
   const int* nbr;     // neighbour table of out parity: [dir][V4h]
   size_t stride;      // bytes per rhs of every field argument
@@ -258,7 +259,7 @@ struct HopArgs {
   int spb;            // sites per workgroup
   int nblocks;        // workgroups along the site axis (before XCD padding)
   int nb8;            // workgroups per XCD slot
-  double alpha, beta, ca, cb, cc;
+  double alpha, beta, ca, cb, cc, cw;
   double d, inv_d, corner;  // 5 - M5, 1/d, -mf / (1 + mf d^{-Ls})
   double mf;
   double* partial;    // optional per-workgroup FP64 partial sums (reductions)

@@ -284,6 +284,12 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
           v[c].re = ca * v[c].re + cb * yv[c].re + cc * zv[c].re;
           v[c].im = ca * v[c].im + cb * yv[c].im + cc * zv[c].im;
         }
+        if (a.w != nullptr) {
+          Store<PREC>::load(a.w + off, V4h, Ls, h, s, yv);
+          const R cw = (R)a.cw;
+#pragma unroll
+          for (int c = 0; c < 12; ++c) v[c] = {v[c].re + cw * yv[c].re, v[c].im + cw * yv[c].im};
+        }
       }
     }
   }

@@ -61,6 +61,9 @@ hipError_t cg_update_xr(dwf_context* ctx, int px, char* x, int pr, char* r, int 
                         const char* q, int nrhs);
 // p = r + beta p
 hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs);
+// r -= alpha q with |r|^2 -> S_RR ; then x += alpha p and p = r + beta p in one pass (old p)
+hipError_t cg_update_r(dwf_context* ctx, int pr, char* r, int pq, const char* q, int nrhs);
+hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r, int pp, char* p, int nrhs);
 // scalar bookkeeping kernels
 hipError_t scal_alpha(dwf_context* ctx, int nrhs);  // alpha = rr / pAp  (0 if inactive)
 hipError_t scal_beta(dwf_context* ctx, int nrhs);   // beta = rr_new / rr_old

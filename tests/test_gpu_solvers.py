@@ -171,3 +171,20 @@ def test_gram_schmidt(prec, tol):
     assert np.max(np.abs(R - Ro)) < tol * np.max(np.abs(Ro))
     G = np.array([[np.vdot(Q[i].ravel(), Q[j].ravel()) for j in range(n)] for i in range(n)])
     assert np.max(np.abs(G - np.eye(n))) < (1e-13 if prec == F64 else 1e-5)
+
+
+@pytest.mark.parametrize("prec,tol,nrhs", [(F64, 1e-12, 1), (F64, 1e-12, 3), (F32, 1e-5, 2)])
+def test_chebyshev_smoother(prec, tol, nrhs):
+    """S_cheb([0.5, 60], 12) -- the smoother of the paper's two-level runs -- against the
+    oracle's term-by-term evaluation (the library uses Clenshaw's recurrence)."""
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=prec, max_nrhs=2)
+    r = even_fields(dims, Ls, nrhs, seed=27)
+    src = pack(op, r, EVEN)
+    vals = unpack(op, src, nrhs, EVEN)
+    out = op.new_field(nrhs)
+    op.chebyshev_smoother(src, out, 12, 0.5, 60.0, nrhs)
+    got = unpack(op, out, nrhs, EVEN)
+    mdag = lambda v: L.mpc_dag(U, v, M5, MF)
+    exp = np.stack([krylov.chebyshev_smoother(oracle_A(U), mdag, v, 0.5, 60.0, 12) for v in vals])
+    assert rel_per_rhs(got, exp) < tol
