@@ -41,7 +41,11 @@ WORKLOADS = {
     "batched": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, nvec=40, order=32, lo=0.05, hi=60.0),
     "mixed": dict(dims=(24, 24, 24, 48), Ls=24, M5=1.8, mf=0.00078, eps=0.15, nvec=24, order=32, lo=0.05, hi=60.0),
     "force": dict(dims=(8, 8, 8, 16), Ls=12, M5=1.8, mf=0.01, eps=0.2),
+    "copy": dict(bytes=4 << 30),
 }
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic.json")
+HOP_SOURCE = os.path.join(ROOT, "paper_2103_05034_amd", "csrc", "hop.hip")
 
 SPINOR_BYTES = {0: 192, 1: 96, 2: 52}
 LINK_BYTES = {0: 144, 1: 72, 2: 72}
@@ -56,6 +60,21 @@ def hop_bytes_per_site(prec, Ls, nrhs=1):
     S, Lb = SPINOR_BYTES[prec], LINK_BYTES[prec]
     link = 8.0 * Lb / (Ls * nrhs)
     return 2 * S + link, 3 * S + link
+
+
+def measured_traffic(key):
+    """HBM bytes per hop launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in
+    profiles/hop_traffic.json, or None when the hop kernel source changed since they were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        digest = hashlib.sha256(open(HOP_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("hop_source_sha256") != digest or key not in rec.get("workloads", {}):
+        return None
+    return rec["workloads"][key]["bytes_per_launch"]
 
 
 def log(msg):
@@ -104,8 +123,15 @@ def run_rb_solve(args):
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
     eta_nat = torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=1)[None]).to("cuda")
     op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=1)
+    if args.order:
+        op.set_order(args.order)
     if args.tile:
-        op.set_tile(args.tile)
+        op.set_tile(args.tile, args.depth)
+        tile = (args.tile, args.depth)
+    else:
+        spb, depth, _ = op.autotune(1, 10)
+        tile = (spb, depth)
+    log(f"hop launch shape: {tile[0]} sites per workgroup, pipeline depth {tile[1]}, order {args.order}")
     eta = op.pack(eta_nat, dwf.DWF_BOTH)
     del eta_nat
     psi = op.new_field(1, both=True)
@@ -177,6 +203,7 @@ def run_rb_solve(args):
             "cg_iterations": iters_all,
             "true_rel_residual": max(res_all),
             "parallelism": "single GPU",
+            "hop_tile": {"sites_per_block": tile[0], "pipeline_depth": tile[1], "order": args.order},
         },
         "roofline": {
             "bound": "hbm",
@@ -184,7 +211,7 @@ def run_rb_solve(args):
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_traffic("rb_solve"),
             "kernel": "hop_kernel (all M_pc passes of the timed solves)",
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms,
@@ -256,7 +283,8 @@ def run_batched(args):
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
     op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F32, max_nrhs=nvec, max_cg_rhs=0)
     spb, depth, _ = op.autotune(nvec, 3)
-    log(f"batched FP32 autotune: spb={spb} depth={depth}")
+    rpb = op.tile[2]
+    log(f"batched FP32 autotune: spb={spb} depth={depth} rhs/workgroup={rpb}")
     vecs = op.new_field(nvec)
     _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
     pristine = vecs.clone()
@@ -306,7 +334,7 @@ def run_batched(args):
         "config": {
             "workload": "40 complex64 vectors, order-32 Chebyshev filter [0.05,60] of M_pc^dag M_pc in one "
             "multi-rhs launch per pass + FP64-accumulated Gram-Schmidt, 16^3x32 Ls=16",
-            "autotuned_tile": {"sites_per_block": spb, "pipeline_depth": depth},
+            "autotuned_tile": {"sites_per_block": spb, "pipeline_depth": depth, "rhs_per_block": rpb},
             "fp64_one_at_a_time_vecs_per_s": nvec / t_64,
             "speedup_vs_fp64_unbatched": t_64 / per_step,
             "fp32_vs_fp64_rel_diff_first_two_vectors": agree,
@@ -454,7 +482,36 @@ def run_force(args):
     }
 
 
-RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force}
+def run_copy(args):
+    """Device-to-device copy of a 4 GiB buffer: the known-size kernel that calibrates the
+    FETCH_SIZE / WRITE_SIZE counters, and the practical copy ceiling of the box."""
+    import torch
+
+    n = WORKLOADS["copy"]["bytes"]
+    x = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        y.copy_(x)
+    t, _ = _timed(lambda: [y.copy_(x) for _ in range(args.steps)])
+    gbs = 2 * n * args.steps / t / 1e9
+    return {
+        "metric": "device copy GB/s (read + write)",
+        "value": gbs,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "copy of a 4 GiB buffer (counter calibration)"},
+    }
+
+
+RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force, "copy": run_copy}
 
 
 def main():
@@ -464,7 +521,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rb_solve", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", type=int, default=0, help="sites per workgroup of the hop kernels (0 = default)")
+    ap.add_argument("--tile", type=int, default=0, help="sites per workgroup of the hop kernels (0 = autotune)")
+    ap.add_argument("--depth", type=int, default=0, help="neighbour-load pipeline depth with --tile (0 = keep)")
+    ap.add_argument("--order", type=int, default=0, help="site traversal order (0 lexicographic, 1 XCD octants)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(

@@ -186,10 +186,11 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U);
 /* ---- introspection -------------------------------------------------------- */
 
 /* Launch shape of the hopping kernels: 4D sites per workgroup (0 = default,
- * sites_per_block * Ls <= 256) and the depth (1..3; 0 keeps the current one)
+ * sites_per_block * Ls <= 256), the depth (1..3; 0 keeps the current one)
  * of the neighbour-load pipeline, i.e. how many directions' spinor loads a
- * wave keeps in flight. */
-int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth);
+ * wave keeps in flight, and the right-hand sides one workgroup loops over
+ * with its links staged once in LDS (1..64; 0 keeps the current one). */
+int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_per_block);
 
 /* SYNCHRONOUS.  Traversal order of the half-lattice sites in the hop kernels:
  * 0 = lexicographic (x fastest, t slowest); 1 = the (x,y,z) box split into
@@ -204,9 +205,11 @@ int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu);
 
 /* SYNCHRONOUS.  Times M_pc^dag M_pc on nrhs right-hand sides (<= max_nrhs)
  * for each candidate launch shape -- workgroups of 256, 128 and 64 lanes,
- * load-pipeline depth 1..3 -- over `reps` applications each, keeps the
- * fastest in the handle and reports it (any output pointer may be NULL). */
-int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, double* best_ms);
+ * load-pipeline depth 1..3, 1/2/4/8 rhs per workgroup (<= nrhs) -- over
+ * `reps` applications each, keeps the fastest in the handle and reports it
+ * (any output pointer may be NULL). */
+int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb,
+                 double* best_ms);
 
 /* Average duration (ms) of the hopping-term kernels since the last reset, as
  * measured by HIP events on the handle's stream when timing is enabled. */

@@ -77,10 +77,10 @@ _PROTOS = {
     "dwf_chebyshev_smoother": (_i, [_vp, _i, _d, _d, _vp, _vp, _i]),
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
-    "dwf_set_tile": (_i, [_vp, _i, _i]),
+    "dwf_set_tile": (_i, [_vp, _i, _i, _i]),
     "dwf_set_order": (_i, [_vp, _i]),
     "dwf_set_occupancy": (_i, [_vp, _i]),
-    "dwf_autotune": (_i, [_vp, _i, _i, _c_int_p, _c_int_p, _c_dbl_p]),
+    "dwf_autotune": (_i, [_vp, _i, _i, _c_int_p, _c_int_p, _c_int_p, _c_dbl_p]),
     "dwf_enable_timing": (_i, [_vp, _i]),
     "dwf_kernel_time": (_i, [_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong)]),
 }
@@ -317,8 +317,8 @@ class Operator:
         _check(self.lib.dwf_force(self.h, _ptr(X_e), _ptr(Y_e), _ptr(grad)))
         return grad
 
-    def set_tile(self, sites_per_block, pipeline_depth=0):
-        _check(self.lib.dwf_set_tile(self.h, sites_per_block, pipeline_depth))
+    def set_tile(self, sites_per_block, pipeline_depth=0, rhs_per_block=0):
+        _check(self.lib.dwf_set_tile(self.h, sites_per_block, pipeline_depth, rhs_per_block))
 
     def set_order(self, mode):
         _check(self.lib.dwf_set_order(self.h, int(mode)))
@@ -328,9 +328,14 @@ class Operator:
 
     def autotune(self, nrhs=1, reps=10):
         """Pick the fastest hop launch shape by timing M_pc^dag M_pc; returns (spb, depth, ms)."""
-        spb, depth, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        spb, depth, rpb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
         self._sync_stream()
-        _check(self.lib.dwf_autotune(self.h, nrhs, reps, ctypes.byref(spb), ctypes.byref(depth), ctypes.byref(ms)))
+        _check(
+            self.lib.dwf_autotune(
+                self.h, nrhs, reps, ctypes.byref(spb), ctypes.byref(depth), ctypes.byref(rpb), ctypes.byref(ms)
+            )
+        )
+        self.tile = (spb.value, depth.value, rpb.value)
         return spb.value, depth.value, ms.value
 
     def enable_timing(self, on=True):

@@ -275,6 +275,7 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   carve(c, dims, Ls, prec, max_nrhs, max_cg_rhs, c->ws);
   c->spb = 0;
   c->depth[0] = c->depth[1] = c->depth[2] = 2;
+  c->rpb = 1;
   c->order_mode = 0;
   c->lds_floor = 0;
   c->timing = false;
@@ -793,8 +794,10 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U) {
 // ---------------------------------------------------------------------------
 // Introspection
 // ---------------------------------------------------------------------------
-int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth) {
+int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_per_block) {
   if (int r = check_h(h)) return r;
+  if (rhs_per_block < 0 || rhs_per_block > 64) return fail(DWF_EINVAL, "rhs_per_block must be in [0, 64]");
+  if (rhs_per_block > 0) h->rpb = rhs_per_block;
   if (sites_per_block < 0 || sites_per_block * h->g.Ls > 256) return fail(DWF_EINVAL, "sites_per_block * Ls must be <= 256");
   if (pipeline_depth < 0 || pipeline_depth > 3) return fail(DWF_EINVAL, "pipeline_depth must be 0 (keep), 1, 2 or 3");
   h->spb = sites_per_block;
@@ -854,7 +857,7 @@ int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu) {
   return DWF_OK;
 }
 
-int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, double* best_ms) {
+int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb, double* best_ms) {
   if (int r = check_h(h)) return r;
   if (nrhs < 1 || nrhs > h->max_nrhs || reps < 1) return fail(DWF_EINVAL, "dwf_autotune: nrhs in [1, max_nrhs], reps >= 1");
   const int P = h->prec;
@@ -866,15 +869,19 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
   HIP_TRY(hipEventCreate(&e1));
   const bool was_timing = h->timing;
   h->timing = false;
-  const int old_spb = h->spb, old_depth = h->depth[P];
-  int bs = 0, bd = 0;
+  const int old_spb = h->spb, old_depth = h->depth[P], old_rpb = h->rpb;
+  int bs = 0, bd = 0, br = 1;
   double bms = 1e30;
   for (int threads = 256; threads >= 64; threads /= 2) {
     const int spb = threads / Ls;
     if (spb < 1) continue;
-    for (int depth = 1; depth <= 3; ++depth) {
+    for (int cand = 0; cand < 12; ++cand) {
+      const int depth = 1 + cand % 3;
+      const int rpb = 1 << (cand / 3);
+      if (rpb > nrhs) continue;
       h->spb = spb;
       h->depth[P] = depth;
+      h->rpb = rpb;
       for (int w = 0; w < 2; ++w) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
       HIP_TRY(hipEventRecord(e0, h->stream));
       for (int k = 0; k < reps; ++k) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
@@ -887,6 +894,7 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
         bms = per;
         bs = spb;
         bd = depth;
+        br = rpb;
       }
     }
   }
@@ -896,13 +904,16 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
   if (bs == 0) {
     h->spb = old_spb;
     h->depth[P] = old_depth;
+    h->rpb = old_rpb;
     return fail(DWF_EINVAL, "dwf_autotune: no candidate shape for Ls = %d", Ls);
   }
   h->spb = bs;
   h->depth[P] = bd;
+  h->rpb = br;
   if (P != DWF_F64) h->depth[DWF_F64] = bd;
   if (best_spb) *best_spb = bs;
   if (best_depth) *best_depth = bd;
+  if (best_rpb) *best_rpb = br;
   if (best_ms) *best_ms = bms;
   return DWF_OK;
 }

@@ -265,6 +265,8 @@ struct HopArgs {
   double* partial;    // optional per-workgroup FP64 partial sums (reductions)
   const int* order;   // optional traversal order of the out parity: processing index -> site h
   int lds_floor;      // minimum dynamic LDS of the launch (occupancy cap), bytes
+  int nrhs;           // right-hand sides of the launch
+  int rpb;            // right-hand sides per workgroup (looped, sharing the LDS links)
 };
 
 // ---------------------------------------------------------------------------
@@ -309,6 +311,7 @@ struct dwf_context {
   // launch shape of the hop kernels (sites per workgroup; load-pipeline depth per precision)
   int spb;
   int depth[3];
+  int rpb;
   double* hop_partials;  // per-workgroup |M_pc p|^2 sums of CG, [max_cg_rhs][V4h]
   int* order;            // site traversal order per out parity, [2][V4h] (device)
   int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t

@@ -190,9 +190,10 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
   using R = typename Store<PREC>::real;
   using V = typename LinkT<R>::vec;
   extern __shared__ char smem_raw[];
-  cplx<R>* ll = reinterpret_cast<cplx<R>*>(smem_raw);  // links [72][spb], later reused
   const int Ls = a.Ls;
   const int spb = a.spb;
+  cplx<R>* ll = reinterpret_cast<cplx<R>*>(smem_raw);  // links [72][spb], kept for all rhs of the workgroup
+  char* scratch = smem_raw + (size_t)spb * 72 * sizeof(cplx<R>);  // M5D^{-1} columns / reduction
   const int b = blockIdx.x;
   const int logical = (b & 7) * a.nb8 + (b >> 3);
   if (logical >= a.nblocks) return;  // whole workgroup leaves together
@@ -203,16 +204,11 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
   const long long h0 = (long long)logical * spb;  // first processing index of the workgroup
   const bool valid = (sl < spb) && (h0 + sl < V4h);
   const long long h = a.order ? (valid ? (long long)a.order[h0 + sl] : 0) : h0 + sl;
-  const size_t off = (size_t)blockIdx.y * a.stride;
-  const char* in = a.in + off;
 
-  // neighbour indices and the first DEPTH directions' spinors
   int nh[8];
 #pragma unroll
   for (int d = 0; d < 8; ++d) nh[d] = valid ? a.nbr[(size_t)d * V4h + h] : 0;
-  cplx<R> buf[DEPTH][12];
-  if (valid) hop_prologue<PREC, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
-  // stage this workgroup's links
+  // stage this workgroup's links once; every rhs the workgroup handles reuses them
   {
     const V* lg = reinterpret_cast<const V*>(a.links);
     for (int idx = tid; idx < spb * 72; idx += blockDim.x) {
@@ -224,85 +220,91 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
       ll[idx] = {t.x, t.y};
     }
   }
-  __syncthreads();
-  cplx<R> acc[12];
-#pragma unroll
-  for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-  if (valid) hop_pipeline<PREC, DAG, 0, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
-
   const R alpha = (R)a.alpha;
-  char* out = a.out + off;
-  cplx<R> v[12];
-  if (EPI == EPI_LIN || EPI == EPI_M5INV) {
+  for (int rr = 0; rr < a.rpb; ++rr) {
+    const int rhs = blockIdx.y * a.rpb + rr;
+    if (rhs >= a.nrhs) break;  // uniform across the workgroup
+    const size_t off = (size_t)rhs * a.stride;
+    const char* in = a.in + off;
+    cplx<R> buf[DEPTH][12];
+    if (valid) hop_prologue<PREC, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
+    __syncthreads();  // links staged (first rhs); scratch free (later rhs)
+    cplx<R> acc[12];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) v[c] = cscale(alpha, acc[c]);
-    if (a.x != nullptr && valid) {
-      cplx<R> xv[12];
-      Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
-      const R beta = (R)a.beta;
+    for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
+    if (valid) hop_pipeline<PREC, DAG, 0, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+
+    char* out = a.out + off;
+    cplx<R> v[12];
+    if (EPI == EPI_LIN || EPI == EPI_M5INV) {
 #pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = {v[c].re + beta * xv[c].re, v[c].im + beta * xv[c].im};
-    }
-    if (EPI == EPI_M5INV) {
-      __syncthreads();  // every lane is done with the link copy
-      cplx<R>* col = ll;
-      const int LP = Ls + 1;
-      if (valid) {
+      for (int c = 0; c < 12; ++c) v[c] = cscale(alpha, acc[c]);
+      if (a.x != nullptr && valid) {
+        cplx<R> xv[12];
+        Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
+        const R beta = (R)a.beta;
 #pragma unroll
-        for (int c = 0; c < 12; ++c) col[(size_t)(sl * 12 + c) * LP + s] = v[c];
+        for (int c = 0; c < 12; ++c) v[c] = {v[c].re + beta * xv[c].re, v[c].im + beta * xv[c].im};
       }
-      __syncthreads();
-      m5inv_columns<R, DAG>(col, spb, Ls, h0, V4h, (R)a.inv_d, (R)a.corner);
-      __syncthreads();
-      if (valid) {
+      if (EPI == EPI_M5INV) {
+        cplx<R>* col = reinterpret_cast<cplx<R>*>(scratch);
+        const int LP = Ls + 1;
+        if (valid) {
 #pragma unroll
-        for (int c = 0; c < 12; ++c) v[c] = col[(size_t)(sl * 12 + c) * LP + s];
-      }
-    }
-  } else {  // EPI_M5, EPI_CHEB
-    if (valid) {
-      const char* x = a.x + off;
-      const int s_lo = (s == 0) ? Ls - 1 : s - 1;
-      const int s_hi = (s == Ls - 1) ? 0 : s + 1;
-      const R m_lo = (s == 0) ? (R)a.mf : (R)-1;       // coupling to slice s-1
-      const R m_hi = (s == Ls - 1) ? (R)a.mf : (R)-1;  // coupling to slice s+1
-      cplx<R> xs[12], up[6], lo[6];
-      Store<PREC>::load(x, V4h, Ls, h, s, xs);
-      // M5D: P_+ from s-1, P_- from s+1; M5D^dag: P_+ from s+1, P_- from s-1
-      load_half<PREC>(x, V4h, Ls, h, DAG ? s_hi : s_lo, 0, up);
-      load_half<PREC>(x, V4h, Ls, h, DAG ? s_lo : s_hi, 6, lo);
-      m5d_combine<R>(xs, up, lo, DAG ? m_hi : m_lo, DAG ? m_lo : m_hi, (R)a.d, v);
-#pragma unroll
-      for (int c = 0; c < 12; ++c) v[c] = {v[c].re + alpha * acc[c].re, v[c].im + alpha * acc[c].im};
-      if (EPI == EPI_CHEB) {
-        cplx<R> yv[12], zv[12];
-        Store<PREC>::load(a.y + off, V4h, Ls, h, s, yv);
-        Store<PREC>::load(a.z + off, V4h, Ls, h, s, zv);
-        const R ca = (R)a.ca, cb = (R)a.cb, cc = (R)a.cc;
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          v[c].re = ca * v[c].re + cb * yv[c].re + cc * zv[c].re;
-          v[c].im = ca * v[c].im + cb * yv[c].im + cc * zv[c].im;
+          for (int c = 0; c < 12; ++c) col[(size_t)(sl * 12 + c) * LP + s] = v[c];
         }
-        if (a.w != nullptr) {
-          Store<PREC>::load(a.w + off, V4h, Ls, h, s, yv);
-          const R cw = (R)a.cw;
+        __syncthreads();
+        m5inv_columns<R, DAG>(col, spb, Ls, h0, V4h, (R)a.inv_d, (R)a.corner);
+        __syncthreads();
+        if (valid) {
 #pragma unroll
-          for (int c = 0; c < 12; ++c) v[c] = {v[c].re + cw * yv[c].re, v[c].im + cw * yv[c].im};
+          for (int c = 0; c < 12; ++c) v[c] = col[(size_t)(sl * 12 + c) * LP + s];
         }
       }
-    }
-  }
-  if (valid) Store<PREC>::store(out, V4h, Ls, h, s, v);
-  if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64), for CG's p.Ap = |M_pc p|^2
-    double n2 = 0;
-    if (valid) {
+    } else {  // EPI_M5, EPI_CHEB
+      if (valid) {
+        const char* x = a.x + off;
+        const int s_lo = (s == 0) ? Ls - 1 : s - 1;
+        const int s_hi = (s == Ls - 1) ? 0 : s + 1;
+        const R m_lo = (s == 0) ? (R)a.mf : (R)-1;       // coupling to slice s-1
+        const R m_hi = (s == Ls - 1) ? (R)a.mf : (R)-1;  // coupling to slice s+1
+        cplx<R> xs[12], up[6], lo[6];
+        Store<PREC>::load(x, V4h, Ls, h, s, xs);
+        // M5D: P_+ from s-1, P_- from s+1; M5D^dag: P_+ from s+1, P_- from s-1
+        load_half<PREC>(x, V4h, Ls, h, DAG ? s_hi : s_lo, 0, up);
+        load_half<PREC>(x, V4h, Ls, h, DAG ? s_lo : s_hi, 6, lo);
+        m5d_combine<R>(xs, up, lo, DAG ? m_hi : m_lo, DAG ? m_lo : m_hi, (R)a.d, v);
 #pragma unroll
-      for (int c = 0; c < 12; ++c) n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+        for (int c = 0; c < 12; ++c) v[c] = {v[c].re + alpha * acc[c].re, v[c].im + alpha * acc[c].im};
+        if (EPI == EPI_CHEB) {
+          cplx<R> yv[12], zv[12];
+          Store<PREC>::load(a.y + off, V4h, Ls, h, s, yv);
+          Store<PREC>::load(a.z + off, V4h, Ls, h, s, zv);
+          const R ca = (R)a.ca, cb = (R)a.cb, cc = (R)a.cc;
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {
+            v[c].re = ca * v[c].re + cb * yv[c].re + cc * zv[c].re;
+            v[c].im = ca * v[c].im + cb * yv[c].im + cc * zv[c].im;
+          }
+          if (a.w != nullptr) {
+            Store<PREC>::load(a.w + off, V4h, Ls, h, s, yv);
+            const R cw = (R)a.cw;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) v[c] = {v[c].re + cw * yv[c].re, v[c].im + cw * yv[c].im};
+          }
+        }
+      }
     }
-    __syncthreads();  // the LDS region becomes reduction scratch
-    const double tot = block_sum(n2, reinterpret_cast<double*>(smem_raw));
-    if (tid == 0) a.partial[(size_t)blockIdx.y * a.nblocks + logical] = tot;
+    if (valid) Store<PREC>::store(out, V4h, Ls, h, s, v);
+    if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64), for CG's p.Ap = |M_pc p|^2
+      double n2 = 0;
+      if (valid) {
+#pragma unroll
+        for (int c = 0; c < 12; ++c) n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
+      }
+      const double tot = block_sum(n2, reinterpret_cast<double*>(scratch));
+      if (tid == 0) a.partial[(size_t)rhs * a.nblocks + logical] = tot;
+    }
   }
 }
 
@@ -362,13 +364,13 @@ __global__ void __launch_bounds__(256) site5_kernel(HopArgs a) {
 // ---------------------------------------------------------------------------
 static size_t cplx_bytes(int prec) { return prec == DWF_F64 ? 16 : 8; }
 
-// LDS bytes of a hop launch: the link copy, the M5D^{-1} columns and the
-// reduction scratch share one region
+// LDS bytes of a hop launch: the link copy (kept for all rhs of a workgroup)
+// followed by a scratch region for the M5D^{-1} columns or the reduction
 static size_t hop_lds(int prec, int spb, int Ls, int epi, bool reduce) {
-  size_t n = (size_t)spb * 72 * cplx_bytes(prec);
-  if (epi == EPI_M5INV) n = std::max(n, (size_t)spb * 12 * (Ls + 1) * cplx_bytes(prec));
-  if (reduce) n = std::max(n, (size_t)256 * sizeof(double));
-  return n;
+  size_t scratch = 0;
+  if (epi == EPI_M5INV) scratch = (size_t)spb * 12 * (Ls + 1) * cplx_bytes(prec);
+  if (reduce) scratch = std::max(scratch, (size_t)256 * sizeof(double));
+  return (size_t)spb * 72 * cplx_bytes(prec) + scratch;
 }
 
 void fill_shape(const dwf_context* ctx, HopArgs& a) {
@@ -396,7 +398,7 @@ void fill_shape(const dwf_context* ctx, HopArgs& a) {
 
 template <int PREC, bool DAG, int EPI, int DEPTH>
 static hipError_t launch_hop_t(const HopArgs& a, int nrhs, hipStream_t st) {
-  dim3 grid(a.nb8 * 8, nrhs);
+  dim3 grid(a.nb8 * 8, (nrhs + a.rpb - 1) / a.rpb);
   dim3 block(a.spb * a.Ls);
   const size_t lds = std::max(hop_lds(PREC, a.spb, a.Ls, EPI, a.partial != nullptr), (size_t)a.lds_floor);
   hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH>), grid, block, lds, st, a);
@@ -439,6 +441,8 @@ hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int
   a.stride = field_bytes_rhs(ctx, prec);
   a.order = ctx->order_mode ? ctx->order + (size_t)out_parity * V4h : nullptr;
   a.lds_floor = ctx->lds_floor;
+  a.nrhs = nrhs;
+  a.rpb = std::max(1, std::min(ctx->rpb, nrhs));
   const int depth = ctx->depth[prec];
   timing_begin(ctx);
   hipError_t e;
