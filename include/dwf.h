@@ -23,8 +23,8 @@
  *    slice s; right-hand sides are consecutive blocks:
  *      DWF_F64 : [V4h][12][Ls] complex128, 192 * Ls * V4h bytes per rhs
  *      DWF_F32 : [V4h][6][Ls][2] complex64 (c = 2j + k), 96 * Ls * V4h bytes per rhs
- *      DWF_F16S: [V4h][3][Ls][4] pairs of IEEE halves (c = 4j + k; value / scale,
- *                round to nearest even) followed by [V4h][Ls] float scales
+ *      DWF_F16S: [V4h][12][Ls] pairs of IEEE halves (value times the FP32
+ *                reciprocal of the scale, round to nearest even) followed by [V4h][Ls] float scales
  *                = max |v| over the 24 reals of the spinor; 52 * Ls * V4h bytes per rhs
  *  - packed "both parities" field: the even half field of all rhs, then the odd.
  *

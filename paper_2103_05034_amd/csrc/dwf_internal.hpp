@@ -61,12 +61,10 @@ __device__ __forceinline__ cplx<R> ctimesi(cplx<R> a) { return {-a.im, a.re}; }
 // grouped so that one lane moves 16 bytes per load:
 //   FP64 : [V4h][12][Ls]      complex128            (1 component per 16 B)
 //   FP32 : [V4h][6][Ls][2]    complex64, c = 2j + k (2 components per 16 B)
-//   FP16S: [V4h][3][Ls][4]    half pairs, c = 4j + k (4 components per 16 B),
-//          then [V4h][Ls] FP32 scales
+//   FP16S: [V4h][12][Ls]      half pairs (4 B), then [V4h][Ls] FP32 scales
 // In each case s runs fastest across lanes, so a wave's load is contiguous.
 // ---------------------------------------------------------------------------
 typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-typedef _Float16 half8v __attribute__((ext_vector_type(8)));
 
 template <int PREC>
 struct Store;
@@ -110,42 +108,36 @@ struct Store<DWF_F32> {
   }
 };
 
-// FP16 values v / scale (round to nearest even) plus one FP32 scale = max |v|
-// per (site, s).  The scale array follows the half data of the same rhs.
+// FP16 values v * (1 / scale) (round to nearest even) plus one FP32 scale =
+// max |v| per (site, s).  Data [V4h][12][Ls] half pairs (4 bytes per lane and
+// component: wider groups made the compiler hoist every direction's loads and
+// halve the occupancy); the scale array follows the half data of the same rhs.
 template <>
 struct Store<DWF_F16S> {
   using real = float;
   static constexpr size_t bytes_per_spinor = 52;
   __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
-    const half8v* p = reinterpret_cast<const half8v*>(base) + h * 3 * Ls + s;
-    const float* sc = reinterpret_cast<const float*>(base + V4h * Ls * 48) + h * Ls + s;
-    float scale = *sc;
+    const half2v* p = reinterpret_cast<const half2v*>(base) + h * 12 * Ls + s;
+    const float scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      half8v t = p[(size_t)j * Ls];
-      v[4 * j + 0] = {(float)t[0] * scale, (float)t[1] * scale};
-      v[4 * j + 1] = {(float)t[2] * scale, (float)t[3] * scale};
-      v[4 * j + 2] = {(float)t[4] * scale, (float)t[5] * scale};
-      v[4 * j + 3] = {(float)t[6] * scale, (float)t[7] * scale};
+    for (int c = 0; c < 12; ++c) {
+      half2v t = p[(size_t)c * Ls];
+      v[c] = {(float)t.x * scale, (float)t.y * scale};
     }
   }
   __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    half8v* p = reinterpret_cast<half8v*>(base) + h * 3 * Ls + s;
-    float* sc = reinterpret_cast<float*>(base + V4h * Ls * 48) + h * Ls + s;
-    *sc = m;
-    const float d = (m > 0.f) ? m : 1.f;
+    half2v* p = reinterpret_cast<half2v*>(base) + h * 12 * Ls + s;
+    reinterpret_cast<float*>(base + V4h * Ls * 48)[h * Ls + s] = m;
+    const float r = 1.f / ((m > 0.f) ? m : 1.f);  // one correctly rounded division per spinor
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      half8v t;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        t[2 * k] = (_Float16)(v[4 * j + k].re / d);
-        t[2 * k + 1] = (_Float16)(v[4 * j + k].im / d);
-      }
-      p[(size_t)j * Ls] = t;
+    for (int c = 0; c < 12; ++c) {
+      half2v t;
+      t.x = (_Float16)(v[c].re * r);
+      t.y = (_Float16)(v[c].im * r);
+      p[(size_t)c * Ls] = t;
     }
   }
 };

@@ -121,21 +121,12 @@ __device__ __forceinline__ void load_half(const char* base, long long V4h, int L
       v[2 * j + 1] = {t.z, t.w};
     }
   } else {
-    // c0 = 0: groups 0 and 1 (components 0..3, 4..5); c0 = 6: groups 1 and 2 (6..7, 8..11)
-    const half8v* p = reinterpret_cast<const half8v*>(base) + h * 3 * Ls + s;
+    const half2v* p = reinterpret_cast<const half2v*>(base) + (h * 12 + c0) * Ls + s;
     const float scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
-    const half8v g0 = p[(size_t)(c0 == 0 ? 0 : 1) * Ls];
-    const half8v g1 = p[(size_t)(c0 == 0 ? 1 : 2) * Ls];
-    if (c0 == 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) v[k] = {(R)g0[2 * k] * scale, (R)g0[2 * k + 1] * scale};
-#pragma unroll
-      for (int k = 0; k < 2; ++k) v[4 + k] = {(R)g1[2 * k] * scale, (R)g1[2 * k + 1] * scale};
-    } else {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) v[k] = {(R)g0[4 + 2 * k] * scale, (R)g0[4 + 2 * k + 1] * scale};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) v[2 + k] = {(R)g1[2 * k] * scale, (R)g1[2 * k + 1] * scale};
+    for (int c = 0; c < 6; ++c) {
+      half2v t = p[(size_t)c * Ls];
+      v[c] = {(R)t.x * scale, (R)t.y * scale};
     }
   }
 }
@@ -185,7 +176,10 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return scratch[0];
 }
 
-template <int PREC, bool DAG, int EPI, int DEPTH>
+// MULTI: the workgroup loops over rpb right-hand sides (links staged once);
+// without it the body runs once, which keeps the loop-carried addresses out of
+// the register budget of the common single-rhs launches.
+template <int PREC, bool DAG, int EPI, int DEPTH, bool MULTI>
 __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
   using R = typename Store<PREC>::real;
   using V = typename LinkT<R>::vec;
@@ -221,8 +215,9 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
     }
   }
   const R alpha = (R)a.alpha;
-  for (int rr = 0; rr < a.rpb; ++rr) {
-    const int rhs = blockIdx.y * a.rpb + rr;
+  const int nrr = MULTI ? a.rpb : 1;
+  for (int rr = 0; rr < nrr; ++rr) {
+    const int rhs = blockIdx.y * nrr + rr;
     if (rhs >= a.nrhs) break;  // uniform across the workgroup
     const size_t off = (size_t)rhs * a.stride;
     const char* in = a.in + off;
@@ -401,7 +396,10 @@ static hipError_t launch_hop_t(const HopArgs& a, int nrhs, hipStream_t st) {
   dim3 grid(a.nb8 * 8, (nrhs + a.rpb - 1) / a.rpb);
   dim3 block(a.spb * a.Ls);
   const size_t lds = std::max(hop_lds(PREC, a.spb, a.Ls, EPI, a.partial != nullptr), (size_t)a.lds_floor);
-  hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH>), grid, block, lds, st, a);
+  if (a.rpb > 1)
+    hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH, true>), grid, block, lds, st, a);
+  else
+    hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH, false>), grid, block, lds, st, a);
   return hipGetLastError();
 }
 
