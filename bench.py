@@ -62,6 +62,65 @@ def hop_bytes_per_site(prec, Ls, nrhs=1):
     return 2 * S + link, 3 * S + link
 
 
+# hop launches of one FP64 CG iteration, as (kernel-name prefix, algorithmic spinor reads + writes):
+# M_pc p (pass 1: 2 S, pass 2 with p.Ap partials: 3 S), then M_pc^dag u with the residual update
+# fused into its second pass (reads t, u, r and writes r: 4 S); each pass also reads 8 L / Ls of links
+CG_ITERATION_HOPS = (
+    ("void dwf::hop_kernel<0, false, 1,", 2),
+    ("void dwf::hop_kernel<0, false, 2,", 3),
+    ("void dwf::hop_kernel<0, true, 1,", 2),
+    ("void dwf::hop_kernel<0, true, 4,", 4),
+)
+
+
+def cg_hop_bytes_per_launch(V5h, Ls):
+    """Algorithmic HBM bytes per hop launch, averaged over the four launches of a CG iteration."""
+    S, Lb = SPINOR_BYTES[0], LINK_BYTES[0]
+    per_site = sum(n for _, n in CG_ITERATION_HOPS) / len(CG_ITERATION_HOPS) * S + 8.0 * Lb / Ls
+    return V5h * per_site
+
+
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+    """HBM bytes per hop launch of a CG iteration from four rocprofv3 --pmc runs (FETCH_SIZE and
+    WRITE_SIZE of the rb_solve bench, and of the copy workload).  Each counter is scaled by the
+    factor that maps its reading on the copy kernel (copy_bytes read, copy_bytes written) onto
+    the known size; the result is the mean over the four launch kinds of a CG iteration."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def per_dispatch(d):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += list(csv.DictReader(open(f)))
+        acc = defaultdict(float)
+        names = {}
+        for r in rows:
+            acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            names[r["Dispatch_Id"]] = r["Kernel_Name"]
+        return [(names[k], v * 1024.0) for k, v in acc.items()]  # counters are KiB per dispatch
+
+    def copy_kib(d):
+        return max(v for _, v in per_dispatch(d))  # the 4 GiB copy dominates every other dispatch
+
+    f_scale = copy_bytes / copy_kib(copy_fetch_dir)
+    w_scale = copy_bytes / copy_kib(copy_write_dir)
+    fetch, write = per_dispatch(fetch_dir), per_dispatch(write_dir)
+    kinds = {}
+    for prefix, _ in CG_ITERATION_HOPS:
+        fv = [v for n, v in fetch if n.startswith(prefix)]
+        wv = [v for n, v in write if n.startswith(prefix)]
+        if not fv or not wv:
+            raise SystemExit(f"no dispatch of {prefix!r} in the counter runs")
+        kinds[prefix] = {
+            "fetch_bytes": f_scale * sum(fv) / len(fv),
+            "write_bytes": w_scale * sum(wv) / len(wv),
+            "dispatches": len(fv),
+        }
+    per_launch = sum(k["fetch_bytes"] + k["write_bytes"] for k in kinds.values()) / len(kinds)
+    return {"fetch_scale": f_scale, "write_scale": w_scale, "kinds": kinds, "bytes_per_launch": per_launch}
+
+
 def measured_traffic(key):
     """HBM bytes per hop launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in
     profiles/hop_traffic.json, or None when the hop kernel source changed since they were taken."""
@@ -177,7 +236,7 @@ def run_rb_solve(args):
     site_updates = sum(2 * V5 * it for it in iters_all)
     value = site_updates / dt
     b1, b2 = hop_bytes_per_site(0, Ls)
-    bytes_per_launch = V5h * (b1 + b2) / 2  # CG launches alternate pass 1 and pass 2
+    bytes_per_launch = cg_hop_bytes_per_launch(V5h, Ls)
     avg_ms = hop_ms / max(hop_launches, 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     out = {
@@ -212,7 +271,7 @@ def run_rb_solve(args):
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": measured_traffic("rb_solve"),
-            "kernel": "hop_kernel (all M_pc passes of the timed solves)",
+            "kernel": "hop_kernel (all passes of the timed solves; bytes = mean of a CG iteration's four)",
             "bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": avg_ms,
             "launches": hop_launches,
@@ -382,20 +441,26 @@ def run_mixed(args):
             src_op.close()
             del src_op
         x64 = torch.zeros_like(b64)
+        log(f"{name}: Chebyshev setup of {nvec} vectors")
         t_setup, _ = _setup_time(op, vecs, pristine, nvec, order, lo, hi, 1)
+        log(f"{name}: setup {t_setup:.3f} s")
         fb = op.field_bytes(1, dwf.DWF_F64)
         iters, res = [], []
 
         def solves():
             if prec == dwf.DWF_F64:
                 for k in range(2):
+                    log(f"{name}: solve {k} (one rhs)")
                     _, it, r = op.cg(b64[k * fb : (k + 1) * fb], x64[k * fb : (k + 1) * fb], 1, tol=1e-10, maxiter=100000)
                     iters.extend(it)
                     res.extend(r)
+                    log(f"{name}: solve {k} done, {it[0]} iterations")
             else:
+                log(f"{name}: two solves (batched)")
                 _, it, r = op.cg(b64, x64, 2, tol=1e-10, maxiter=100000)
                 iters.extend(it)
                 res.extend(r)
+                log(f"{name}: solves done, {list(it)} iterations")
 
         t_solve, _ = _timed(solves)
         results[name] = {
@@ -524,7 +589,24 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="sites per workgroup of the hop kernels (0 = autotune)")
     ap.add_argument("--depth", type=int, default=0, help="neighbour-load pipeline depth with --tile (0 = keep)")
     ap.add_argument("--order", type=int, default=0, help="site traversal order (0 lexicographic, 1 XCD octants)")
+    ap.add_argument(
+        "--traffic",
+        nargs=4,
+        metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+        help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this bench and of --workload copy "
+        "into profiles/hop_traffic.json (no GPU needed)",
+    )
     args = ap.parse_args()
+    if args.traffic:
+        import hashlib
+
+        rec = summarize_traffic(*args.traffic, copy_bytes=WORKLOADS["copy"]["bytes"])
+        rec["hop_source_sha256"] = hashlib.sha256(open(HOP_SOURCE, "rb").read()).hexdigest()
+        out = {"hop_source_sha256": rec.pop("hop_source_sha256"), "workloads": {"rb_solve": rec}}
+        with open(TRAFFIC_FILE, "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps(out, indent=1))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
             json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not built"}),

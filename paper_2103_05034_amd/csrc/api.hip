@@ -155,6 +155,34 @@ hipError_t mdagm_pap(dwf_context* c, int prec, const char* p, char* q, char* t, 
   return mpc_chunk(c, prec, u, q, t, n, 1);
 }
 
+// One FP64 CG operator step without writing A p: u = M_pc p with p.Ap = |u|^2
+// into S_PAP, alpha from it, then the last pass of M_pc^dag u updates
+// r -= alpha A p in place and leaves |r|^2 in S_RR.
+hipError_t cg_step_f64(dwf_context* c, const char* p, char* r, char* t, char* u, int n) {
+  hipError_t e = mpc_chunk(c, DWF_F64, p, u, t, n, 0, c->hop_partials);
+  if (e != hipSuccess) return e;
+  e = reduce_partials(c, c->hop_partials, hop_blocks(c), n, S_PAP);
+  if (e != hipSuccess) return e;
+  e = scal_alpha(c, n);
+  if (e != hipSuccess) return e;
+  HopArgs a{};
+  a.in = u;
+  a.out = t;
+  a.alpha = 1.0;
+  e = launch_hop(c, DWF_F64, a, DWF_ODD, 1, EPI_M5INV, n);
+  if (e != hipSuccess) return e;
+  HopArgs b{};
+  b.in = t;
+  b.x = u;
+  b.out = r;
+  b.alpha = -0.25;
+  b.partial = c->hop_partials;
+  b.scal = c->scalars;
+  e = launch_hop(c, DWF_F64, b, DWF_EVEN, 1, EPI_CGR, n);
+  if (e != hipSuccess) return e;
+  return reduce_partials(c, c->hop_partials, hop_blocks(c), n, S_RR);
+}
+
 hipError_t mdagm_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, char* u, int n) {
   hipError_t e = mpc_chunk(c, prec, in, u, t, n, 0);
   if (e != hipSuccess) return e;
@@ -457,9 +485,7 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
       for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
       if (!any) break;
     }
-    HIP_TRY(mdagm_pap(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
-    HIP_TRY(scal_alpha(h, nrhs));
-    HIP_TRY(cg_update_r(h, DWF_F64, r, DWF_F64, q, nrhs));
+    HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs));  // alpha, r -= alpha A p, |r|^2
     HIP_TRY(scal_beta(h, nrhs));
     HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, nrhs));
     HIP_TRY(scal_converge(h, nrhs, tol2, true));

@@ -71,12 +71,21 @@ __global__ void finalize_kernel(const double* __restrict__ partials, double* __r
   }
 }
 
-// out[rhs * ostride] = sum_k partials[rhs * count + k]
+// out[rhs * ostride] = sum_k partials[rhs * count + k].  Each thread keeps
+// eight independent sums (k = tid + j*BS mod 8*BS), so eight loads are in
+// flight instead of one dependent chain; the order is fixed by count alone.
 __global__ void sum_partials_kernel(const double* __restrict__ partials, int count, double* __restrict__ out,
                                     int ostride) {
   const int rhs = blockIdx.x;
-  double a = 0, b = 0;
-  for (int k = threadIdx.x; k < count; k += BS) a += partials[(size_t)rhs * count + k];
+  const double* p = partials + (size_t)rhs * count;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int k = threadIdx.x;
+  for (; k + 7 * BS < count; k += 8 * BS) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] += p[k + j * BS];
+  }
+  for (int j = 0; k < count; k += BS, ++j) acc[j] += p[k];
+  double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])), b = 0;
   block_reduce2(a, b);
   if (threadIdx.x == 0) out[(size_t)rhs * ostride] = a;
 }

@@ -234,6 +234,7 @@ enum Epilogue {
   EPI_M5INV = 1,  // out = M5D^{-1} [alpha * Dhop(in) + beta * x]  (x optional)
   EPI_M5 = 2,     // out = M5D x + alpha * Dhop(in)
   EPI_CHEB = 3,   // out = ca * (M5D x + alpha * Dhop(in)) + cb * y + cc * z (+ cw * w)
+  EPI_CGR = 4,    // q = M5D x + alpha * Dhop(in) kept in registers; out -= alpha_cg * q  (CG residual, FP64)
 };
 
 struct HopArgs {
@@ -259,6 +260,7 @@ struct HopArgs {
   int lds_floor;      // minimum dynamic LDS of the launch (occupancy cap), bytes
   int nrhs;           // right-hand sides of the launch
   int rpb;            // right-hand sides per workgroup (looped, sharing the LDS links)
+  const double* scal; // EPI_CGR: per-rhs solver scalars, alpha_cg = scal[rhs * NSCAL + S_ALPHA]
 };
 
 // ---------------------------------------------------------------------------

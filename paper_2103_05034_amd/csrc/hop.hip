@@ -63,16 +63,22 @@ __device__ __forceinline__ void hop_compute(const cplx<R> psi[12], const cplx<R>
   reconstruct<MU, SIGMA>(chi, acc);
 }
 
-// compute direction D from its buffer slot, then refill the slot with D + DEPTH
-template <int PREC, bool DAG, int D, int DEPTH>
+// Pipeline step K handles direction dir_at(K) = K (+x, -x, +y, ...): the +x and
+// -x neighbours of a wave's consecutive sites share most of their cache lines,
+// which then meet in L1.
+__host__ __device__ constexpr int dir_at(int k) { return k; }
+
+// compute the direction of step K from its buffer slot, then refill the slot
+// with the neighbour of step K + DEPTH
+template <int PREC, bool DAG, int K, int DEPTH>
 __device__ __forceinline__ void hop_pipeline(const char* in, long long V4h, int Ls, int s, const int nh[8],
                                              const cplx<typename Store<PREC>::real>* __restrict__ ll, int spb,
                                              int sl, cplx<typename Store<PREC>::real> (&buf)[DEPTH][12],
                                              cplx<typename Store<PREC>::real> acc[12]) {
-  if constexpr (D < 8) {
-    hop_compute<typename Store<PREC>::real, DAG, D>(buf[D % DEPTH], ll, spb, sl, acc);
-    if constexpr (D + DEPTH < 8) Store<PREC>::load(in, V4h, Ls, nh[D + DEPTH], s, buf[D % DEPTH]);
-    hop_pipeline<PREC, DAG, D + 1, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+  if constexpr (K < 8) {
+    hop_compute<typename Store<PREC>::real, DAG, dir_at(K)>(buf[K % DEPTH], ll, spb, sl, acc);
+    if constexpr (K + DEPTH < 8) Store<PREC>::load(in, V4h, Ls, nh[dir_at(K + DEPTH)], s, buf[K % DEPTH]);
+    hop_pipeline<PREC, DAG, K + 1, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
   }
 }
 
@@ -80,7 +86,7 @@ template <int PREC, int J, int DEPTH>
 __device__ __forceinline__ void hop_prologue(const char* in, long long V4h, int Ls, int s, const int nh[8],
                                              cplx<typename Store<PREC>::real> (&buf)[DEPTH][12]) {
   if constexpr (J < DEPTH) {
-    Store<PREC>::load(in, V4h, Ls, nh[J], s, buf[J]);
+    Store<PREC>::load(in, V4h, Ls, nh[dir_at(J)], s, buf[J]);
     hop_prologue<PREC, J + 1, DEPTH>(in, V4h, Ls, s, nh, buf);
   }
 }
@@ -187,7 +193,7 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
   const int Ls = a.Ls;
   const int spb = a.spb;
   cplx<R>* ll = reinterpret_cast<cplx<R>*>(smem_raw);  // links [72][spb], kept for all rhs of the workgroup
-  char* scratch = smem_raw + (size_t)spb * 72 * sizeof(cplx<R>);  // M5D^{-1} columns / reduction
+  char* scratch = smem_raw + (size_t)spb * 72 * sizeof(cplx<R>);  // M5D^{-1} columns, x, reduction
   const int b = blockIdx.x;
   const int logical = (b & 7) * a.nb8 + (b >> 3);
   if (logical >= a.nblocks) return;  // whole workgroup leaves together
@@ -256,18 +262,33 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
           for (int c = 0; c < 12; ++c) v[c] = col[(size_t)(sl * 12 + c) * LP + s];
         }
       }
-    } else {  // EPI_M5, EPI_CHEB
+    } else {  // EPI_M5, EPI_CHEB, EPI_CGR
+      // x(s) goes through LDS, [12][lanes], so that the s+-1 halves of M5D come
+      // from the neighbouring lanes of the same site instead of a second pass
+      // over cache lines whose fill may still be in flight
+      cplx<R>* xl = reinterpret_cast<cplx<R>*>(scratch);
+      const int nl = spb * Ls;
+      cplx<R> xs[12];
       if (valid) {
-        const char* x = a.x + off;
+        Store<PREC>::load(a.x + off, V4h, Ls, h, s, xs);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) xl[c * nl + tid] = xs[c];
+      }
+      __syncthreads();
+      if (valid) {
         const int s_lo = (s == 0) ? Ls - 1 : s - 1;
         const int s_hi = (s == Ls - 1) ? 0 : s + 1;
         const R m_lo = (s == 0) ? (R)a.mf : (R)-1;       // coupling to slice s-1
         const R m_hi = (s == Ls - 1) ? (R)a.mf : (R)-1;  // coupling to slice s+1
-        cplx<R> xs[12], up[6], lo[6];
-        Store<PREC>::load(x, V4h, Ls, h, s, xs);
         // M5D: P_+ from s-1, P_- from s+1; M5D^dag: P_+ from s+1, P_- from s-1
-        load_half<PREC>(x, V4h, Ls, h, DAG ? s_hi : s_lo, 0, up);
-        load_half<PREC>(x, V4h, Ls, h, DAG ? s_lo : s_hi, 6, lo);
+        const int t_up = sl * Ls + (DAG ? s_hi : s_lo);
+        const int t_lo = sl * Ls + (DAG ? s_lo : s_hi);
+        cplx<R> up[6], lo[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          up[c] = xl[c * nl + t_up];
+          lo[c] = xl[(6 + c) * nl + t_lo];
+        }
         m5d_combine<R>(xs, up, lo, DAG ? m_hi : m_lo, DAG ? m_lo : m_hi, (R)a.d, v);
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = {v[c].re + alpha * acc[c].re, v[c].im + alpha * acc[c].im};
@@ -290,8 +311,27 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
         }
       }
     }
-    if (valid) Store<PREC>::store(out, V4h, Ls, h, s, v);
-    if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64), for CG's p.Ap = |M_pc p|^2
+    if constexpr (EPI == EPI_CGR) {
+      // CG residual update with the operator output never written: r -= alpha q,
+      // r unchanged for a right-hand side that has stopped (alpha = 0); the
+      // partials below are then |r|^2
+      const double al = a.scal[(size_t)rhs * NSCAL + S_ALPHA];
+      if (valid) {
+        cplx<R> rv[12];
+        Store<PREC>::load(out, V4h, Ls, h, s, rv);
+        if (al != 0.0) {
+#pragma unroll
+          for (int c = 0; c < 12; ++c) rv[c] = {fma((R)-al, v[c].re, rv[c].re), fma((R)-al, v[c].im, rv[c].im)};
+          Store<PREC>::store(out, V4h, Ls, h, s, rv);
+        }
+#pragma unroll
+        for (int c = 0; c < 12; ++c) v[c] = rv[c];
+      }
+    } else {
+      if (valid) Store<PREC>::store(out, V4h, Ls, h, s, v);
+    }
+    if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64): p.Ap = |M_pc p|^2, or CG's |r|^2
+      if (EPI != EPI_LIN && EPI != EPI_M5INV) __syncthreads();  // scratch still holds x
       double n2 = 0;
       if (valid) {
 #pragma unroll
@@ -360,10 +400,12 @@ __global__ void __launch_bounds__(256) site5_kernel(HopArgs a) {
 static size_t cplx_bytes(int prec) { return prec == DWF_F64 ? 16 : 8; }
 
 // LDS bytes of a hop launch: the link copy (kept for all rhs of a workgroup)
-// followed by a scratch region for the M5D^{-1} columns or the reduction
+// followed by a scratch region for the M5D^{-1} columns, the x copy of the
+// M5D epilogue, or the reduction
 static size_t hop_lds(int prec, int spb, int Ls, int epi, bool reduce) {
   size_t scratch = 0;
   if (epi == EPI_M5INV) scratch = (size_t)spb * 12 * (Ls + 1) * cplx_bytes(prec);
+  if (epi == EPI_M5 || epi == EPI_CHEB || epi == EPI_CGR) scratch = (size_t)spb * 12 * Ls * cplx_bytes(prec);
   if (reduce) scratch = std::max(scratch, (size_t)256 * sizeof(double));
   return (size_t)spb * 72 * cplx_bytes(prec) + scratch;
 }
@@ -423,6 +465,9 @@ static hipError_t launch_hop_p(const HopArgs& a, int dag, int epi, int depth, in
     case EPI_M5 * 2 + 1: return launch_hop_d<PREC, true, EPI_M5>(a, depth, nrhs, st);
     case EPI_CHEB * 2 + 0: return launch_hop_d<PREC, false, EPI_CHEB>(a, depth, nrhs, st);
     case EPI_CHEB * 2 + 1: return launch_hop_d<PREC, true, EPI_CHEB>(a, depth, nrhs, st);
+    case EPI_CGR * 2 + 1:
+      if constexpr (PREC == DWF_F64) return launch_hop_d<PREC, true, EPI_CGR>(a, depth, nrhs, st);
+      break;
   }
   return hipErrorInvalidValue;
 }
