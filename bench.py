@@ -413,9 +413,13 @@ def run_batched(args):
 
 
 def run_mixed(args):
-    """Chebyshev setup of 24 vectors + 2 CG solves to 1e-10 at near-physical mass:
-    FP16 + per-site scale storage (FP32 arithmetic, FP64 reliable updates, batched)
-    against plain FP64 (one rhs at a time)."""
+    """Chebyshev setup of 24 vectors + 2 CG solves to 1e-10 at near-physical mass.
+
+    Mixed: the setup runs on FP16 + per-site-scale fields (FP32 arithmetic, batched, FP64
+    Gram-Schmidt); the solves run on FP32 fields with FP64 reliable updates, both rhs batched.
+    Plain: the same work in FP64, one vector / rhs at a time.  A CG whose inner fields are also
+    FP16 is attempted with a bounded iteration count and reported: at this conditioning the FP16
+    rounding of the operator's intermediate fields exceeds the residual it has to resolve."""
     import torch
 
     import paper_2103_05034_amd as dwf
@@ -425,74 +429,102 @@ def run_mixed(args):
     dims, Ls, nvec = cfg["dims"], cfg["Ls"], cfg["nvec"]
     order, lo, hi = cfg["order"], cfg["lo"], cfg["hi"]
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
-    results = {}
-    for name, prec, nb in (("mixed_f16s", dwf.DWF_F16S, nvec), ("plain_f64", dwf.DWF_F64, 1)):
-        op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=prec, max_nrhs=nb, max_cg_rhs=2 if prec else 1)
+
+    def make(prec, nb, ncg):
+        return dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=prec, max_nrhs=nb, max_cg_rhs=ncg)
+
+    # two Gaussian sources, FP64 packed
+    src = make(dwf.DWF_F64, 1, 0)
+    b64 = torch.zeros(2 * src.field_bytes(1, dwf.DWF_F64), dtype=torch.uint8, device="cuda")
+    _fill_gaussian(src, b64, 2, dims, Ls, seed=5, chunk=1)
+    fb = src.field_bytes(1, dwf.DWF_F64)
+    src.close()
+    del src
+
+    def setup(prec, nb):
+        op = make(prec, nb, 0)
         spb, depth, _ = op.autotune(min(nb, 8), 2)
         vecs = op.new_field(nvec)
         _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
         pristine = vecs.clone()
-        # two Gaussian sources, FP64 packed
-        opb = op if prec == dwf.DWF_F64 else None
-        b64 = torch.zeros(2 * op.field_bytes(1, dwf.DWF_F64), dtype=torch.uint8, device="cuda")
-        src_op = op if prec == dwf.DWF_F64 else dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=0)
-        _fill_gaussian(src_op, b64, 2, dims, Ls, seed=5, chunk=1)
-        if src_op is not op:
-            src_op.close()
-            del src_op
-        x64 = torch.zeros_like(b64)
-        log(f"{name}: Chebyshev setup of {nvec} vectors")
-        t_setup, _ = _setup_time(op, vecs, pristine, nvec, order, lo, hi, 1)
-        log(f"{name}: setup {t_setup:.3f} s")
-        fb = op.field_bytes(1, dwf.DWF_F64)
-        iters, res = [], []
+        log(f"setup prec={prec}: Chebyshev filter of {nvec} vectors (tile {spb}x{depth})")
+        t, _ = _setup_time(op, vecs, pristine, nvec, order, lo, hi, 1)
+        log(f"setup prec={prec}: {t:.3f} s")
+        op.close()
+        del op, vecs, pristine
+        torch.cuda.empty_cache()
+        return t, [spb, depth]
 
-        def solves():
-            if prec == dwf.DWF_F64:
-                for k in range(2):
-                    log(f"{name}: solve {k} (one rhs)")
-                    _, it, r = op.cg(b64[k * fb : (k + 1) * fb], x64[k * fb : (k + 1) * fb], 1, tol=1e-10, maxiter=100000)
-                    iters.extend(it)
-                    res.extend(r)
-                    log(f"{name}: solve {k} done, {it[0]} iterations")
-            else:
-                log(f"{name}: two solves (batched)")
-                _, it, r = op.cg(b64, x64, 2, tol=1e-10, maxiter=100000)
+    def solve(prec, batched, maxiter=100000, tag=""):
+        op = make(prec, 2 if batched else 1, 2 if batched else 1)
+        op.autotune(2 if batched else 1, 2)
+        x64 = torch.zeros_like(b64)
+        iters, res, codes = [], [], []
+        op.set_progress(lambda it, rel: log(f"{tag} it={it} rel={max(rel):.2e}") and False, every=500)
+
+        def run():
+            chunks = [(0, 2)] if batched else [(0, 1), (1, 2)]
+            for k0, k1 in chunks:
+                code, it, r = op.cg(b64[k0 * fb : k1 * fb], x64[k0 * fb : k1 * fb], k1 - k0, tol=1e-10,
+                                    maxiter=maxiter, allow_noconv=True)
+                codes.append(code)
                 iters.extend(it)
                 res.extend(r)
-                log(f"{name}: solves done, {list(it)} iterations")
 
-        t_solve, _ = _timed(solves)
-        results[name] = {
-            "setup_s": t_setup,
-            "solve_s": t_solve,
-            "total_s": t_setup + t_solve,
-            "cg_iterations": iters,
-            "true_rel_residual": res,
-            "tile": [spb, depth],
-        }
-        log(f"{name}: setup {t_setup:.3f} s, 2 solves {t_solve:.3f} s, iterations {iters}, residuals {res}")
+        t, _ = _timed(run)
+        log(f"{tag}: {t:.3f} s, iterations {iters}, residuals {res}, status {codes}")
         op.close()
-        del op, vecs, pristine, b64, x64
+        del op, x64
         torch.cuda.empty_cache()
-    speed = results["plain_f64"]["total_s"] / results["mixed_f16s"]["total_s"]
+        return t, iters, res, codes
+
+    t_set_mixed, tile_mixed = setup(dwf.DWF_F16S, nvec)
+    t_sol_mixed, it_mixed, res_mixed, codes_mixed = solve(dwf.DWF_F32, True, tag="FP32-field CG")
+    t_set_plain, tile_plain = setup(dwf.DWF_F64, 1)
+    t_sol_plain, it_plain, res_plain, codes_plain = solve(dwf.DWF_F64, False, tag="FP64 CG")
+    cap = 2 * max(it_plain)
+    t_f16, it_f16, res_f16, codes_f16 = solve(dwf.DWF_F16S, True, maxiter=cap, tag="FP16-field CG")
+    if any(codes_mixed) or any(codes_plain):
+        raise SystemExit(f"a solve did not converge: mixed {codes_mixed}, plain {codes_plain}")
+    total_mixed = t_set_mixed + t_sol_mixed
+    total_plain = t_set_plain + t_sol_plain
     return {
         "metric": METRIC,
-        "value": speed,
-        "unit": "x (plain FP64 time / mixed FP16+scale time), setup of 24 vectors + 2 CG solves to 1e-10",
+        "value": total_plain / total_mixed,
+        "unit": "x (plain FP64 time / mixed time), setup of 24 vectors + 2 CG solves to 1e-10",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 0,
-        "ms_per_step": results["mixed_f16s"]["total_s"] * 1e3,
+        "ms_per_step": total_mixed * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16+scale storage, f32 arithmetic, f64 reliable updates",
+        "dtype": "setup: f16+scale storage, f32 arithmetic; solves: f32 fields, f64 reliable updates",
         "data": "synthetic",
         "config": {
             "workload": "24^3x48 Ls=24 M5=1.8 mf=0.00078 links exp(0.15iH): Chebyshev setup of 24 vectors "
             "(order 32 [0.05,60]) + FP64 Gram-Schmidt + 2 CG solves to 1e-10",
-            **results,
+            "mixed": {
+                "setup_s": t_set_mixed,
+                "setup_tile": tile_mixed,
+                "solve_s": t_sol_mixed,
+                "cg_iterations": it_mixed,
+                "true_rel_residual": res_mixed,
+            },
+            "plain_f64": {
+                "setup_s": t_set_plain,
+                "setup_tile": tile_plain,
+                "solve_s": t_sol_plain,
+                "cg_iterations": it_plain,
+                "true_rel_residual": res_plain,
+            },
+            "fp16_field_cg_attempt": {
+                "maxiter": cap,
+                "solve_s": t_f16,
+                "cg_iterations": it_f16,
+                "true_rel_residual": res_f16,
+                "converged": not any(codes_f16),
+            },
         },
     }
 

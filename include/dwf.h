@@ -127,12 +127,28 @@ int dwf_mpcdagmpc(dwf_handle h, const void* in_e, void* out_e, int nrhs);
  * handle precision; x holds the initial guess on entry.  With a DWF_F64
  * handle every step is FP64; with DWF_F32 / DWF_F16S the iteration runs on
  * low-precision fields with FP64 dot products and FP64 reliable updates
- * r = b - A x whenever |r| falls by 10x since the last update.  Stops when
- * every ||r|| / ||b|| < tol; iters[nrhs] and true_rel_resid[nrhs] are host
- * arrays (either may be NULL) receiving iterations and ||b - A x|| / ||b||
- * in FP64.  Returns DWF_ENOCONV after maxiter, DWF_EBREAKDOWN on NaN. */
+ * r = b - A x whenever |r| falls below a tenth of its largest value since
+ * the last update, after which p is re-orthogonalised against the new r.
+ * Stops when every ||r|| / ||b|| < tol; iters[nrhs] and true_rel_resid[nrhs]
+ * are host arrays (either may be NULL) receiving iterations and
+ * ||b - A x|| / ||b|| in FP64.  Returns DWF_ENOCONV after maxiter, or early
+ * when a low-precision solve stagnates (the true ||r|| has not halved over
+ * 12 consecutive reliable updates for every active rhs: the low-precision
+ * operator is too coarse for the conditioning), DWF_EBREAKDOWN on NaN. */
 int dwf_cg(dwf_handle h, const void* b, void* x, int nrhs, double tol, int maxiter, int* iters,
            double* true_rel_resid);
+
+/* Progress of the synchronous solvers (dwf_cg, dwf_solve_rb): fn is called on
+ * the calling thread after iteration `iteration` with the recursive
+ * ||r|| / ||b|| of each of the nrhs right-hand sides (a host array valid for
+ * the call only), at least `every` iterations apart (rounded up to the
+ * solver's host read-back period: 8 iterations in FP64, 1 in mixed
+ * precision).  A nonzero return stops the solve: x keeps the current
+ * iterate, iters and the true residuals are filled in, and the solver
+ * returns DWF_ENOCONV.  fn = NULL turns reporting off; `user` is passed
+ * through untouched.  This is a reporting hook, not part of the method. */
+typedef int (*dwf_progress_fn)(void* user, int iteration, int nrhs, const double* rel_resid);
+int dwf_set_progress(dwf_handle h, dwf_progress_fn fn, void* user, int every);
 
 /* SYNCHRONOUS.  Red-black solve of D_DW psi = eta (FP64, packed "both"
  * layout, nrhs = 1): eta' = eta_e - M_eo M5D^{-1} eta_o, CG on

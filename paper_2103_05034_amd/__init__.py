@@ -51,6 +51,8 @@ _c_dbl_p = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
+# int (*)(void* user, int iteration, int nrhs, const double* rel_resid)
+PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double))
 
 # name -> (restype, argtypes); mirrors include/dwf.h
 _PROTOS = {
@@ -80,6 +82,7 @@ _PROTOS = {
     "dwf_set_tile": (_i, [_vp, _i, _i, _i]),
     "dwf_set_order": (_i, [_vp, _i]),
     "dwf_set_occupancy": (_i, [_vp, _i]),
+    "dwf_set_progress": (_i, [_vp, PROGRESS_FN, _vp, _i]),
     "dwf_autotune": (_i, [_vp, _i, _i, _c_int_p, _c_int_p, _c_int_p, _c_dbl_p]),
     "dwf_enable_timing": (_i, [_vp, _i]),
     "dwf_kernel_time": (_i, [_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong)]),
@@ -337,6 +340,24 @@ class Operator:
         )
         self.tile = (spb.value, depth.value, rpb.value)
         return spb.value, depth.value, ms.value
+
+    def set_progress(self, fn=None, every=100):
+        """Report solver progress: fn(iteration, [rel_resid per rhs]) is called from dwf_cg /
+        dwf_solve_rb at least `every` iterations apart; a truthy return stops the solve
+        (the solver then returns DWF_ENOCONV).  fn=None turns reporting off."""
+        if fn is None:
+            self._progress_cb = None
+            _check(self.lib.dwf_set_progress(self.h, PROGRESS_FN(), None, 0))
+            return
+
+        def tramp(_user, it, n, rel):
+            try:
+                return 1 if fn(int(it), [rel[k] for k in range(n)]) else 0
+            except Exception:  # an exception cannot cross the C frame: stop the solve instead
+                return 1
+
+        self._progress_cb = PROGRESS_FN(tramp)  # kept alive while registered
+        _check(self.lib.dwf_set_progress(self.h, self._progress_cb, None, int(every)))
 
     def enable_timing(self, on=True):
         _check(self.lib.dwf_enable_timing(self.h, int(on)))

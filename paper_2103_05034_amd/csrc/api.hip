@@ -441,7 +441,7 @@ int dwf_mpcdagmpc(dwf_handle h, const void* in_e, void* out_e, int nrhs) {
 // CG
 // ---------------------------------------------------------------------------
 static int finish_cg(dwf_handle h, int nrhs, int maxiter, int* iters, double* resid, const std::vector<double>& sc,
-                     const std::vector<double>& tr) {
+                     const std::vector<double>& tr, bool stopped = false) {
   bool nconv = false, brk = false;
   for (int r = 0; r < nrhs; ++r) {
     const double* s = &sc[(size_t)r * NSCAL];
@@ -453,8 +453,22 @@ static int finish_cg(dwf_handle h, int nrhs, int maxiter, int* iters, double* re
     if (s[S_ACTIVE] != 0.0) nconv = true;
   }
   if (brk) return fail(DWF_EBREAKDOWN, "CG breakdown (non-finite or non-positive curvature)");
+  if (nconv && stopped) return fail(DWF_ENOCONV, "CG stopped by the progress callback");
   if (nconv) return fail(DWF_ENOCONV, "CG did not converge in %d iterations", maxiter);
   return DWF_OK;
+}
+
+// Report progress to the caller's hook (if any) after iteration `it`, at most
+// once per progress_every iterations; returns true when the hook asks to stop.
+static bool report_progress(dwf_handle h, int it, int nrhs, const std::vector<double>& sc, int& last) {
+  if (!h->progress_fn || it - last < h->progress_every) return false;
+  last = it;
+  std::vector<double> rel(nrhs);
+  for (int rr = 0; rr < nrhs; ++rr) {
+    const double* s = &sc[(size_t)rr * NSCAL];
+    rel[rr] = s[S_BB] > 0 ? std::sqrt(s[S_RR] / s[S_BB]) : 0.0;
+  }
+  return h->progress_fn(h->progress_user, it, nrhs, rel.data()) != 0;
 }
 
 // r = b - A x in FP64 and |r|^2 -> slot, using FP64 temporaries
@@ -478,12 +492,18 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
   HIP_TRY(scal_converge(h, nrhs, tol2, false));
   std::vector<double> sc;
   const int check = 8;
+  bool stopped = false;
+  int last = 0;
   for (int it = 0; it < maxiter; ++it) {
     if (it % check == 0) {
       if (int rc = read_scalars(h, nrhs, sc)) return rc;
       bool any = false;
       for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
       if (!any) break;
+      if (it > 0 && report_progress(h, it, nrhs, sc, last)) {
+        stopped = true;
+        break;
+      }
     }
     HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs));  // alpha, r -= alpha A p, |r|^2
     HIP_TRY(scal_beta(h, nrhs));
@@ -495,7 +515,7 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
   if (int rc = read_scalars(h, nrhs, sc)) return rc;
   std::vector<double> tr(nrhs);
   for (int rr = 0; rr < nrhs; ++rr) tr[rr] = sc[(size_t)rr * NSCAL + S_TRUE];
-  return finish_cg(h, nrhs, maxiter, iters, resid, sc, tr);
+  return finish_cg(h, nrhs, maxiter, iters, resid, sc, tr, stopped);
 }
 
 // Low-precision CG with FP64 reliable updates.
@@ -503,11 +523,10 @@ static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, 
                     double* resid) {
   const int P = h->prec;
   const double tol2 = tol * tol;
-  const double delta2 = 0.01;  // reliable update when |r| drops 10x
+  const double delta2 = 0.01;  // reliable update when |r| falls 10x below its largest value since the last one
   char* r64 = h->r64;
   HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
   HIP_TRY(blas_dot(h, DWF_F64, b, DWF_F64, b, nrhs, S_BB, false));
-  HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
   HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
   HIP_TRY(blas_copy(h, DWF_F64, r64, DWF_F32, h->lo_r, nrhs));
   HIP_TRY(blas_copy(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
@@ -518,11 +537,30 @@ static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, 
   HIP_TRY(scal_converge(h, nrhs, tol2, false));
   std::vector<double> sc;
   if (int rc = read_scalars(h, nrhs, sc)) return rc;
+  std::vector<double> rrmax(nrhs);  // largest iterated |r|^2 since the last reliable update
+  for (int rr = 0; rr < nrhs; ++rr) rrmax[rr] = sc[(size_t)rr * NSCAL + S_RR];
+  // Stagnation: when the low-precision operator's error on the lowest modes
+  // exceeds the reduction an update cycle asks for, the true residual stops
+  // falling while the iterated one keeps going.  A rhs whose true |r| has
+  // not halved over `patience` consecutive update cycles (updates asked for
+  // by a tenfold fall of the iterated |r|, not the final tolerance checks)
+  // is stagnant; the solve stops once every active rhs is.
+  const int patience = 12;
+  std::vector<double> best(rrmax);
+  std::vector<int> idle(nrhs, 0);
+  std::vector<char> cycle(nrhs, 0);
+  bool stagnant = false;
   bool pending = false;  // lo_x holds an update not yet folded into x
+  bool stopped = false;
+  int last = 0;
   for (int it = 0; it < maxiter; ++it) {
     bool any = false;
     for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
     if (!any) break;
+    if (it > 0 && report_progress(h, it, nrhs, sc, last)) {
+      stopped = true;
+      break;
+    }
     HIP_TRY(mdagm_pap(h, P, h->lo_p, h->lo_q, h->t_buf, h->u_buf, nrhs));
     HIP_TRY(scal_alpha(h, nrhs));
     HIP_TRY(cg_update_xr(h, DWF_F32, h->lo_x, DWF_F32, h->lo_r, P, h->lo_p, P, h->lo_q, nrhs));
@@ -531,23 +569,45 @@ static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, 
     bool update = false;
     for (int rr = 0; rr < nrhs; ++rr) {
       const double* s = &sc[(size_t)rr * NSCAL];
+      cycle[rr] = 0;
       if (s[S_ACTIVE] == 0.0) continue;
-      if (s[S_RR] < delta2 * s[S_RRMAX] || s[S_RR] < tol2 * s[S_BB] || !std::isfinite(s[S_RR])) update = true;
+      rrmax[rr] = std::max(rrmax[rr], s[S_RR]);
+      cycle[rr] = s[S_RR] < delta2 * rrmax[rr];
+      if (cycle[rr] || s[S_RR] < tol2 * s[S_BB] || !std::isfinite(s[S_RR])) update = true;
     }
     if (update) {
       HIP_TRY(blas_axpby(h, DWF_F32, h->lo_x, DWF_F64, x, nrhs, 1.0, 1.0, -1, -1, 1));
       HIP_TRY(blas_zero(h, DWF_F32, h->lo_x, nrhs));
       pending = false;
       HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
-      HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
       HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
       HIP_TRY(blas_copy(h, DWF_F64, r64, DWF_F32, h->lo_r, nrhs));
+      // r^dag p against the new residual, removed from p in the update below
+      HIP_TRY(blas_dot(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs, S_TMP, true));
     }
     HIP_TRY(scal_beta(h, nrhs));
-    HIP_TRY(cg_update_p(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+    HIP_TRY(cg_update_p(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs, update));
     HIP_TRY(scal_converge(h, nrhs, tol2, true, update ? 1 : 0));
     if (update) {
       if (int rc = read_scalars(h, nrhs, sc)) return rc;
+      bool all_stuck = true, any_active = false;
+      for (int rr = 0; rr < nrhs; ++rr) {
+        const double* s = &sc[(size_t)rr * NSCAL];
+        rrmax[rr] = s[S_RR];
+        if (s[S_ACTIVE] == 0.0) continue;
+        any_active = true;
+        if (s[S_RR] < 0.25 * best[rr]) {
+          best[rr] = s[S_RR];
+          idle[rr] = 0;
+        } else if (cycle[rr]) {
+          ++idle[rr];
+        }
+        if (idle[rr] < patience) all_stuck = false;
+      }
+      if (any_active && all_stuck) {
+        stagnant = true;
+        break;
+      }
     }
   }
   if (pending) {
@@ -557,7 +617,12 @@ static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, 
   if (int rc = read_scalars(h, nrhs, sc)) return rc;
   std::vector<double> tr(nrhs);
   for (int rr = 0; rr < nrhs; ++rr) tr[rr] = sc[(size_t)rr * NSCAL + S_TRUE];
-  return finish_cg(h, nrhs, maxiter, iters, resid, sc, tr);
+  const int rc = finish_cg(h, nrhs, maxiter, iters, resid, sc, tr, stopped);
+  if (rc == DWF_ENOCONV && stagnant)
+    return fail(DWF_ENOCONV,
+                "mixed-precision CG stagnated: the true residual stopped falling (the low-precision operator is "
+                "too coarse for this conditioning; use a higher handle precision)");
+  return rc;
 }
 
 int dwf_cg(dwf_handle h, const void* b, void* x, int nrhs, double tol, int maxiter, int* iters,
@@ -871,6 +936,15 @@ int dwf_set_order(dwf_handle h, int mode) {
   HIP_TRY(hipMemcpyAsync(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->order_mode = mode;
+  return DWF_OK;
+}
+
+int dwf_set_progress(dwf_handle h, dwf_progress_fn fn, void* user, int every) {
+  if (int r = check_h(h)) return r;
+  if (fn && every < 1) return fail(DWF_EINVAL, "dwf_set_progress: every must be >= 1");
+  h->progress_fn = fn;
+  h->progress_user = user;
+  h->progress_every = fn ? every : 0;
   return DWF_OK;
 }
 

@@ -226,20 +226,29 @@ __global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __rest
   vstore<PP>(p + rhs * sp, g, i, vr);
 }
 
-// p = r + beta p
+// p = r + beta p.  With orth (right after a reliable update replaced r by the
+// true residual), p first loses its component along the new r,
+// p <- p - (r^dag p / |r|^2) r, so that p = (1 - beta c) r + beta p with
+// c = r^dag p / |r|^2 taken from scal[S_TMP], scal[S_TMPI] and scal[S_RR].
 template <int PR, int PP>
 __global__ void cg_p_kernel(VecGeom g, const char* __restrict__ r, char* __restrict__ p, size_t sr, size_t sp,
-                            const double* __restrict__ scal) {
+                            const double* __restrict__ scal, int orth) {
   const int rhs = blockIdx.y;
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i >= g.n) return;
-  const double beta = scal[rhs * NSCAL + S_BETA];
+  const double* s = scal + rhs * NSCAL;
+  const double beta = s[S_BETA];
+  cplx<double> ar = {1.0, 0.0};
+  if (orth && beta != 0.0 && s[S_RR] > 0.0) ar = {1.0 - beta * s[S_TMP] / s[S_RR], -beta * s[S_TMPI] / s[S_RR]};
   cplx<double> vr[12], vp[12];
   vload<PR>(r + rhs * sr, g, i, vr);
   if (beta != 0.0) {
     vload<PP>(p + rhs * sp, g, i, vp);
 #pragma unroll
-    for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
+    for (int c = 0; c < 12; ++c) {
+      const cplx<double> t = {ar.re * vr[c].re - ar.im * vr[c].im, ar.re * vr[c].im + ar.im * vr[c].re};
+      vr[c] = {fma(beta, vp[c].re, t.re), fma(beta, vp[c].im, t.im)};
+    }
   }
   vstore<PP>(p + rhs * sp, g, i, vr);
 }
@@ -439,19 +448,19 @@ hipError_t cg_update_xr(dwf_context* ctx, int px, char* x, int pr, char* r, int 
 }
 
 template <int PR, int PP>
-static void p_l(dwf_context* ctx, VecGeom g, const char* r, char* p, int nrhs) {
+static void p_l(dwf_context* ctx, VecGeom g, const char* r, char* p, int nrhs, int orth) {
   hipLaunchKernelGGL((cg_p_kernel<PR, PP>), dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, r, p,
-                     field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP), ctx->scalars);
+                     field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP), ctx->scalars, orth);
 }
 
-hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs) {
+hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs, bool orth) {
   VecGeom g = vgeom(ctx);
   if (pr == DWF_F64 && pp == DWF_F64)
-    p_l<DWF_F64, DWF_F64>(ctx, g, r, p, nrhs);
+    p_l<DWF_F64, DWF_F64>(ctx, g, r, p, nrhs, orth);
   else if (pr == DWF_F32 && pp == DWF_F32)
-    p_l<DWF_F32, DWF_F32>(ctx, g, r, p, nrhs);
+    p_l<DWF_F32, DWF_F32>(ctx, g, r, p, nrhs, orth);
   else if (pr == DWF_F32 && pp == DWF_F16S)
-    p_l<DWF_F32, DWF_F16S>(ctx, g, r, p, nrhs);
+    p_l<DWF_F32, DWF_F16S>(ctx, g, r, p, nrhs, orth);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

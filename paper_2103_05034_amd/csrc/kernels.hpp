@@ -36,7 +36,7 @@ enum Slot {
   S_BETA = 4,
   S_BB = 5,
   S_ACTIVE = 6,  // 1 while the rhs iterates, 0 once converged
-  S_RRMAX = 7,   // |r|^2 at the last reliable update
+  S_RRMAX = 7,   // unused
   S_TMP = 8,     // scratch dot result (re)
   S_TMPI = 9,    // scratch dot result (im)
   S_TRUE = 10,   // true |r|^2
@@ -60,7 +60,8 @@ hipError_t blas_zero(dwf_context* ctx, int prec, char* out, int nrhs);
 hipError_t cg_update_xr(dwf_context* ctx, int px, char* x, int pr, char* r, int pp, const char* p, int pq,
                         const char* q, int nrhs);
 // p = r + beta p
-hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs);
+hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p, int nrhs,
+                       bool orth = false);  // orth: remove p's component along r first
 // r -= alpha q with |r|^2 -> S_RR ; then x += alpha p and p = r + beta p in one pass (old p)
 hipError_t cg_update_r(dwf_context* ctx, int pr, char* r, int pq, const char* q, int nrhs);
 hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r, int pp, char* p, int nrhs);

@@ -91,4 +91,5 @@ def test_calls_on_null_handle_fail_cleanly(lib):
 
     assert lib.dwf_mpc(None, None, None, 1, 0) == dwf.DWF_EINVAL
     assert "null handle" in dwf.last_error()
+    assert lib.dwf_set_progress(None, dwf.PROGRESS_FN(), None, 0) == dwf.DWF_EINVAL
     assert lib.dwf_destroy(None) == dwf.DWF_OK

@@ -188,3 +188,50 @@ def test_chebyshev_smoother(prec, tol, nrhs):
     mdag = lambda v: L.mpc_dag(U, v, M5, MF)
     exp = np.stack([krylov.chebyshev_smoother(oracle_A(U), mdag, v, 0.5, 60.0, 12) for v in vals])
     assert rel_per_rhs(got, exp) < tol
+
+
+@pytest.mark.parametrize("prec", [F64, F16S])
+def test_cg_progress_reports_and_stops(prec):
+    import paper_2103_05034_amd as dwf
+
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=prec)
+    op64 = op if prec == F64 else make_operator(dims, Ls, seed=0, prec=F64)[0]
+    b = pack(op64, even_fields(dims, Ls, 1, seed=31), EVEN)
+    seen = []
+    op.set_progress(lambda it, rel: seen.append((it, rel[0])) and False, every=16)
+    x = op.new_field(1, prec=F64)
+    code, iters, res = op.cg(b, x, 1, tol=1e-10, maxiter=20000)
+    assert code == 0 and res[0] < 1.5e-10
+    assert len(seen) >= 2
+    its = [s[0] for s in seen]
+    assert all(b2 - b1 >= 16 for b1, b2 in zip(its, its[1:])) and its[-1] <= iters[0]
+    assert seen[0][1] > 1e-10 and all(np.isfinite(r) for _, r in seen)
+    # a nonzero return stops the solve with x holding the current iterate
+    op.set_progress(lambda it, rel: it >= 40, every=8)
+    x = op.new_field(1, prec=F64)
+    code, iters, res = op.cg(b, x, 1, tol=1e-10, maxiter=20000, allow_noconv=True)
+    assert code == dwf.DWF_ENOCONV and "progress" in dwf.last_error()
+    assert 40 <= iters[0] <= 48 and 1e-10 < res[0] < 1.0
+    op.set_progress(None)
+    code, iters, res = op.cg(b, x, 1, tol=1e-10, maxiter=20000)  # resumes from the stopped iterate
+    assert code == 0 and res[0] < 1.5e-10
+
+
+@pytest.mark.parametrize("dims,Ls,prec,slack", [((16, 16, 16, 32), 16, F32, 1.3), ((8, 8, 8, 16), 12, F16S, 4.0)])
+def test_mixed_cg_near_physical_mass(dims, Ls, prec, slack):
+    """mf = 0.00078, links exp(0.15 iH): FP32 fields with FP64 reliable updates need about the FP64
+    iteration count (re-orthogonalising p after each update keeps the recursion conjugate); FP16
+    fields still converge on the smaller lattice.  Both reach the FP64 true residual."""
+    mf = 0.00078
+    U = synth.gauge_links(dims, eps=0.15, seed=0)
+    op64, _ = make_operator(dims, Ls, prec=F64, mf=mf, U=U, max_nrhs=1, max_cg_rhs=1)
+    b = op64.pack(__import__("torch").from_numpy(synth.gaussian_fermion_batch(dims, Ls, 1, 5)).cuda(), EVEN)
+    x = op64.new_field(1)
+    code, it64, res64 = op64.cg(b, x, 1, tol=1e-10, maxiter=5000)
+    assert code == 0 and res64[0] < 1.5e-10
+    op, _ = make_operator(dims, Ls, prec=prec, mf=mf, U=U, max_nrhs=1, max_cg_rhs=1)
+    x = op.new_field(1, prec=F64)
+    code, it, res = op.cg(b, x, 1, tol=1e-10, maxiter=int(slack * it64[0]) + 50)
+    assert code == 0 and res[0] < 1.5e-10
+    assert it[0] <= slack * it64[0]
