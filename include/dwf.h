@@ -189,6 +189,53 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
  * diagonal) is written to host memory R_host if non-NULL. */
 int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
 
+/* ---- coarse-space transfer ------------------------------------------------ */
+
+/* Blocks of the two-level method (Two level preconditioner section: the
+ * blocked basis phi_k^b is phi_k restricted to block b): 4D boxes of
+ * block[0..3] = bx, by, bz, bt sites tiling the lattice, each with all Ls
+ * slices (the Algorithm A / B table uses 4x2x4x2 and 2^4 at Ls = 16).  Every
+ * extent must divide the lattice extent, the block must hold equally many
+ * even and odd sites, and (even sites per block) x Ls <= 512.  Blocks are
+ * numbered lexicographically, bx-block index fastest; *nblocks (host, may be
+ * NULL) receives their count.  Builds a table in the handle's workspace;
+ * SYNCHRONOUS.  The calls below work on even-parity packed fields of the
+ * handle's precision and need dwf_set_blocks first. */
+int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks);
+
+/* Chirality split of nvec fields (Deflation basis setup section: the
+ * filtered vectors are projected with 1 +- Gamma_5 before coarsening the
+ * five-dimensional operator): out[2k] = (1 + Gamma_5) in[k] / 2 and
+ * out[2k+1] = (1 - Gamma_5) in[k] / 2, (Gamma_5 v)_s = gamma_5 v_{Ls-1-s}.
+ * in: nvec fields, out: 2 nvec fields; they must not overlap. */
+int dwf_chiral_split(dwf_handle h, const void* in, void* out, int nvec);
+
+/* Device scratch (bytes) that dwf_block_orthonormalize needs for nvec
+ * vectors with the current blocks; 0 if blocks are not set or nvec is
+ * outside [1, 64]. */
+size_t dwf_block_scratch_bytes(dwf_handle h, int nvec);
+
+/* SYNCHRONOUS.  In place: inside every block, orthonormalise
+ * phi_0^b .. phi_{nvec-1}^b in index order (Q^b R^b = Phi^b, R^b upper
+ * triangular with a positive real diagonal), by two rounds of Cholesky QR
+ * with FP64 Gram matrices.  scratch: caller-owned device memory of at least
+ * dwf_block_scratch_bytes(h, nvec) bytes.  1 <= nvec <= 64.  Returns
+ * DWF_EBREAKDOWN if some block's vectors are linearly dependent. */
+int dwf_block_orthonormalize(dwf_handle h, void* basis, int nvec, void* scratch, size_t scratch_bytes);
+
+/* Restriction (the restrictor <phi_k^b| of the Two level preconditioner
+ * section): coarse[r][b][k] = <phi_k^b, v_r> = sum over the block's 5D sites,
+ * spins and colours of conj(phi_k) v_r, for nrhs fields v (complex128
+ * output, [nrhs][nblocks][nvec], device).  Sums are reduced in a fixed
+ * order in FP64. */
+int dwf_restrict(dwf_handle h, const void* basis, int nvec, const void* v, int nrhs, void* coarse);
+
+/* Prolongation (the prolongator |phi_k^b>): v_r = sum_{b,k} coarse[r][b][k]
+ * phi_k^b for nrhs coarse vectors laid out as dwf_restrict writes them; FP64
+ * accumulation, stored in the handle's precision.  v must not alias the
+ * basis. */
+int dwf_prolong(dwf_handle h, const void* basis, int nvec, const void* coarse, int nrhs, void* v);
+
 /* ---- HMC force ------------------------------------------------------------ */
 
 /* Link gradient of S = phi^dag (M_pc^dag M_pc)^{-1} phi given X = A^{-1} phi

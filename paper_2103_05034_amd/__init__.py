@@ -79,6 +79,12 @@ _PROTOS = {
     "dwf_chebyshev_smoother": (_i, [_vp, _i, _d, _d, _vp, _vp, _i]),
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_set_blocks": (_i, [_vp, _c_int_p, _c_int_p]),
+    "dwf_chiral_split": (_i, [_vp, _vp, _vp, _i]),
+    "dwf_block_scratch_bytes": (ctypes.c_size_t, [_vp, _i]),
+    "dwf_block_orthonormalize": (_i, [_vp, _vp, _i, _vp, ctypes.c_size_t]),
+    "dwf_restrict": (_i, [_vp, _vp, _i, _vp, _i, _vp]),
+    "dwf_prolong": (_i, [_vp, _vp, _i, _vp, _i, _vp]),
     "dwf_set_tile": (_i, [_vp, _i, _i, _i]),
     "dwf_set_order": (_i, [_vp, _i]),
     "dwf_set_occupancy": (_i, [_vp, _i]),
@@ -309,6 +315,51 @@ class Operator:
         _check(self.lib.dwf_gram_schmidt(self.h, _ptr(vecs), nvecs, R))
         r = np.frombuffer(R, dtype=np.float64).reshape(nvecs, nvecs, 2)
         return r[..., 0] + 1j * r[..., 1]
+
+    # ---- coarse-space transfer -----------------------------------------------------
+    def set_blocks(self, block):
+        """Blocks of bx, by, bz, bt 4D sites (all Ls slices); returns the number of blocks."""
+        nb = ctypes.c_int()
+        _check(self.lib.dwf_set_blocks(self.h, (ctypes.c_int * 4)(*[int(b) for b in block]), ctypes.byref(nb)))
+        self.nblocks = nb.value
+        return nb.value
+
+    def chiral_split(self, vecs, nvec, out=None):
+        """out[2k], out[2k+1] = (1 +- Gamma_5) vecs[k] / 2."""
+        if out is None:
+            out = self.new_field(2 * nvec)
+        self._sync_stream()
+        _check(self.lib.dwf_chiral_split(self.h, _ptr(vecs), _ptr(out), nvec))
+        return out
+
+    def block_orthonormalize(self, basis, nvec):
+        import torch
+
+        nbytes = self.lib.dwf_block_scratch_bytes(self.h, nvec)
+        if nbytes == 0:
+            raise DWFError(DWF_EINVAL, "set blocks first; nvec must be in [1, 64]")
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        _check(self.lib.dwf_block_orthonormalize(self.h, _ptr(basis), nvec, _ptr(scratch), nbytes))
+        return basis
+
+    def restrict(self, basis, nvec, v, nrhs=1, coarse=None):
+        """coarse[r][b][k] = <phi_k^b, v_r> (complex128 device tensor [nrhs, nblocks, nvec])."""
+        import torch
+
+        if coarse is None:
+            coarse = torch.empty((nrhs, self.nblocks, nvec), dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        _check(self.lib.dwf_restrict(self.h, _ptr(basis), nvec, _ptr(v), nrhs, _ptr(coarse)))
+        return coarse
+
+    def prolong(self, basis, nvec, coarse, nrhs=1, out=None):
+        """out_r = sum_{b,k} coarse[r][b][k] phi_k^b."""
+        if out is None:
+            out = self.new_field(nrhs)
+        self._sync_stream()
+        _check(self.lib.dwf_prolong(self.h, _ptr(basis), nvec, _ptr(coarse.contiguous()), nrhs, _ptr(out)))
+        return out
 
     def force(self, X_e, Y_e, grad=None):
         import torch

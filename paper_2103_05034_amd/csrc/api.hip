@@ -108,6 +108,7 @@ size_t carve(dwf_context* c, const int dims[4], int Ls, int prec, int max_nrhs, 
     }
   }
   d->order = reinterpret_cast<int*>(take((size_t)2 * V4h * sizeof(int)));
+  d->bsite = reinterpret_cast<int*>(take((size_t)V4h * sizeof(int)));
   d->hop_partials = max_cg_rhs > 0 ? reinterpret_cast<double*>(take((size_t)max_cg_rhs * V4h * sizeof(double)))
                                     : nullptr;
   int pc = chunk;
@@ -923,6 +924,113 @@ static bool build_order(const Geom& g, int mode, std::vector<int>& ord) {
     return true;
   }
   return false;
+}
+
+// ---------------------------------------------------------------------------
+// Coarse-space transfer (blocks, chirality split, block orthonormalisation,
+// restriction, prolongation)
+// ---------------------------------------------------------------------------
+int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks) {
+  if (int r = check_h(h)) return r;
+  if (!block) return fail(DWF_EINVAL, "dwf_set_blocks: block is NULL");
+  const Geom& g = h->g;
+  const int ext[4] = {g.X, g.Y, g.Z, g.T};
+  for (int i = 0; i < 4; ++i)
+    if (block[i] < 1 || ext[i] % block[i])
+      return fail(DWF_EINVAL, "dwf_set_blocks: block extent %d (dim %d) must divide the lattice extent %d", block[i],
+                  i, ext[i]);
+  const int vol = block[0] * block[1] * block[2] * block[3];
+  if (vol % 2) return fail(DWF_EINVAL, "dwf_set_blocks: the block volume must be even");
+  const int nsb = vol / 2;
+  if ((long long)nsb * g.Ls > 512)
+    return fail(DWF_EINVAL, "dwf_set_blocks: even sites per block x Ls = %lld exceeds 512", (long long)nsb * g.Ls);
+  const int nx = g.X / block[0], ny = g.Y / block[1], nz = g.Z / block[2], nt = g.T / block[3];
+  const long long nb = (long long)nx * ny * nz * nt;
+  std::vector<int> tab((size_t)nb * nsb);
+  for (int bt = 0; bt < nt; ++bt)
+    for (int bz = 0; bz < nz; ++bz)
+      for (int by = 0; by < ny; ++by)
+        for (int bx = 0; bx < nx; ++bx) {
+          const long long b = ((long long)(bt * nz + bz) * ny + by) * nx + bx;
+          int j = 0;
+          for (int t = bt * block[3]; t < (bt + 1) * block[3]; ++t)
+            for (int z = bz * block[2]; z < (bz + 1) * block[2]; ++z)
+              for (int y = by * block[1]; y < (by + 1) * block[1]; ++y)
+                for (int x = bx * block[0]; x < (bx + 1) * block[0]; ++x)
+                  if (((x + y + z + t) & 1) == 0) {
+                    if (j == nsb) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
+                    tab[(size_t)b * nsb + j++] = (int)half_index(g, x, y, z, t);
+                  }
+          if (j != nsb) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
+        }
+  HIP_TRY(hipMemcpyAsync(h->bsite, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int i = 0; i < 4; ++i) h->blk[i] = block[i];
+  h->nb = (int)nb;
+  h->nsb = nsb;
+  if (nblocks) *nblocks = (int)nb;
+  return DWF_OK;
+}
+
+static int check_blocks(dwf_handle h, int nvec, const char* who) {
+  if (int r = check_h(h)) return r;
+  if (h->nb <= 0) return fail(DWF_EINVAL, "%s: call dwf_set_blocks first", who);
+  if (nvec < 1 || nvec > 64) return fail(DWF_EINVAL, "%s: nvec must be in [1, 64]", who);
+  return DWF_OK;
+}
+
+int dwf_chiral_split(dwf_handle h, const void* in, void* out, int nvec) {
+  if (int r = check_h(h)) return r;
+  if (!in || !out || in == out) return fail(DWF_EINVAL, "dwf_chiral_split: in and out must be distinct device pointers");
+  if (nvec < 1) return fail(DWF_EINVAL, "dwf_chiral_split: nvec must be >= 1");
+  HIP_TRY(launch_chiral_split(h, h->prec, reinterpret_cast<const char*>(in), reinterpret_cast<char*>(out), nvec));
+  return DWF_OK;
+}
+
+size_t dwf_block_scratch_bytes(dwf_handle h, int nvec) {
+  if (!h || h->nb <= 0 || nvec < 1 || nvec > 64) return 0;
+  return 2 * up((size_t)h->nb * nvec * nvec * 16) + ALIGN;
+}
+
+int dwf_block_orthonormalize(dwf_handle h, void* basis, int nvec, void* scratch, size_t scratch_bytes) {
+  if (int r = check_blocks(h, nvec, "dwf_block_orthonormalize")) return r;
+  if (!basis || !scratch) return fail(DWF_EINVAL, "dwf_block_orthonormalize: NULL pointer");
+  if (scratch_bytes < dwf_block_scratch_bytes(h, nvec))
+    return fail(DWF_ENOMEM, "dwf_block_orthonormalize: scratch of %zu bytes, %zu needed", scratch_bytes,
+                dwf_block_scratch_bytes(h, nvec));
+  char* base = reinterpret_cast<char*>(scratch);
+  double* gram = reinterpret_cast<double*>(base);
+  double* w = reinterpret_cast<double*>(base + up((size_t)h->nb * nvec * nvec * 16));
+  int* flag = reinterpret_cast<int*>(base + 2 * up((size_t)h->nb * nvec * nvec * 16));
+  char* q = reinterpret_cast<char*>(basis);
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+  for (int pass = 0; pass < 2; ++pass) {  // Cholesky QR, twice
+    HIP_TRY(launch_block_dot(h, h->prec, q, nvec, q, nvec, gram, true));
+    HIP_TRY(launch_block_cholesky(h, gram, w, nvec, flag));
+    HIP_TRY(launch_block_apply(h, h->prec, q, nvec, w));
+  }
+  int hf = 0;
+  HIP_TRY(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (hf) return fail(DWF_EBREAKDOWN, "dwf_block_orthonormalize: a block's vectors are linearly dependent");
+  return DWF_OK;
+}
+
+int dwf_restrict(dwf_handle h, const void* basis, int nvec, const void* v, int nrhs, void* coarse) {
+  if (int r = check_blocks(h, nvec, "dwf_restrict")) return r;
+  if (!basis || !v || !coarse || nrhs < 1) return fail(DWF_EINVAL, "dwf_restrict: NULL pointer or nrhs < 1");
+  HIP_TRY(launch_block_dot(h, h->prec, reinterpret_cast<const char*>(basis), nvec, reinterpret_cast<const char*>(v),
+                           nrhs, reinterpret_cast<double*>(coarse), false));
+  return DWF_OK;
+}
+
+int dwf_prolong(dwf_handle h, const void* basis, int nvec, const void* coarse, int nrhs, void* v) {
+  if (int r = check_blocks(h, nvec, "dwf_prolong")) return r;
+  if (!basis || !v || !coarse || nrhs < 1) return fail(DWF_EINVAL, "dwf_prolong: NULL pointer or nrhs < 1");
+  if (v == basis) return fail(DWF_EINVAL, "dwf_prolong: v must not alias the basis");
+  HIP_TRY(launch_block_prolong(h, h->prec, reinterpret_cast<const char*>(basis), nvec,
+                               reinterpret_cast<const double*>(coarse), nrhs, reinterpret_cast<char*>(v)));
+  return DWF_OK;
 }
 
 int dwf_set_order(dwf_handle h, int mode) {

@@ -1,0 +1,403 @@
+// Coarse-space transfer of the two-level method on even-parity fields.
+//
+// Blocks (Two level preconditioner section): 4D boxes of bx*by*bz*bt sites
+// tiling the lattice, each taken with all Ls slices; a block holds nsb =
+// bx*by*bz*bt/2 even sites, listed in `bsite[b * nsb + j]` (half-lattice
+// index, block-local lexicographic order).  The blocked basis phi_k^b is a
+// field phi_k restricted to block b.
+//
+// * chiral_split: P+- v = (v +- Gamma_5 v)/2 with (Gamma_5 v)_s = gamma_5
+//   v_{Ls-1-s}: the five-dimensional chirality used when the domain-wall
+//   operator is coarsened (Deflation basis setup section).
+// * block_dot: c[r][b][k] = <phi_k^b, v_r>, the restrictor applied to nrhs
+//   fields; with v = the basis itself it is the Gram matrix of every block.
+// * block_combine: out_r = sum_k c[r][b][k] phi_k^b (prolongator), or the
+//   in-place map phi_k <- sum_{j<=k} W[b][j][k] phi_j^b used to
+//   orthonormalise (W = R^{-1} of the block's Cholesky factor).
+// * block_cholesky: per block G = R^dag R, then W = R^{-1}.
+//
+// One workgroup owns one block; its lane p = j * Ls + s holds one 5D site of
+// the block.  Spinor loads are contiguous along s as in every other kernel.
+// Sums over a block are reduced in a fixed order (wavefront shuffles, then
+// the waves in index order), so results are reproducible run to run.
+#include "dwf_internal.hpp"
+#include "kernels.hpp"
+
+namespace dwf {
+
+constexpr int KG = 4;  // basis vectors per reduction batch of block_dot
+
+// (P+ v, P- v) for one lane: upper spins take (v_s + v_r)/2 and (v_s - v_r)/2,
+// lower spins (gamma_5 = -1) the other way round; r = Ls - 1 - s
+template <int P>
+__global__ void __launch_bounds__(256) chiral_split_kernel(Geom g, const char* __restrict__ in, char* __restrict__ out,
+                                                            size_t stride) {
+  using R = typename Store<P>::real;
+  const long long n = g.V4h * g.Ls;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int k = blockIdx.y;
+  const long long h = i / g.Ls;
+  const int s = (int)(i - h * g.Ls);
+  const char* v = in + (size_t)k * stride;
+  cplx<R> a[12], b[12], p[12], m[12];
+  Store<P>::load(v, g.V4h, g.Ls, h, s, a);
+  Store<P>::load(v, g.V4h, g.Ls, h, g.Ls - 1 - s, b);
+  const R half = (R)0.5;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) {
+    const cplx<R> sum = {(a[c].re + b[c].re) * half, (a[c].im + b[c].im) * half};
+    const cplx<R> dif = {(a[c].re - b[c].re) * half, (a[c].im - b[c].im) * half};
+    p[c] = c < 6 ? sum : dif;
+    m[c] = c < 6 ? dif : sum;
+  }
+  Store<P>::store(out + (size_t)(2 * k) * stride, g.V4h, g.Ls, h, s, p);
+  Store<P>::store(out + (size_t)(2 * k + 1) * stride, g.V4h, g.Ls, h, s, m);
+}
+
+// Fixed-order sum of NV doubles over the workgroup; thread 0 gets the totals.
+// red holds (blockDim / 64) * NV doubles.
+template <int NV>
+__device__ __forceinline__ void group_sum(double (&v)[NV], double* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    v[i] = x;
+  }
+  __syncthreads();  // red is free
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[i * nw + wave] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double t = 0;
+      for (int w = 0; w < nw; ++w) t += red[i * nw + w];
+      v[i] = t;
+    }
+  }
+}
+
+struct BlockArgs {
+  Geom g;
+  const int* bsite;  // [nb][nsb]
+  int nsb, nb;
+  const char* basis;  // nvec fields, stride `stride`
+  int nvec;
+  size_t stride;
+  const char* v;  // block_dot: nrhs fields, stride `stride`
+  char* out;      // block_combine: output fields (or the basis itself, in place)
+  int nrhs;
+  double* coef;        // block_dot output / block_combine input, complex [nrhs][nb][nvec]
+  int per_block;       // block_dot: lay coef out as [nb][nrhs][nvec] (each block's Gram matrix contiguous)
+  const double* wmat;  // block_combine in-place mode: complex [nb][nvec][nvec], W[j][k] at (j * nvec + k)
+};
+
+// c[r][b][k] = <phi_k^b, v_r> for the RT right-hand sides r = blockIdx.y * RT + ...
+template <int P, int RT>
+__global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
+  using R = typename Store<P>::real;
+  extern __shared__ double red[];
+  const int b = blockIdx.x;
+  const int r0 = blockIdx.y * RT;
+  const int np = a.nsb * a.g.Ls;
+  const int p = threadIdx.x;
+  const bool live = p < np;
+  long long h = 0;
+  int s = 0;
+  if (live) {
+    const int j = p / a.g.Ls;
+    s = p - j * a.g.Ls;
+    h = a.bsite[(size_t)b * a.nsb + j];
+  }
+  cplx<R> v[RT][12];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const bool use = live && (r0 + r < a.nrhs);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[r][c] = {0, 0};
+    if (use) Store<P>::load(a.v + (size_t)(r0 + r) * a.stride, a.g.V4h, a.g.Ls, h, s, v[r]);
+  }
+  for (int k0 = 0; k0 < a.nvec; k0 += KG) {
+    double acc[2 * RT * KG];
+#pragma unroll
+    for (int i = 0; i < 2 * RT * KG; ++i) acc[i] = 0;
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) {
+      if (live && k0 + kk < a.nvec) {
+        cplx<R> f[12];
+        Store<P>::load(a.basis + (size_t)(k0 + kk) * a.stride, a.g.V4h, a.g.Ls, h, s, f);
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          double re = 0, im = 0;
+#pragma unroll
+          for (int c = 0; c < 12; ++c) {  // conj(f) v
+            re = fma((double)f[c].re, (double)v[r][c].re, re);
+            re = fma((double)f[c].im, (double)v[r][c].im, re);
+            im = fma((double)f[c].re, (double)v[r][c].im, im);
+            im = fma(-(double)f[c].im, (double)v[r][c].re, im);
+          }
+          acc[2 * (r * KG + kk)] = re;
+          acc[2 * (r * KG + kk) + 1] = im;
+        }
+      }
+    }
+    group_sum<2 * RT * KG>(acc, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk)
+          if (r0 + r < a.nrhs && k0 + kk < a.nvec) {
+            const size_t row = a.per_block ? (size_t)b * a.nrhs + r0 + r : (size_t)(r0 + r) * a.nb + b;
+            double* o = a.coef + 2 * (row * a.nvec + k0 + kk);
+            o[0] = acc[2 * (r * KG + kk)];
+            o[1] = acc[2 * (r * KG + kk) + 1];
+          }
+    }
+  }
+}
+
+// INPLACE = false: out_r = sum_k coef[r][b][k] phi_k^b for the KT right-hand
+//   sides r = blockIdx.y * KT + ...
+// INPLACE = true: phi_k <- sum_{j<=k} W[b][j][k] phi_j^b for every k, one
+//   workgroup per block taking the k tiles from the top down, so that the
+//   phi_j a tile still needs (j below the tile) are not yet overwritten; every
+//   lane reads and writes only its own 5D site.
+template <int P, int KT, bool INPLACE>
+__global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
+  using R = typename Store<P>::real;
+  extern __shared__ double cs[];  // complex coefficients of the workgroup
+  const int b = blockIdx.x;
+  const int np = a.nsb * a.g.Ls;
+  const int p = threadIdx.x;
+  const bool live = p < np;
+  long long h = 0;
+  int s = 0;
+  if (live) {
+    const int j = p / a.g.Ls;
+    s = p - j * a.g.Ls;
+    h = a.bsite[(size_t)b * a.nsb + j];
+  }
+  const int n = a.nvec;
+  if (INPLACE) {
+    for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
+      cs[2 * i] = a.wmat[2 * ((size_t)b * n * n + i)];
+      cs[2 * i + 1] = a.wmat[2 * ((size_t)b * n * n + i) + 1];
+    }
+  } else {
+    const int r0 = blockIdx.y * KT;
+    for (int i = threadIdx.x; i < KT * n; i += blockDim.x) {
+      const int r = i / n, k = i - r * n;
+      double re = 0, im = 0;
+      if (r0 + r < a.nrhs) {
+        const double* c = a.coef + 2 * (((size_t)(r0 + r) * a.nb + b) * n + k);
+        re = c[0];
+        im = c[1];
+      }
+      cs[2 * i] = re;
+      cs[2 * i + 1] = im;
+    }
+  }
+  __syncthreads();
+  if (!live) return;
+  const int ntiles = INPLACE ? (n + KT - 1) / KT : 1;
+  for (int tile = ntiles - 1; tile >= 0; --tile) {
+    const int k0 = tile * KT;                         // INPLACE: outputs k0 .. k0+KT-1
+    const int jmax = INPLACE ? min(n, k0 + KT) : n;  // inputs j < jmax
+    cplx<double> acc[KT][12];
+#pragma unroll
+    for (int t = 0; t < KT; ++t)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[t][c] = {0, 0};
+    for (int j = 0; j < jmax; ++j) {
+      cplx<R> f[12];
+      Store<P>::load(a.basis + (size_t)j * a.stride, a.g.V4h, a.g.Ls, h, s, f);
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        // coefficient of phi_j in output t
+        const int idx = INPLACE ? (j * n + k0 + t) : (t * n + j);
+        if (INPLACE && (k0 + t >= n || j > k0 + t)) continue;
+        const double cr = cs[2 * idx], ci = cs[2 * idx + 1];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+          acc[t][c].re = fma(cr, (double)f[c].re, fma(-ci, (double)f[c].im, acc[t][c].re));
+          acc[t][c].im = fma(cr, (double)f[c].im, fma(ci, (double)f[c].re, acc[t][c].im));
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KT; ++t) {
+      const int k = INPLACE ? k0 + t : blockIdx.y * KT + t;
+      if (k >= (INPLACE ? n : a.nrhs)) continue;
+      cplx<R> o[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) o[c] = {(R)acc[t][c].re, (R)acc[t][c].im};
+      Store<P>::store(a.out + (size_t)k * a.stride, a.g.V4h, a.g.Ls, h, s, o);
+    }
+  }
+}
+
+// Per block: Cholesky G = R^dag R of the Hermitian Gram matrix
+// G[k][j] = <phi_j, phi_k> (as block_dot lays it out, row = rhs = k), then
+// W = R^{-1}, upper triangular, stored W[j][k] at (j * n + k).  One thread per
+// block; a non-positive or non-finite pivot raises *flag.
+__global__ void block_cholesky_kernel(const double* __restrict__ gram, double* __restrict__ w, int nb, int n,
+                                      int* flag) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  const double* G = gram + 2 * (size_t)b * n * n;
+  double* W = w + 2 * (size_t)b * n * n;
+  // R is built in W's storage row by row (R[j][k], k >= j), then inverted in place
+  // column by column from the right: both stay upper triangular.
+  for (int j = 0; j < n; ++j) {
+    // R[j][j] = sqrt(G_jj - sum_{i<j} |R[i][j]|^2)
+    double d = G[2 * (j * n + j)];
+    for (int i = 0; i < j; ++i) {
+      const double rr = W[2 * (i * n + j)], ri = W[2 * (i * n + j) + 1];
+      d -= rr * rr + ri * ri;
+    }
+    if (!(d > 0.0) || !isfinite(d)) {
+      *flag = 1;
+      d = 1.0;
+    }
+    const double rjj = sqrt(d);
+    W[2 * (j * n + j)] = rjj;
+    W[2 * (j * n + j) + 1] = 0.0;
+    for (int k = j + 1; k < n; ++k) {
+      // R[j][k] = (G_jk - sum_{i<j} conj(R[i][j]) R[i][k]) / R[j][j], G_jk = <phi_j, phi_k> = gram[k][j]
+      double re = G[2 * (k * n + j)], im = G[2 * (k * n + j) + 1];
+      for (int i = 0; i < j; ++i) {
+        const double ar = W[2 * (i * n + j)], ai = -W[2 * (i * n + j) + 1];  // conj(R[i][j])
+        const double br = W[2 * (i * n + k)], bi = W[2 * (i * n + k) + 1];
+        re -= ar * br - ai * bi;
+        im -= ar * bi + ai * br;
+      }
+      W[2 * (j * n + k)] = re / rjj;
+      W[2 * (j * n + k) + 1] = im / rjj;
+    }
+    for (int k = 0; k < j; ++k) {  // lower triangle of W is zero
+      W[2 * (j * n + k)] = 0.0;
+      W[2 * (j * n + k) + 1] = 0.0;
+    }
+  }
+  // in-place inverse of the upper triangular R, column k from the diagonal up:
+  // Winv[k][k] = 1 / R[k][k]; Winv[j][k] = -(sum_{i=j+1..k} R[j][i] Winv[i][k]) / R[j][j]
+  for (int k = n - 1; k >= 0; --k) {
+    const double inv = 1.0 / W[2 * (k * n + k)];
+    W[2 * (k * n + k)] = inv;
+    for (int j = k - 1; j >= 0; --j) {
+      double re = 0, im = 0;
+      for (int i = j + 1; i <= k; ++i) {
+        // R[j][i] is still in place for i > j (rows above j untouched so far in this column pass);
+        // Winv[i][k] for i > j is already final
+        const double ar = W[2 * (j * n + i)], ai = W[2 * (j * n + i) + 1];
+        const double br = W[2 * (i * n + k)], bi = W[2 * (i * n + k) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      const double rjj = W[2 * (j * n + j)];
+      W[2 * (j * n + k)] = -re / rjj;
+      W[2 * (j * n + k) + 1] = -im / rjj;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int lanes_of(const dwf_context* c) { return c->nsb * c->g.Ls; }
+static int group_of(int lanes) { return (lanes + 63) / 64 * 64; }
+
+hipError_t launch_chiral_split(dwf_context* c, int prec, const char* in, char* out, int nvec) {
+  const long long n = c->g.V4h * c->g.Ls;
+  dim3 grid((unsigned)((n + 255) / 256), nvec);
+  const size_t st = field_bytes_rhs(c, prec);
+  switch (prec) {
+    case DWF_F64: hipLaunchKernelGGL(chiral_split_kernel<DWF_F64>, grid, dim3(256), 0, c->stream, c->g, in, out, st); break;
+    case DWF_F32: hipLaunchKernelGGL(chiral_split_kernel<DWF_F32>, grid, dim3(256), 0, c->stream, c->g, in, out, st); break;
+    default: hipLaunchKernelGGL(chiral_split_kernel<DWF_F16S>, grid, dim3(256), 0, c->stream, c->g, in, out, st); break;
+  }
+  return hipGetLastError();
+}
+
+static BlockArgs block_args(const dwf_context* c, int prec, const char* basis, int nvec) {
+  BlockArgs a{};
+  a.g = c->g;
+  a.bsite = c->bsite;
+  a.nsb = c->nsb;
+  a.nb = c->nb;
+  a.basis = basis;
+  a.nvec = nvec;
+  a.stride = field_bytes_rhs(c, prec);
+  return a;
+}
+
+template <int P, int RT>
+static void dot_t(const dwf_context* c, const BlockArgs& a) {
+  const int lanes = group_of(lanes_of(c));
+  const size_t lds = (size_t)(lanes / 64) * 2 * RT * KG * sizeof(double);
+  hipLaunchKernelGGL((block_dot_kernel<P, RT>), dim3(a.nb, (a.nrhs + RT - 1) / RT), dim3(lanes), lds, c->stream, a);
+}
+
+hipError_t launch_block_dot(dwf_context* c, int prec, const char* basis, int nvec, const char* v, int nrhs,
+                            double* coef, bool per_block) {
+  BlockArgs a = block_args(c, prec, basis, nvec);
+  a.v = v;
+  a.nrhs = nrhs;
+  a.coef = coef;
+  a.per_block = per_block ? 1 : 0;
+  switch (prec) {
+    case DWF_F64: dot_t<DWF_F64, 2>(c, a); break;
+    case DWF_F32: dot_t<DWF_F32, 2>(c, a); break;
+    default: dot_t<DWF_F16S, 2>(c, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int P, int KT, bool INPLACE>
+static void combine_t(const dwf_context* c, const BlockArgs& a) {
+  const int lanes = group_of(lanes_of(c));
+  const size_t lds = (INPLACE ? (size_t)a.nvec * a.nvec : (size_t)KT * a.nvec) * 2 * sizeof(double);
+  const unsigned gy = INPLACE ? 1 : (unsigned)((a.nrhs + KT - 1) / KT);
+  hipLaunchKernelGGL((block_combine_kernel<P, KT, INPLACE>), dim3(a.nb, gy), dim3(lanes), lds, c->stream, a);
+}
+
+hipError_t launch_block_prolong(dwf_context* c, int prec, const char* basis, int nvec, const double* coef, int nrhs,
+                                char* out) {
+  BlockArgs a = block_args(c, prec, basis, nvec);
+  a.coef = const_cast<double*>(coef);
+  a.nrhs = nrhs;
+  a.out = out;
+  switch (prec) {
+    case DWF_F64: combine_t<DWF_F64, 2, false>(c, a); break;
+    case DWF_F32: combine_t<DWF_F32, 2, false>(c, a); break;
+    default: combine_t<DWF_F16S, 2, false>(c, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_apply(dwf_context* c, int prec, char* basis, int nvec, const double* wmat) {
+  BlockArgs a = block_args(c, prec, basis, nvec);
+  a.wmat = wmat;
+  a.out = basis;
+  switch (prec) {
+    case DWF_F64: combine_t<DWF_F64, 2, true>(c, a); break;
+    case DWF_F32: combine_t<DWF_F32, 2, true>(c, a); break;
+    default: combine_t<DWF_F16S, 2, true>(c, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_cholesky(dwf_context* c, const double* gram, double* w, int nvec, int* flag) {
+  hipLaunchKernelGGL(block_cholesky_kernel, dim3((c->nb + 63) / 64), dim3(64), 0, c->stream, gram, w, c->nb, nvec,
+                     flag);
+  return hipGetLastError();
+}
+
+}  // namespace dwf

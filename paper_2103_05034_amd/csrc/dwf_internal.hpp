@@ -310,6 +310,10 @@ struct dwf_context {
   int* order;            // site traversal order per out parity, [2][V4h] (device)
   int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
   int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
+  // coarse-space blocks: extents, count, even sites per block, their half-lattice indices [nb][nsb]
+  int blk[4];
+  int nb, nsb;
+  int* bsite;
   // progress reporting of the synchronous solvers
   dwf_progress_fn progress_fn;
   void* progress_user;

@@ -78,6 +78,19 @@ hipError_t gs_multidot(dwf_context* ctx, int prec, const char* Q, const char* v,
 hipError_t gs_multiaxpy(dwf_context* ctx, int prec, const char* Q, char* v, int j, const double* coef);
 hipError_t gs_scale(dwf_context* ctx, int prec, char* v, const double* inv_norm);
 
+// coarse.hip (block tables in ctx->bsite; coefficients complex FP64)
+hipError_t launch_chiral_split(dwf_context* c, int prec, const char* in, char* out, int nvec);
+// coef[r][b][k] = <phi_k^b, v_r> ([b][r][k] with per_block)
+hipError_t launch_block_dot(dwf_context* c, int prec, const char* basis, int nvec, const char* v, int nrhs,
+                            double* coef, bool per_block);
+// out_r = sum_k coef[r][b][k] phi_k^b
+hipError_t launch_block_prolong(dwf_context* c, int prec, const char* basis, int nvec, const double* coef, int nrhs,
+                                char* out);
+// phi_k <- sum_{j<=k} W[b][j][k] phi_j^b in place
+hipError_t launch_block_apply(dwf_context* c, int prec, char* basis, int nvec, const double* wmat);
+// per block: Cholesky of the Gram matrix ([b][k][j] = <phi_j, phi_k>) and W = R^{-1}
+hipError_t launch_block_cholesky(dwf_context* c, const double* gram, double* w, int nvec, int* flag);
+
 // force.hip
 hipError_t launch_force(dwf_context* ctx, const char* a_even, const char* a_odd, const char* b_even,
                         const char* b_odd, double* grad_U);
