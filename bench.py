@@ -42,6 +42,8 @@ WORKLOADS = {
     "mixed": dict(dims=(24, 24, 24, 48), Ls=24, M5=1.8, mf=0.00078, eps=0.15, nvec=24, order=32, lo=0.05, hi=60.0),
     "force": dict(dims=(8, 8, 8, 16), Ls=12, M5=1.8, mf=0.01, eps=0.2),
     "copy": dict(bytes=4 << 30),
+    # Algorithm A: 4x2x4x2 blocks, 40 basis vectors; Algorithm B: 2^4 blocks, 32 (both chirality-split)
+    "coarse": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, algos={"A": ((4, 2, 4, 2), 20), "B": ((2, 2, 2, 2), 16)}),
 }
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic.json")
@@ -608,7 +610,84 @@ def run_copy(args):
     }
 
 
-RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force, "copy": run_copy}
+def run_coarse(args):
+    """Coarse-space transfer on 40 / 32 FP32 vectors at 16^3x32, Ls=16 with the Algorithm A / B
+    blocks: chirality split, block orthonormalisation (two Cholesky-QR rounds), restriction and
+    prolongation of one field, each timed and set against its algorithmic bytes."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["coarse"]
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    X, Y, Z, T = dims
+    V5h = X * Y * Z * T * Ls // 2
+    S = SPINOR_BYTES[dwf.DWF_F32]
+    U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
+    reps = max(args.steps, 1)
+    results = {}
+    for name, (block, nraw) in cfg["algos"].items():
+        nvec = 2 * nraw
+        op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F32, max_nrhs=1, max_cg_rhs=0)
+        nb = op.set_blocks(block)
+        raw = op.new_field(nraw)
+        _fill_gaussian(op, raw, nraw, dims, Ls, seed=2)
+        basis = op.new_field(nvec)
+        v = op.new_field(1)
+        _fill_gaussian(op, v, 1, dims, Ls, seed=5, chunk=1)
+        coarse = torch.zeros((1, nb, nvec), dtype=torch.complex128, device="cuda")
+        out = op.new_field(1)
+        steps = {
+            "chiral_split": (lambda: op.chiral_split(raw, nraw, out=basis), 3 * nraw * S * V5h),
+            "block_orthonormalize": (lambda: op.block_orthonormalize(basis, nvec), 6 * nvec * S * V5h),
+            "restrict": (lambda: op.restrict(basis, nvec, v, 1, coarse=coarse), (nvec + 1) * S * V5h),
+            "prolong": (lambda: op.prolong(basis, nvec, coarse, 1, out=out), (nvec + 1) * S * V5h),
+        }
+        res = {"block": list(block), "blocks": nb, "basis_vectors": nvec}
+        for step, (fn, nbytes) in steps.items():
+            for _ in range(args.warmup):
+                fn()
+            t, _ = _timed(lambda: [fn() for _ in range(reps)])
+            ms = t / reps * 1e3
+            res[step] = {"ms": ms, "algorithmic_GBs": nbytes / (ms * 1e-3) / 1e9}
+            log(f"coarse {name} {step}: {ms:.3f} ms, {res[step]['algorithmic_GBs']:.0f} GB/s")
+        # the transfer must stay a projector: restrict(prolong(c)) == c after orthonormalisation
+        back = op.restrict(basis, nvec, out, 1)
+        torch.cuda.synchronize()
+        res["restrict_prolong_rel_err"] = float((back - coarse).abs().max() / coarse.abs().max())
+        results[name] = res
+        op.close()
+        del op, raw, basis, v, out, coarse
+        torch.cuda.empty_cache()
+    a = results["A"]["restrict"]["algorithmic_GBs"]
+    return {
+        "metric": METRIC,
+        "value": a,
+        "unit": "GB/s (restriction of one field onto 40 FP32 basis vectors, 4x2x4x2 blocks)",
+        "n_gpus": 1,
+        "steps": reps,
+        "warmup": args.warmup,
+        "ms_per_step": results["A"]["restrict"]["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 sums",
+        "data": "synthetic",
+        "config": {"workload": "coarse-space transfer, 16^3x32 Ls=16, Algorithm A / B blocks", **results},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": a,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": a / PEAK_HBM_GBS,
+            "traffic": None,
+            "kernel": "block_dot_kernel (restriction)",
+        },
+    }
+
+
+RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force, "copy": run_copy, "coarse": run_coarse}
 
 
 def main():

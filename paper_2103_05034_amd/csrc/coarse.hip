@@ -123,13 +123,16 @@ __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
     for (int c = 0; c < 12; ++c) v[r][c] = {0, 0};
     if (use) Store<P>::load(a.v + (size_t)(r0 + r) * a.stride, a.g.V4h, a.g.Ls, h, s, v[r]);
   }
-  for (int k0 = 0; k0 < a.nvec; k0 += KG) {
+  // a Gram matrix (per_block) is Hermitian and its Cholesky factorisation reads
+  // only the entries with basis index <= rhs index: stop at the tile's last rhs
+  const int kend = a.per_block ? min(a.nvec, r0 + RT) : a.nvec;
+  for (int k0 = 0; k0 < kend; k0 += KG) {
     double acc[2 * RT * KG];
 #pragma unroll
     for (int i = 0; i < 2 * RT * KG; ++i) acc[i] = 0;
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk) {
-      if (live && k0 + kk < a.nvec) {
+      if (live && k0 + kk < kend) {
         cplx<R> f[12];
         Store<P>::load(a.basis + (size_t)(k0 + kk) * a.stride, a.g.V4h, a.g.Ls, h, s, f);
 #pragma unroll
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
       for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int kk = 0; kk < KG; ++kk)
-          if (r0 + r < a.nrhs && k0 + kk < a.nvec) {
+          if (r0 + r < a.nrhs && k0 + kk < kend) {
             const size_t row = a.per_block ? (size_t)b * a.nrhs + r0 + r : (size_t)(r0 + r) * a.nb + b;
             double* o = a.coef + 2 * (row * a.nvec + k0 + kk);
             o[0] = acc[2 * (r * KG + kk)];
@@ -244,67 +247,69 @@ __global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
 }
 
 // Per block: Cholesky G = R^dag R of the Hermitian Gram matrix
-// G[k][j] = <phi_j, phi_k> (as block_dot lays it out, row = rhs = k), then
-// W = R^{-1}, upper triangular, stored W[j][k] at (j * n + k).  One thread per
-// block; a non-positive or non-finite pivot raises *flag.
-__global__ void block_cholesky_kernel(const double* __restrict__ gram, double* __restrict__ w, int nb, int n,
-                                      int* flag) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= nb) return;
+// G[k][j] = <phi_j, phi_k> (as block_dot lays it out, row = rhs = k; only
+// j <= k is read), then W = R^{-1}, upper triangular, stored W[j][k] at
+// (j * n + k).  One wave per block, lane k owning column k: row j of R is
+// R[j][k] = (G_jk - sum_{i<j} conj(R[i][j]) R[i][k]) / R[j][j], computed by
+// all lanes k >= j at once from column j (finished by lane j in the step
+// before); column k of R^{-1} then needs only R and the lane's own column.
+// A non-positive or non-finite pivot raises *flag.
+__global__ void __launch_bounds__(64) block_cholesky_kernel(const double* __restrict__ gram, double* __restrict__ w,
+                                                            int nb, int n, int* flag) {
+  extern __shared__ double rs[];  // R, complex [n][n]
+  const int b = blockIdx.x;
+  const int k = threadIdx.x;
   const double* G = gram + 2 * (size_t)b * n * n;
   double* W = w + 2 * (size_t)b * n * n;
-  // R is built in W's storage row by row (R[j][k], k >= j), then inverted in place
-  // column by column from the right: both stay upper triangular.
+  for (int i = k; i < n * n; i += 64) {
+    rs[2 * i] = 0.0;
+    rs[2 * i + 1] = 0.0;
+  }
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
-    // R[j][j] = sqrt(G_jj - sum_{i<j} |R[i][j]|^2)
-    double d = G[2 * (j * n + j)];
-    for (int i = 0; i < j; ++i) {
-      const double rr = W[2 * (i * n + j)], ri = W[2 * (i * n + j) + 1];
-      d -= rr * rr + ri * ri;
+    if (k == j) {
+      double d = G[2 * (j * n + j)];
+      for (int i = 0; i < j; ++i) d -= rs[2 * (i * n + j)] * rs[2 * (i * n + j)] + rs[2 * (i * n + j) + 1] * rs[2 * (i * n + j) + 1];
+      if (!(d > 0.0) || !isfinite(d)) {
+        *flag = 1;
+        d = 1.0;
+      }
+      rs[2 * (j * n + j)] = sqrt(d);
     }
-    if (!(d > 0.0) || !isfinite(d)) {
-      *flag = 1;
-      d = 1.0;
-    }
-    const double rjj = sqrt(d);
-    W[2 * (j * n + j)] = rjj;
-    W[2 * (j * n + j) + 1] = 0.0;
-    for (int k = j + 1; k < n; ++k) {
-      // R[j][k] = (G_jk - sum_{i<j} conj(R[i][j]) R[i][k]) / R[j][j], G_jk = <phi_j, phi_k> = gram[k][j]
-      double re = G[2 * (k * n + j)], im = G[2 * (k * n + j) + 1];
+    __syncthreads();
+    if (k > j && k < n) {
+      double re = G[2 * (k * n + j)], im = G[2 * (k * n + j) + 1];  // G_jk = <phi_j, phi_k>
       for (int i = 0; i < j; ++i) {
-        const double ar = W[2 * (i * n + j)], ai = -W[2 * (i * n + j) + 1];  // conj(R[i][j])
-        const double br = W[2 * (i * n + k)], bi = W[2 * (i * n + k) + 1];
+        const double ar = rs[2 * (i * n + j)], ai = -rs[2 * (i * n + j) + 1];  // conj(R[i][j])
+        const double br = rs[2 * (i * n + k)], bi = rs[2 * (i * n + k) + 1];
         re -= ar * br - ai * bi;
         im -= ar * bi + ai * br;
       }
-      W[2 * (j * n + k)] = re / rjj;
-      W[2 * (j * n + k) + 1] = im / rjj;
+      const double inv = 1.0 / rs[2 * (j * n + j)];
+      rs[2 * (j * n + k)] = re * inv;
+      rs[2 * (j * n + k) + 1] = im * inv;
     }
-    for (int k = 0; k < j; ++k) {  // lower triangle of W is zero
-      W[2 * (j * n + k)] = 0.0;
-      W[2 * (j * n + k) + 1] = 0.0;
-    }
+    __syncthreads();
   }
-  // in-place inverse of the upper triangular R, column k from the diagonal up:
-  // Winv[k][k] = 1 / R[k][k]; Winv[j][k] = -(sum_{i=j+1..k} R[j][i] Winv[i][k]) / R[j][j]
-  for (int k = n - 1; k >= 0; --k) {
-    const double inv = 1.0 / W[2 * (k * n + k)];
-    W[2 * (k * n + k)] = inv;
-    for (int j = k - 1; j >= 0; --j) {
-      double re = 0, im = 0;
-      for (int i = j + 1; i <= k; ++i) {
-        // R[j][i] is still in place for i > j (rows above j untouched so far in this column pass);
-        // Winv[i][k] for i > j is already final
-        const double ar = W[2 * (j * n + i)], ai = W[2 * (j * n + i) + 1];
-        const double br = W[2 * (i * n + k)], bi = W[2 * (i * n + k) + 1];
-        re += ar * br - ai * bi;
-        im += ar * bi + ai * br;
-      }
-      const double rjj = W[2 * (j * n + j)];
-      W[2 * (j * n + k)] = -re / rjj;
-      W[2 * (j * n + k) + 1] = -im / rjj;
+  if (k >= n) return;
+  // column k of R^{-1}: W[k][k] = 1 / R[k][k]; W[j][k] = -(sum_{i=j+1..k} R[j][i] W[i][k]) / R[j][j]
+  for (int j = k + 1; j < n; ++j) {
+    W[2 * (j * n + k)] = 0.0;
+    W[2 * (j * n + k) + 1] = 0.0;
+  }
+  W[2 * (k * n + k)] = 1.0 / rs[2 * (k * n + k)];
+  W[2 * (k * n + k) + 1] = 0.0;
+  for (int j = k - 1; j >= 0; --j) {
+    double re = 0, im = 0;
+    for (int i = j + 1; i <= k; ++i) {
+      const double ar = rs[2 * (j * n + i)], ai = rs[2 * (j * n + i) + 1];
+      const double br = W[2 * (i * n + k)], bi = W[2 * (i * n + k) + 1];
+      re += ar * br - ai * bi;
+      im += ar * bi + ai * br;
     }
+    const double inv = -1.0 / rs[2 * (j * n + j)];
+    W[2 * (j * n + k)] = re * inv;
+    W[2 * (j * n + k) + 1] = im * inv;
   }
 }
 
@@ -395,8 +400,8 @@ hipError_t launch_block_apply(dwf_context* c, int prec, char* basis, int nvec, c
 }
 
 hipError_t launch_block_cholesky(dwf_context* c, const double* gram, double* w, int nvec, int* flag) {
-  hipLaunchKernelGGL(block_cholesky_kernel, dim3((c->nb + 63) / 64), dim3(64), 0, c->stream, gram, w, c->nb, nvec,
-                     flag);
+  hipLaunchKernelGGL(block_cholesky_kernel, dim3(c->nb), dim3(64), (size_t)nvec * nvec * 2 * sizeof(double), c->stream,
+                     gram, w, c->nb, nvec, flag);
   return hipGetLastError();
 }
 

@@ -179,3 +179,20 @@ def test_fullsize_orthonormal_basis_identities(block):
     cc = rng.standard_normal((1, nb, nvec)) + 1j * rng.standard_normal((1, nb, nvec))
     back = coarse_host(op.restrict(basis, nvec, op.prolong(basis, nvec, torch.from_numpy(cc).cuda(), 1), 1))
     assert relmax(back, cc) < 1e-6
+
+
+def test_block_orthonormalize_max_nvec():
+    """nvec = 64, the largest basis: the Gram, Cholesky and update kernels hold a full
+    64 x 64 complex matrix per block in LDS."""
+    dims, Ls = C1
+    block = (2, 2, 2, 2)
+    op, _ = make_operator(dims, Ls, prec=F64, max_nrhs=64, max_cg_rhs=0)
+    op.set_blocks(block)
+    V = even_fields(dims, Ls, 64, seed=48)
+    buf = pack(op, V, EVEN)
+    op.block_orthonormalize(buf, 64)
+    G = coarse_host(op.restrict(buf, 64, buf, 64))
+    assert np.max(np.abs(G - np.eye(64)[:, None, :])) < 1e-12
+    Q = unpack(op, buf, 64, EVEN)
+    Qo, _ = C.block_orthonormalize(list(V), dims, block)
+    assert max(relmax(Q[k], Qo[k]) for k in range(64)) < 1e-10
