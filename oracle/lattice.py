@@ -238,6 +238,28 @@ def mpcdagmpc(U, psi_e, M5, mf):
     return mpc_dag(U, mpc(U, psi_e, M5, mf), M5, mf)
 
 
+def mpc2(U, psi_e, M5, mf):
+    """Second Schur form (Results, Krylov table): 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe."""
+    t = m5d_inv(m_oe(U, psi_e), M5, mf)
+    return psi_e - m5d_inv(m_eo(U, t), M5, mf)
+
+
+def mpc2_dag(U, psi_e, M5, mf):
+    """(1 - M_ee^{-1} M_eo M_oo^{-1} M_oe)^dag = 1 - M_oe^dag M_oo^{-dag} M_eo^dag M_ee^{-dag}."""
+    y = m5d_inv(psi_e, M5, mf, dag=True)
+    t = m5d_inv(m_eo(U, y, dag=True), M5, mf, dag=True)
+    return psi_e - m_oe(U, t, dag=True)
+
+
+def mpc2dagmpc2(U, psi_e, M5, mf):
+    return mpc2_dag(U, mpc2(U, psi_e, M5, mf), M5, mf)
+
+
+def schur_source2(U, eta, M5, mf):
+    """Right-hand side of the second form: M_ee^{-1} eta'."""
+    return m5d_inv(schur_source(U, eta, M5, mf), M5, mf)
+
+
 def schur_source(U, eta, M5, mf):
     """eta' = eta_e - M_eo M_oo^{-1} eta_o (the even-site source of the Schur system)."""
     eta_e = on_parity(eta, EVEN)

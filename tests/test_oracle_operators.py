@@ -265,3 +265,47 @@ def test_mpcdagmpc_dense_spectrum(small):
     Mpc = L.dense_matrix(lambda v: L.mpc(U, v, M5, MF), shape, even)
     sv = np.linalg.svd(Mpc, compute_uv=False)
     assert np.max(np.abs(np.sort(sv**2) - w)) < 1e-11 * w.max()
+
+
+def test_mpc2_adjoint(small):
+    """The second Schur form's adjoint, assembled from adjoint blocks in reverse order,
+    is the conjugate transpose of its dense matrix."""
+    dims, Ls, U, shape = small
+    even = L.parity_entry_mask(shape, L.EVEN)
+    M2 = L.dense_matrix(lambda v: L.mpc2(U, v, M5, MF), shape, even)
+    M2dag = L.dense_matrix(lambda v: L.mpc2_dag(U, v, M5, MF), shape, even)
+    assert np.max(np.abs(M2dag - M2.conj().T)) < 1e-13
+    # det(1 - M_ee^{-1} M_eo M_oo^{-1} M_oe) = det M_pc / det M_ee, M_ee = K on each even site and colour
+    Mpc = L.dense_matrix(lambda v: L.mpc(U, v, M5, MF), shape, even)
+    ld2 = np.linalg.slogdet(M2)[1]
+    ld1 = np.linalg.slogdet(Mpc)[1]
+    ldK = np.linalg.slogdet(L.m5d_matrix(Ls, M5, MF))[1]
+    assert abs(ld2 - (ld1 - 8 * 3 * ldK)) < 1e-10 * abs(ld1)
+
+
+def test_red_black_solve_form2_matches_dense_solve(small):
+    from oracle import krylov
+
+    dims, Ls, U, shape = small
+    eta = synth.gaussian_fermion(dims, Ls, seed=15)
+    D = L.dense_matrix(lambda v: L.ddw(U, v, M5, MF), shape)
+    psi_dense = np.linalg.solve(D, eta.ravel()).reshape(shape)
+    b = L.mpc2_dag(U, L.schur_source2(U, eta, M5, MF), M5, MF)
+    res = krylov.cg(lambda v: L.mpc2dagmpc2(U, v, M5, MF), b, tol=1e-13, maxiter=2000)
+    assert res.converged
+    psi = res.x + L.reconstruct_odd(U, res.x, eta, M5, MF)
+    assert rel(psi, psi_dense) < 1e-10
+
+
+def test_unpreconditioned_cgnr_matches_dense_solve(small):
+    """CGNR on D_DW^dag D_DW over both parities (the Krylov table's unpreconditioned row)."""
+    from oracle import krylov
+
+    dims, Ls, U, shape = small
+    eta = synth.gaussian_fermion(dims, Ls, seed=16)
+    D = L.dense_matrix(lambda v: L.ddw(U, v, M5, MF), shape)
+    psi_dense = np.linalg.solve(D, eta.ravel()).reshape(shape)
+    b = L.ddw(U, eta, M5, MF, dag=True)
+    res = krylov.cg(lambda v: L.ddw(U, L.ddw(U, v, M5, MF), M5, MF, dag=True), b, tol=1e-13, maxiter=5000)
+    assert res.converged
+    assert rel(res.x, psi_dense) < 1e-10
