@@ -157,6 +157,25 @@ int dwf_set_progress(dwf_handle h, dwf_progress_fn fn, void* user, int every);
 int dwf_solve_rb(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters,
                  double* true_rel_resid);
 
+/* Red-black operator used by dwf_mpc, dwf_mpcdagmpc, dwf_cg, dwf_solve_rb and
+ * dwf_power (Results, Krylov table: the two Schur forms of the preconditioned
+ * operator): form 1 (default) M_pc = M_ee - M_eo M_oo^{-1} M_oe; form 2
+ * M_pc = 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe, whose red-black solve takes the
+ * right-hand side M_ee^{-1} eta'.  The filters, the smoother and the force
+ * are defined on form 1 and return DWF_EINVAL under form 2.  The adjoint
+ * of form 2 (dwf_mpc with dagger) needs out distinct from in. */
+int dwf_set_schur_form(dwf_handle h, int form);
+
+/* SYNCHRONOUS.  Unpreconditioned solve of D_DW psi = eta by CG on
+ * D_DW^dag D_DW psi = D_DW^dag eta over both parities (Results, Krylov table,
+ * the CGNR row), FP64 packed "both" fields, psi holding the initial guess.
+ * Needs a DWF_F64 handle with max_cg_rhs >= 2.  iters and true_rel_resid
+ * (host, may be NULL) receive the iterations and ||b - A psi|| / ||b|| of the
+ * normal equations.  Returns DWF_ENOCONV after maxiter or when stopped by the
+ * progress callback. */
+int dwf_solve_unprec(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters,
+                     double* true_rel_resid);
+
 /* SYNCHRONOUS.  Power method for lambda_max of M_pc^dag M_pc from the start
  * vector v (handle precision, one rhs, overwritten with the last iterate). */
 int dwf_power(dwf_handle h, void* v, int iters, double rtol, double* lambda_max, int* iters_done);

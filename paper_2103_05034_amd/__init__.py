@@ -79,6 +79,8 @@ _PROTOS = {
     "dwf_chebyshev_smoother": (_i, [_vp, _i, _d, _d, _vp, _vp, _i]),
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_set_schur_form": (_i, [_vp, _i]),
+    "dwf_solve_unprec": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p]),
     "dwf_set_blocks": (_i, [_vp, _c_int_p, _c_int_p]),
     "dwf_chiral_split": (_i, [_vp, _vp, _vp, _i]),
     "dwf_block_scratch_bytes": (ctypes.c_size_t, [_vp, _i]),
@@ -282,6 +284,19 @@ class Operator:
         res = ctypes.c_double()
         self._sync_stream()
         code = self.lib.dwf_solve_rb(self.h, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
+        _check(code)
+        return it.value, res.value
+
+    def set_schur_form(self, form):
+        """1: M_ee - M_eo M_oo^-1 M_oe (default); 2: 1 - M_ee^-1 M_eo M_oo^-1 M_oe."""
+        _check(self.lib.dwf_set_schur_form(self.h, int(form)))
+
+    def solve_unprec(self, eta, psi, tol=1e-10, maxiter=100000):
+        """CGNR on D_DW^dag D_DW over both parities; returns (iterations, true residual)."""
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        self._sync_stream()
+        code = self.lib.dwf_solve_unprec(self.h, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
         _check(code)
         return it.value, res.value
 

@@ -129,9 +129,39 @@ size_t fbytes(const dwf_context* c, int prec) { return field_bytes_rhs(c, prec);
 // ---------------------------------------------------------------------------
 // Operator compositions (one chunk of at most the temporaries' capacity).
 // ---------------------------------------------------------------------------
+// Second Schur form (Results, Krylov table): out = in - M5D^{-1} D^{eo} M5D^{-1} D^{oe} in / 4.
+// Adjoint: out = in - D^{oe dag} M5D^{-dag} D^{eo dag} M5D^{-dag} in / 4, with out holding
+// M5D^{-dag} in until the last pass (out must not alias in).
+static hipError_t mpc2_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, int n, int dag,
+                             double* partial) {
+  hipError_t e;
+  const char* src = in;
+  if (dag) {
+    e = launch_site5(c, prec, in, out, 1, 1, n);
+    if (e != hipSuccess) return e;
+    src = out;
+  }
+  HopArgs a{};
+  a.in = src;
+  a.out = t;
+  a.alpha = 1.0;
+  e = launch_hop(c, prec, a, DWF_ODD, dag, EPI_M5INV, n);
+  if (e != hipSuccess) return e;
+  HopArgs b{};
+  b.in = t;
+  b.x = in;
+  b.out = out;
+  b.alpha = -0.25;
+  b.beta = 1.0;
+  b.partial = partial;
+  b.x_after = 1;
+  return launch_hop(c, prec, b, DWF_EVEN, dag, dag ? EPI_LIN : EPI_M5INV, n);
+}
+
 // t_o = M5D^{-1} D_hop^{oe} in ; out = M5D in - D_hop^{eo} t / 4  (optionally |out|^2 partials)
 hipError_t mpc_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, int n, int dag,
                      double* partial = nullptr) {
+  if (c->schur_form == 2) return mpc2_chunk(c, prec, in, out, t, n, dag, partial);
   HopArgs a{};
   a.in = in;
   a.out = t;
@@ -307,6 +337,7 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   c->rpb = 1;
   c->order_mode = 0;
   c->lds_floor = 0;
+  c->schur_form = 1;
   c->timing = false;
   c->ev_used = 0;
   c->ev_ms = 0;
@@ -506,7 +537,13 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
         break;
       }
     }
-    HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs));  // alpha, r -= alpha A p, |r|^2
+    if (h->schur_form == 1) {
+      HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs));  // alpha, r -= alpha A p, |r|^2
+    } else {
+      HIP_TRY(mdagm_pap(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
+      HIP_TRY(scal_alpha(h, nrhs));
+      HIP_TRY(cg_update_r(h, DWF_F64, r, DWF_F64, q, nrhs));
+    }
     HIP_TRY(scal_beta(h, nrhs));
     HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, nrhs));
     HIP_TRY(scal_converge(h, nrhs, tol2, true));
@@ -657,8 +694,13 @@ int dwf_solve_rb(dwf_handle h, const void* eta, void* psi, double tol, int maxit
   a.alpha = 0.5;
   a.beta = 1.0;
   HIP_TRY(launch_hop(h, DWF_F64, a, DWF_EVEN, 0, EPI_LIN, 1));
-  // b = M_pc^dag eta'
-  HIP_TRY(mpc_chunk(h, DWF_F64, psi_o, h->b64, h->t64, 1, 1));
+  // b = M_pc^dag eta' (first form); b = M_pc2^dag M5D^{-1} eta' (second form)
+  if (h->schur_form == 2) {
+    HIP_TRY(launch_site5(h, DWF_F64, psi_o, h->u64, 0, 1, 1));
+    HIP_TRY(mpc_chunk(h, DWF_F64, h->u64, h->b64, h->t64, 1, 1));
+  } else {
+    HIP_TRY(mpc_chunk(h, DWF_F64, psi_o, h->b64, h->t64, 1, 1));
+  }
   int rc = dwf_cg(h, h->b64, psi_e, 1, tol, maxiter, iters, resid);
   if (rc != DWF_OK && rc != DWF_ENOCONV) return rc;
   // psi_o = M5D^{-1} (eta_o + D_hop^{oe} psi_e / 2)
@@ -735,6 +777,7 @@ static int cheb_chunk(dwf_handle h, int order, double lo, double hi, char* V, ch
 int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* vecs, int nvecs) {
   if (int r = check_h(h)) return r;
   if (!vecs || nvecs < 1 || order < 0 || !(hi > lo)) return fail(DWF_EINVAL, "dwf_chebyshev_filter: bad argument");
+  if (h->schur_form != 1) return fail(DWF_EINVAL, "dwf_chebyshev_filter: needs the first Schur form");
   const size_t fb = fbytes(h, h->prec);
   for (int r0 = 0; r0 < nvecs; r0 += h->max_nrhs) {
     const int n = nvecs - r0 < h->max_nrhs ? nvecs - r0 : h->max_nrhs;
@@ -746,6 +789,7 @@ int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* ve
 int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int delta, int nvec, const void* eta,
                          void* out_series) {
   if (int r = check_h(h)) return r;
+  if (h->schur_form != 1) return fail(DWF_EINVAL, "dwf_chebyshev_series: needs the first Schur form");
   if (!eta || !out_series || m < 0 || delta < 1 || nvec < 1 || !(lam_max > lam_lo) || !(lam_max > 0))
     return fail(DWF_EINVAL, "dwf_chebyshev_series: bad argument");
   const int P = h->prec;
@@ -796,6 +840,7 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
   if (int r = check_h(h)) return r;
   if (int r = check_io(in_e, out_e, nrhs)) return r;
   if (order < 1 || !(lo > 0) || !(hi > lo)) return fail(DWF_EINVAL, "dwf_chebyshev_smoother: order >= 1 and 0 < lo < hi");
+  if (h->schur_form != 1) return fail(DWF_EINVAL, "dwf_chebyshev_smoother: needs the first Schur form");
   const int P = h->prec;
   const size_t fb = fbytes(h, P);
   std::vector<double> c;
@@ -865,6 +910,7 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U) {
   if (int r = check_h(h)) return r;
   if (!X_e || !Y_e || !grad_U) return fail(DWF_EINVAL, "dwf_force: null pointer");
   if (h->max_cg_rhs < 1) return fail(DWF_EINVAL, "dwf_force: handle was created without solver workspace");
+  if (h->schur_form != 1) return fail(DWF_EINVAL, "dwf_force: needs the first Schur form");
   const char* X = reinterpret_cast<const char*>(X_e);
   const char* Y = reinterpret_cast<const char*>(Y_e);
   char* Z = h->t64;  // M5D^{-1} M_oe X      (odd)
@@ -1030,6 +1076,83 @@ int dwf_prolong(dwf_handle h, const void* basis, int nvec, const void* coarse, i
   if (v == basis) return fail(DWF_EINVAL, "dwf_prolong: v must not alias the basis");
   HIP_TRY(launch_block_prolong(h, h->prec, reinterpret_cast<const char*>(basis), nvec,
                                reinterpret_cast<const double*>(coarse), nrhs, reinterpret_cast<char*>(v)));
+  return DWF_OK;
+}
+
+int dwf_set_schur_form(dwf_handle h, int form) {
+  if (int r = check_h(h)) return r;
+  if (form != 1 && form != 2) return fail(DWF_EINVAL, "dwf_set_schur_form: form must be 1 or 2");
+  h->schur_form = form;
+  return DWF_OK;
+}
+
+// CGNR on D_DW^dag D_DW over both parities (the Krylov table's unpreconditioned
+// row), driven from the host: every both-parity vector is two half fields, so
+// the BLAS calls run on nrhs = 2 and the two halves' dots are added here.
+int dwf_solve_unprec(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters, double* resid) {
+  if (int r = check_h(h)) return r;
+  if (!eta || !psi || eta == psi) return fail(DWF_EINVAL, "dwf_solve_unprec: eta and psi must be distinct");
+  if (h->prec != DWF_F64) return fail(DWF_EINVAL, "dwf_solve_unprec: needs a DWF_F64 handle");
+  if (h->max_cg_rhs < 2) return fail(DWF_EINVAL, "dwf_solve_unprec: needs max_cg_rhs >= 2 (two half fields per vector)");
+  if (!(tol > 0) || maxiter < 0) return fail(DWF_EINVAL, "dwf_solve_unprec: tol must be > 0 and maxiter >= 0");
+  char* x = reinterpret_cast<char*>(psi);
+  char *b = h->b64, *r = h->r64, *p = h->p64, *q = h->q64, *w = h->t64;
+  std::vector<double> sc;
+  auto dot2 = [&](const char* u, const char* v, double& out) -> int {
+    HIP_TRY(blas_dot(h, DWF_F64, u, DWF_F64, v, 2, S_TMP, false));
+    if (int rc = read_scalars(h, 2, sc)) return rc;
+    out = sc[S_TMP] + sc[NSCAL + S_TMP];
+    return DWF_OK;
+  };
+  auto normal = [&](const char* v, char* out) -> int {  // out = D^dag D v, w = D v
+    if (int rc = dwf_ddw(h, v, w, 1, 0)) return rc;
+    return dwf_ddw(h, w, out, 1, 1);
+  };
+  if (int rc = dwf_ddw(h, eta, b, 1, 1)) return rc;  // b = D^dag eta
+  double bb = 0, rr = 0, pap = 0;
+  if (int rc = dot2(b, b, bb)) return rc;
+  if (int rc = normal(x, q)) return rc;
+  HIP_TRY(blas_copy(h, DWF_F64, b, DWF_F64, r, 2));
+  HIP_TRY(blas_axpby(h, DWF_F64, q, DWF_F64, r, 2, -1.0, 1.0, -1, -1, 1));  // r = b - A x
+  HIP_TRY(blas_copy(h, DWF_F64, r, DWF_F64, p, 2));
+  if (int rc = dot2(r, r, rr)) return rc;
+  const double tol2 = tol * tol;
+  int it = 0, last = 0;
+  bool stopped = false;
+  while (bb > 0 && rr > tol2 * bb && it < maxiter) {
+    if (int rc = normal(p, q)) return rc;
+    if (int rc = dot2(w, w, pap)) return rc;  // p.A p = |D p|^2
+    const double alpha = rr / pap;
+    if (!(pap > 0) || !std::isfinite(alpha)) return fail(DWF_EBREAKDOWN, "dwf_solve_unprec: breakdown");
+    HIP_TRY(blas_axpby(h, DWF_F64, p, DWF_F64, x, 2, alpha, 1.0, -1, -1, 1));
+    HIP_TRY(blas_axpby(h, DWF_F64, q, DWF_F64, r, 2, -alpha, 1.0, -1, -1, 1));
+    double rr_new = 0;
+    if (int rc = dot2(r, r, rr_new)) return rc;
+    ++it;
+    if (h->progress_fn && it - last >= h->progress_every) {
+      last = it;
+      const double rel = std::sqrt(rr_new / bb);
+      if (h->progress_fn(h->progress_user, it, 1, &rel)) {
+        stopped = true;
+        break;
+      }
+    }
+    const double beta = rr_new / rr;
+    rr = rr_new;
+    HIP_TRY(blas_axpby(h, DWF_F64, r, DWF_F64, p, 2, 1.0, beta, -1, -1, 1));
+  }
+  // true residual of the normal equations
+  if (int rc = normal(x, q)) return rc;
+  HIP_TRY(blas_copy(h, DWF_F64, b, DWF_F64, r, 2));
+  HIP_TRY(blas_axpby(h, DWF_F64, q, DWF_F64, r, 2, -1.0, 1.0, -1, -1, 1));
+  double tr = 0;
+  if (int rc = dot2(r, r, tr)) return rc;
+  if (iters) *iters = it;
+  const double rel = bb > 0 ? std::sqrt(tr / bb) : 0.0;
+  if (resid) *resid = rel;
+  if (!std::isfinite(rel)) return fail(DWF_EBREAKDOWN, "dwf_solve_unprec: non-finite residual");
+  if (stopped) return fail(DWF_ENOCONV, "CG stopped by the progress callback");
+  if (bb > 0 && rr > tol2 * bb) return fail(DWF_ENOCONV, "dwf_solve_unprec: no convergence in %d iterations", maxiter);
   return DWF_OK;
 }
 

@@ -261,6 +261,7 @@ struct HopArgs {
   int nrhs;           // right-hand sides of the launch
   int rpb;            // right-hand sides per workgroup (looped, sharing the LDS links)
   const double* scal; // EPI_CGR: per-rhs solver scalars, alpha_cg = scal[rhs * NSCAL + S_ALPHA]
+  int x_after;        // EPI_M5INV: add beta * x after the inverse instead of before
 };
 
 // ---------------------------------------------------------------------------
@@ -310,6 +311,7 @@ struct dwf_context {
   int* order;            // site traversal order per out parity, [2][V4h] (device)
   int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
   int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
+  int schur_form;  // 1: M_ee - M_eo M_oo^{-1} M_oe; 2: 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe
   // coarse-space blocks: extents, count, even sites per block, their half-lattice indices [nb][nsb]
   int blk[4];
   int nb, nsb;

@@ -240,7 +240,8 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
     if (EPI == EPI_LIN || EPI == EPI_M5INV) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = cscale(alpha, acc[c]);
-      if (a.x != nullptr && valid) {
+      const bool x_after = EPI == EPI_M5INV && a.x_after;
+      if (a.x != nullptr && valid && !x_after) {
         cplx<R> xv[12];
         Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
         const R beta = (R)a.beta;
@@ -260,6 +261,13 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
         if (valid) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) v[c] = col[(size_t)(sl * 12 + c) * LP + s];
+          if (x_after && a.x != nullptr) {  // second Schur form: x + M5D^{-1}(alpha Dhop in)
+            cplx<R> xv[12];
+            Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
+            const R beta = (R)a.beta;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) v[c] = {v[c].re + beta * xv[c].re, v[c].im + beta * xv[c].im};
+          }
         }
       }
     } else {  // EPI_M5, EPI_CHEB, EPI_CGR
@@ -331,7 +339,7 @@ __global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
       if (valid) Store<PREC>::store(out, V4h, Ls, h, s, v);
     }
     if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64): p.Ap = |M_pc p|^2, or CG's |r|^2
-      if (EPI != EPI_LIN && EPI != EPI_M5INV) __syncthreads();  // scratch still holds x
+      if (EPI != EPI_LIN) __syncthreads();  // scratch still holds x or the M5D^{-1} columns
       double n2 = 0;
       if (valid) {
 #pragma unroll
