@@ -42,6 +42,7 @@ WORKLOADS = {
     "mixed": dict(dims=(24, 24, 24, 48), Ls=24, M5=1.8, mf=0.00078, eps=0.15, nvec=24, order=32, lo=0.05, hi=60.0),
     "force": dict(dims=(8, 8, 8, 16), Ls=12, M5=1.8, mf=0.01, eps=0.2),
     "copy": dict(bytes=4 << 30),
+    "krylov": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, tol=1e-10),
     # Algorithm A: 4x2x4x2 blocks, 40 basis vectors; Algorithm B: 2^4 blocks, 32 (both chirality-split)
     "coarse": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, algos={"A": ((4, 2, 4, 2), 20), "B": ((2, 2, 2, 2), 16)}),
 }
@@ -687,7 +688,58 @@ def run_coarse(args):
     }
 
 
-RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force, "copy": run_copy, "coarse": run_coarse}
+def run_krylov(args):
+    """The Krylov table's FP64 rows on the 16^3x32, Ls=16 synthetic links: red-black CGNR with
+    the first and the second Schur form, and unpreconditioned CGNR on D_DW^dag D_DW, all
+    solving one D_DW psi = eta to 1e-10; iterations, full-lattice matrix multiplies (one
+    red-black iteration or one CGNR iteration = 2) and time to solution."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["krylov"]
+    dims, Ls = cfg["dims"], cfg["Ls"]
+    X, Y, Z, T = dims
+    V5 = X * Y * Z * T * Ls
+    U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
+    op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=2)
+    op.autotune(1, 3)
+    eta = op.pack(torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=1)[None]).cuda(), dwf.DWF_BOTH)
+    rows = {}
+    op.set_progress(lambda it, rel: log(f"  it={it} rel={rel[0]:.2e}") and False, every=1000)
+    for name, form in (("prec-CGNR form 1", 1), ("prec-CGNR form 2", 2), ("CGNR unpreconditioned", 0)):
+        psi = op.new_field(1, both=True)
+        if form:
+            op.set_schur_form(form)
+            t, (it, res) = _timed(lambda: op.solve_rb(eta, psi, tol=cfg["tol"], maxiter=100000))
+        else:
+            op.set_schur_form(1)
+            t, (it, res) = _timed(lambda: op.solve_unprec(eta, psi, tol=cfg["tol"], maxiter=100000))
+        rows[name] = {"iterations": it, "full_matmuls": 2 * it, "time_s": t, "true_rel_residual": res,
+                      "site_updates_per_s": 2 * V5 * it / t}
+        log(f"{name}: {it} iterations, {t:.3f} s, residual {res:.2e}")
+    op.close()
+    base = rows["prec-CGNR form 1"]
+    return {
+        "metric": METRIC,
+        "value": base["site_updates_per_s"],
+        "unit": "5D site-updates/s (prec-CGNR form 1)",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": base["time_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Krylov table rows, 16^3x32 Ls=16 mf=0.01, links exp(0.2iH), tol 1e-10", **rows},
+    }
+
+
+RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force, "copy": run_copy, "coarse": run_coarse,
+           "krylov": run_krylov}
 
 
 def main():
