@@ -277,7 +277,9 @@ int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_
 /* SYNCHRONOUS.  Traversal order of the half-lattice sites in the hop kernels:
  * 0 = lexicographic (x fastest, t slowest); 1 = the (x,y,z) box split into
  * 2x2x2 sub-boxes, one per XCD, each streamed with t slowest (needs X, Y, Z
- * divisible by 4).  Results do not depend on the order. */
+ * divisible by 4); 2 = eight slabs of consecutive t, one per XCD, each
+ * streamed with t fastest, then x, z, y (needs T divisible by 8).  Results
+ * do not depend on the order. */
 int dwf_set_order(dwf_handle h, int mode);
 
 /* Cap the resident hop workgroups per compute unit (0 = no cap) by reserving

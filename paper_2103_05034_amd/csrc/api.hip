@@ -969,6 +969,23 @@ static bool build_order(const Geom& g, int mode, std::vector<int>& ord) {
     }
     return true;
   }
+  if (mode == 2) {
+    // eight slabs of consecutive t, one per XCD; inside a slab t runs fastest,
+    // then x, z, y, so the z- and t-neighbours of a site are visited soon after it
+    if (g.T % 8) return false;
+    const int st = g.T / 8;
+    for (int p = 0; p < 2; ++p) {
+      size_t k = (size_t)p * g.V4h;
+      for (int slab = 0; slab < 8; ++slab)
+        for (int y = 0; y < g.Y; ++y)
+          for (int z = 0; z < g.Z; ++z)
+            for (int x = 0; x < g.X; ++x)
+              for (int t = slab * st; t < (slab + 1) * st; ++t)
+                if (((x + y + z + t) & 1) == p) ord[k++] = (int)half_index(g, x, y, z, t);
+      if (k != (size_t)(p + 1) * g.V4h) return false;
+    }
+    return true;
+  }
   return false;
 }
 

@@ -49,7 +49,7 @@ def _workload(dims, Ls, eps, prec, nrhs=1, mf=0.01, seed_src=1, max_cg_rhs=0):
     return op, U
 
 
-@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("order", [0, 1, 2])
 def test_rb_workload_fp64_sampled(order):
     """16^3 x 32, Ls = 16, FP64 (the red-black solve workload): D_hop, M_pc and
     M_pc^dag M_pc at sampled sites, in the autotuned launch shape."""

@@ -159,16 +159,17 @@ def test_repeat_is_bitwise_deterministic():
     assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("prec", [F64, F32, F16S])
-def test_traversal_order_gives_identical_results(prec):
-    """The XCD-octant traversal only permutes which workgroup computes a site."""
-    dims, Ls = (8, 4, 4, 6), 6
+def test_traversal_order_gives_identical_results(prec, order):
+    """The XCD-octant and t-slab traversals only permute which workgroup computes a site."""
+    dims, Ls = (8, 4, 4, 8), 6
     op, U = make_operator(dims, Ls, seed=17, prec=prec)
     nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 2, seed=18)])
     inp = pack(op, nat, EVEN)
     a, b = op.new_field(2), op.new_field(2)
     op.mpcdagmpc(inp, a, 2)
-    op.set_order(1)
+    op.set_order(order)
     op.mpcdagmpc(inp, b, 2)
     import torch
 
