@@ -185,8 +185,19 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 // MULTI: the workgroup loops over rpb right-hand sides (links staged once);
 // without it the body runs once, which keeps the loop-carried addresses out of
 // the register budget of the common single-rhs launches.
+// Minimum waves per SIMD the compiler must leave room for.  The single-rhs
+// FP32 and FP16S kernels gain from holding three (fewer registers, more
+// waves); the FP64 kernels keep the scheduler's own choice, which holds more
+// loads in flight per wave and measured faster than any cap, and so do the
+// multi-rhs kernels, which would spill under it.
+template <int PREC, bool MULTI>
+struct HopOccupancy {
+  static constexpr int waves = (PREC == DWF_F64 || MULTI) ? 1 : 3;
+};
+
 template <int PREC, bool DAG, int EPI, int DEPTH, bool MULTI>
-__global__ void __launch_bounds__(256) hop_kernel(HopArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOccupancy<PREC, MULTI>::waves)))
+hop_kernel(HopArgs a) {
   using R = typename Store<PREC>::real;
   using V = typename LinkT<R>::vec;
   extern __shared__ char smem_raw[];
