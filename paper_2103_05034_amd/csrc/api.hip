@@ -1068,7 +1068,7 @@ int dwf_block_orthonormalize(dwf_handle h, void* basis, int nvec, void* scratch,
   char* q = reinterpret_cast<char*>(basis);
   HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
   for (int pass = 0; pass < 2; ++pass) {  // Cholesky QR, twice
-    HIP_TRY(launch_block_dot(h, h->prec, q, nvec, q, nvec, gram, true));
+    HIP_TRY(launch_block_gram(h, h->prec, q, nvec, gram));
     HIP_TRY(launch_block_cholesky(h, gram, w, nvec, flag));
     HIP_TRY(launch_block_apply(h, h->prec, q, nvec, w));
   }

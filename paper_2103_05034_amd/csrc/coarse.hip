@@ -166,6 +166,94 @@ __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
   }
 }
 
+// Gram matrix of every block, G[b][k][j] = <phi_j^b, phi_k^b> for j <= k, with
+// each basis vector read once: the block's rows (5D site x colour-spin
+// component) pass through LDS in chunks of `chunk` 5D sites, all nvec
+// vectors at once, and every thread accumulates 2 x 2 tiles of (j, k) pairs
+// in FP64 from the staged rows.
+constexpr int GRAM_TPT = 4;  // tiles per thread: (n/2)(n/2+1)/2 <= 528 for n <= 64
+
+template <int P>
+__global__ void __launch_bounds__(256) block_gram_kernel(BlockArgs a, int chunk) {
+  using R = typename Store<P>::real;
+  extern __shared__ char smem[];
+  cplx<R>* sm = reinterpret_cast<cplx<R>*>(smem);  // [chunk * 12][n]
+  const int b = blockIdx.x;
+  const int n = a.nvec;
+  const int Ls = a.g.Ls;
+  const int np = a.nsb * Ls;
+  const int half = (n + 1) / 2;
+  const int ntiles = half * (half + 1) / 2;
+  double acc[GRAM_TPT][8];
+  int ta[GRAM_TPT], tb[GRAM_TPT];
+#pragma unroll
+  for (int q = 0; q < GRAM_TPT; ++q) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[q][i] = 0;
+    // tile index -> (ta <= tb): row-major over the upper triangle
+    int t = threadIdx.x + q * blockDim.x, row = 0;
+    while (t >= half - row && row < half) {
+      t -= half - row;
+      ++row;
+    }
+    ta[q] = row;
+    tb[q] = row + t;
+  }
+  for (int p0 = 0; p0 < np; p0 += chunk) {
+    const int cs = min(chunk, np - p0);
+    __syncthreads();  // previous chunk consumed
+    for (int item = threadIdx.x; item < cs * n; item += blockDim.x) {
+      const int j = item / cs, pl = item - j * cs;  // consecutive threads: consecutive 5D sites
+      const int p = p0 + pl;
+      const int site = p / Ls, s = p - site * Ls;
+      const long long h = a.bsite[(size_t)b * a.nsb + site];
+      cplx<R> f[12];
+      Store<P>::load(a.basis + (size_t)j * a.stride, a.g.V4h, Ls, h, s, f);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) sm[(size_t)(pl * 12 + c) * n + j] = f[c];
+    }
+    __syncthreads();
+    const int rows = cs * 12;
+#pragma unroll
+    for (int q = 0; q < GRAM_TPT; ++q) {
+      if (threadIdx.x + q * blockDim.x >= ntiles) continue;
+      const int j0 = 2 * ta[q], k0 = 2 * tb[q];
+      const bool j1 = j0 + 1 < n, k1 = k0 + 1 < n;
+      for (int r = 0; r < rows; ++r) {
+        const cplx<R>* row = sm + (size_t)r * n;
+        const cplx<R> x0 = row[j0], y0 = row[k0];
+        const cplx<R> x1 = j1 ? row[j0 + 1] : cplx<R>{0, 0};
+        const cplx<R> y1 = k1 ? row[k0 + 1] : cplx<R>{0, 0};
+        // conj(x) y
+        acc[q][0] = fma((double)x0.re, (double)y0.re, fma((double)x0.im, (double)y0.im, acc[q][0]));
+        acc[q][1] = fma((double)x0.re, (double)y0.im, fma(-(double)x0.im, (double)y0.re, acc[q][1]));
+        acc[q][2] = fma((double)x0.re, (double)y1.re, fma((double)x0.im, (double)y1.im, acc[q][2]));
+        acc[q][3] = fma((double)x0.re, (double)y1.im, fma(-(double)x0.im, (double)y1.re, acc[q][3]));
+        acc[q][4] = fma((double)x1.re, (double)y0.re, fma((double)x1.im, (double)y0.im, acc[q][4]));
+        acc[q][5] = fma((double)x1.re, (double)y0.im, fma(-(double)x1.im, (double)y0.re, acc[q][5]));
+        acc[q][6] = fma((double)x1.re, (double)y1.re, fma((double)x1.im, (double)y1.im, acc[q][6]));
+        acc[q][7] = fma((double)x1.re, (double)y1.im, fma(-(double)x1.im, (double)y1.re, acc[q][7]));
+      }
+    }
+  }
+  // G[b][k][j] = <phi_j, phi_k>, j <= k
+  double* G = a.coef + 2 * (size_t)b * n * n;
+#pragma unroll
+  for (int q = 0; q < GRAM_TPT; ++q) {
+    if (threadIdx.x + q * blockDim.x >= ntiles) continue;
+    const int j0 = 2 * ta[q], k0 = 2 * tb[q];
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int dk = 0; dk < 2; ++dk) {
+        const int j = j0 + dj, k = k0 + dk;
+        if (j >= n || k >= n || j > k) continue;
+        G[2 * (k * n + j)] = acc[q][2 * (2 * dj + dk)];
+        G[2 * (k * n + j) + 1] = acc[q][2 * (2 * dj + dk) + 1];
+      }
+  }
+}
+
 // INPLACE = false: out_r = sum_k coef[r][b][k] phi_k^b for the KT right-hand
 //   sides r = blockIdx.y * KT + ...
 // INPLACE = true: phi_k <- sum_{j<=k} W[b][j][k] phi_j^b for every k, one
@@ -395,6 +483,22 @@ hipError_t launch_block_apply(dwf_context* c, int prec, char* basis, int nvec, c
     case DWF_F64: combine_t<DWF_F64, 2, true>(c, a); break;
     case DWF_F32: combine_t<DWF_F32, 2, true>(c, a); break;
     default: combine_t<DWF_F16S, 2, true>(c, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_gram(dwf_context* c, int prec, const char* basis, int nvec, double* gram) {
+  BlockArgs a = block_args(c, prec, basis, nvec);
+  a.coef = gram;
+  const size_t cb = prec == DWF_F64 ? 16 : 8;
+  const size_t budget = 48 * 1024;
+  int chunk = (int)(budget / (12 * (size_t)nvec * cb));  // 5D sites staged per pass
+  if (chunk < 1) chunk = 1;
+  const size_t lds = (size_t)chunk * 12 * nvec * cb;
+  switch (prec) {
+    case DWF_F64: hipLaunchKernelGGL(block_gram_kernel<DWF_F64>, dim3(a.nb), dim3(256), lds, c->stream, a, chunk); break;
+    case DWF_F32: hipLaunchKernelGGL(block_gram_kernel<DWF_F32>, dim3(a.nb), dim3(256), lds, c->stream, a, chunk); break;
+    default: hipLaunchKernelGGL(block_gram_kernel<DWF_F16S>, dim3(a.nb), dim3(256), lds, c->stream, a, chunk); break;
   }
   return hipGetLastError();
 }

@@ -88,6 +88,8 @@ hipError_t launch_block_prolong(dwf_context* c, int prec, const char* basis, int
                                 char* out);
 // phi_k <- sum_{j<=k} W[b][j][k] phi_j^b in place
 hipError_t launch_block_apply(dwf_context* c, int prec, char* basis, int nvec, const double* wmat);
+// per block: Gram matrix [b][k][j] = <phi_j, phi_k> (j <= k) with each vector read once
+hipError_t launch_block_gram(dwf_context* c, int prec, const char* basis, int nvec, double* gram);
 // per block: Cholesky of the Gram matrix ([b][k][j] = <phi_j, phi_k>) and W = R^{-1}
 hipError_t launch_block_cholesky(dwf_context* c, const double* gram, double* w, int nvec, int* flag);
 
