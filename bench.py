@@ -281,6 +281,13 @@ def run_rb_solve(args):
             "avg_launch_ms": avg_ms,
             "launches": hop_launches,
         },
+        "context": {
+            "paper_rb_cgnr_per_summit_node": 2.18e8,
+            "note": "derived, not published: 6448 full matmuls in 62 s on 16^3x32x16 (4 V100, FP64, "
+            "RBC configuration at m=0.001; Results, Krylov table); another machine and other links, so "
+            "context only, not a baseline",
+            "this_gpu_over_that_node": value / 2.18e8,
+        },
         "operator": {
             "mpcdagmpc_ms": ms_app,
             "mpcdagmpc_site_updates_per_s": 2 * V5 / (ms_app * 1e-3),
