@@ -182,3 +182,28 @@ def test_force_workload_c4():
         assert abs(fd - an) < 1e-6 * max(abs(an), 1e-2 * np.abs(G).max()), (t, z, y, x, mu, fd, an)
         op_p.close()
         op_m.close()
+
+
+def test_mixed_workload_fp32_field_solve_sampled():
+    """24^3 x 48, Ls = 24, mf = 0.00078: the mixed workload's solve (FP32 fields, FP64
+    reliable updates) reaches the FP64 true residual, and the oracle's M_pc^dag M_pc
+    applied to the GPU solution on patches around sampled sites reproduces b there."""
+    import torch
+
+    dims, Ls, mf = (24, 24, 24, 48), 24, 0.00078
+    U = synth.gauge_links(dims, eps=0.15, seed=0)
+    psi = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=5), EVEN)
+    op64, _ = make_operator(dims, Ls, prec=F64, mf=mf, U=U, max_nrhs=1, max_cg_rhs=0)
+    b = pack(op64, psi[None], EVEN)
+    op32, _ = make_operator(dims, Ls, prec=F32, mf=mf, U=U, max_nrhs=1, max_cg_rhs=1)
+    x = op32.new_field(1, prec=F64)
+    code, iters, res = op32.cg(b, x, 1, tol=1e-10, maxiter=5000)
+    assert code == 0 and res[0] < 1.5e-10
+    op32.close()
+    del op32
+    torch.cuda.empty_cache()
+    X = unpack(op64, x, 1, EVEN)[0]
+    sites = sample_sites(dims, 2, seed=11, parity=EVEN)
+    Ax = oracle_at_sites(lambda u, p: L.mpcdagmpc(u, L.on_parity(p, EVEN), 1.8, mf), U, X, dims, sites, 4)
+    bs = gpu_at_sites(psi, sites)
+    assert rel(Ax, bs) < 1e-7
