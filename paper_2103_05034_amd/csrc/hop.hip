@@ -214,21 +214,43 @@ hop_kernel(HopArgs a) {
   const long long V4h = a.V4h;
   const long long h0 = (long long)logical * spb;  // first processing index of the workgroup
   const bool valid = (sl < spb) && (h0 + sl < V4h);
-  const long long h = a.order ? (valid ? (long long)a.order[h0 + sl] : 0) : h0 + sl;
+  // index loads are unconditional (clamped to site 0 on idle lanes), so the
+  // eight neighbour indices are fetched in one round trip instead of eight
+  const long long hq = valid ? h0 + sl : 0;
+  const long long h = a.order ? (long long)a.order[hq] : hq;
 
   int nh[8];
 #pragma unroll
-  for (int d = 0; d < 8; ++d) nh[d] = valid ? a.nbr[(size_t)d * V4h + h] : 0;
-  // stage this workgroup's links once; every rhs the workgroup handles reuses them
+  for (int d = 0; d < 8; ++d) nh[d] = a.nbr[(size_t)d * V4h + h];
+  // The workgroup's site indices go through LDS, so that the link loads below
+  // carry no dependent lookup of the traversal order.
+  __shared__ int site_h[256];
+  if (s == 0 && sl < spb) site_h[sl] = valid ? (int)h : -1;
+  __syncthreads();
+  // Stage this workgroup's links once; every rhs the workgroup handles reuses
+  // them.  A thread issues all its link loads (up to eight) before its first
+  // LDS store, so the staging costs one memory round trip.
   {
+    constexpr int U = 8;
     const V* lg = reinterpret_cast<const V*>(a.links);
-    for (int idx = tid; idx < spb * 72; idx += blockDim.x) {
-      const int dk = idx / spb;
-      const int sl2 = idx - dk * spb;
-      const long long i2 = h0 + sl2;
-      const long long h2 = (i2 < V4h) ? (a.order ? (long long)a.order[i2] : i2) : -1;
-      V t = (h2 >= 0) ? lg[(size_t)dk * V4h + h2] : V{0, 0};
-      ll[idx] = {t.x, t.y};
+    const int total = spb * 72;
+    for (int base = 0; base < total; base += U * (int)blockDim.x) {
+      V t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * (int)blockDim.x + tid;
+        t[u] = V{0, 0};
+        if (idx < total) {
+          const int dk = idx / spb;
+          const int h2 = site_h[idx - dk * spb];
+          if (h2 >= 0) t[u] = lg[(size_t)dk * V4h + h2];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * (int)blockDim.x + tid;
+        if (idx < total) ll[idx] = {t[u].x, t[u].y};
+      }
     }
   }
   const R alpha = (R)a.alpha;
