@@ -222,6 +222,14 @@ int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
  * handle's precision and need dwf_set_blocks first. */
 int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks);
 
+/* As dwf_set_blocks, with parity = DWF_EVEN (the same) or DWF_BOTH: then the
+ * coarse-space calls below take fields of both parities in the packed
+ * "both" layout (for n fields: the n even halves, then the n odd halves),
+ * a block holds all bx*by*bz*bt of its sites (sites per block x Ls <= 512),
+ * and dwf_chiral_split writes its 2 nvec outputs in the same layout.  The
+ * two-level solver (below) coarsens the full-lattice H_DW this way. */
+int dwf_set_blocks_ex(dwf_handle h, const int block[4], int parity, int* nblocks);
+
 /* Chirality split of nvec fields (Deflation basis setup section: the
  * filtered vectors are projected with 1 +- Gamma_5 before coarsening the
  * five-dimensional operator): out[2k] = (1 + Gamma_5) in[k] / 2 and
@@ -254,6 +262,101 @@ int dwf_restrict(dwf_handle h, const void* basis, int nvec, const void* v, int n
  * accumulation, stored in the handle's precision.  v must not alias the
  * basis. */
 int dwf_prolong(dwf_handle h, const void* basis, int nvec, const void* coarse, int nrhs, void* v);
+
+/* ---- two-level HDCR solver (FP64, fields of both parities) ---------------- */
+
+/* out = H_DW in = Gamma_5 D_DW in, (Gamma_5 v)_s = gamma_5 v_{Ls-1-s} (Spectrum
+ * of domain wall fermions section), for nrhs packed "both" fields.  Needs a
+ * DWF_F64 handle with max_cg_rhs >= 1. */
+int dwf_hdw(dwf_handle h, const void* in, void* out, int nrhs);
+
+/* Parameters of Algorithms A / B (their table): the smoother
+ * S_cheb([smoother_lo, smoother_hi], smoother_order) of the Chebyshev
+ * smoothers section with M = H_DW; the coarse solve, CG on the normal
+ * equations of the little Dirac operator stopped at relative residual
+ * coarse_tol of those equations or after coarse_maxiter iterations; and the
+ * outer GCR restarted every nkrylov directions. */
+typedef struct {
+  int smoother_order;
+  double smoother_lo, smoother_hi;
+  double coarse_tol;
+  int coarse_maxiter;
+  int nkrylov;
+} dwf_hdcr_params;
+
+typedef struct dwf_hdcr_s* dwf_hdcr;
+
+/* Device workspace (bytes) of an HDCR solver with nvec basis vectors and
+ * nkrylov outer directions under the handle's current DWF_BOTH blocks: the
+ * stencil of the little Dirac operator (nblocks x 9 x nvec^2 complex128),
+ * coarse vectors, and 11 + 2 nkrylov FP64 fields of both parities.  0 if
+ * blocks are not set with DWF_BOTH or an argument is out of range. */
+size_t dwf_hdcr_workspace_bytes(dwf_handle h, int nvec, int nkrylov);
+
+/* Create a solver on a DWF_F64 handle whose blocks were set with
+ * dwf_set_blocks_ex(..., DWF_BOTH, ...); 1 <= nvec <= 64, 1 <= nkrylov <= 64,
+ * smoother_order >= 1, 0 < smoother_lo < smoother_hi, coarse_tol > 0.  The
+ * caller owns ws (>= dwf_hdcr_workspace_bytes) and keeps it, and the handle,
+ * alive until dwf_hdcr_destroy.  Calls on the solver fail with DWF_EINVAL
+ * if the handle's blocks are changed afterwards. */
+int dwf_hdcr_create(dwf_handle h, int nvec, const dwf_hdcr_params* params, void* ws, size_t ws_bytes,
+                    dwf_hdcr* out);
+int dwf_hdcr_destroy(dwf_hdcr hd);
+
+/* In place: vecs <- T_order(x(D_DW^dag D_DW)) vecs, x(A) = 2 (A - lo)/(hi - lo) - 1,
+ * for nvecs fields of both parities (packed "both" layout), the setup filter
+ * of the Deflation basis setup section on the five-dimensional squared
+ * operator that Algorithms A / B coarsen.  No normalisation. */
+int dwf_hdcr_filter(dwf_hdcr hd, int order, double lo, double hi, void* vecs, int nvecs);
+
+/* SYNCHRONOUS.  Use basis (nvec packed "both" fields, normally chirally split
+ * and block-orthonormalised with the DWF_BOTH blocks) as the blocked basis
+ * phi_k^b and build the little Dirac operator A^{ab}_{jk} = <phi_j^a | H_DW |
+ * phi_k^b> (Two level preconditioner section).  The basis stays owned by
+ * the caller and must stay unchanged while the solver uses it. */
+int dwf_hdcr_set_basis(dwf_hdcr hd, const void* basis);
+
+/* Device pointer to the little Dirac operator, a 9-point stencil over the
+ * block grid: complex128 [nblocks][9][nvec][nvec], entry (j, k) of stencil
+ * point d at (d * nvec + k) * nvec + j.  Point d < 8 couples block b to the
+ * block that hop direction d leads to (d = 2 mu + 0 forward / 1 backward,
+ * mu = x, y, z, t), point 8 to b itself.  NULL for a null solver. */
+const void* dwf_hdcr_coarse_data(dwf_hdcr hd);
+
+/* y = A x for one coarse vector (complex128 [nblocks][nvec], device). */
+int dwf_hdcr_coarse_apply(dwf_hdcr hd, const void* x, void* y);
+
+/* SYNCHRONOUS.  c = A^{-1} d by CG on A^dag A c = A^dag d from c = 0 (A is
+ * Hermitian), stopped when the normal equations' relative residual is
+ * <= tol or after maxiter iterations; *iters (host, may be NULL) receives
+ * the count.  d and c are coarse vectors (device); the solver's coarse
+ * work vectors are overwritten. */
+int dwf_hdcr_coarse_solve(dwf_hdcr hd, const void* d, void* c, double tol, int maxiter, int* iters);
+
+/* out = S_cheb([lo, hi], N) r with M = H_DW: [c_0/2 + sum_{j=1}^N c_j
+ * T_j(x(H_DW^2))] H_DW r (Chebyshev smoothers section), one field of both
+ * parities; r and out distinct. */
+int dwf_hdcr_smoother(dwf_hdcr hd, const void* r, void* out);
+
+/* SYNCHRONOUS.  x = one V(1,1) cycle applied to r (Composite V(1,1) section):
+ * x1 = S r, x2 = x1 + Q (r - H_DW x1), x = x2 + S (r - H_DW x2) with
+ * Q = P A^{-1} P^dag from the coarse solve; *coarse_iters (may be NULL)
+ * receives the coarse CG iterations.  r and x distinct. */
+int dwf_hdcr_vcycle(dwf_hdcr hd, const void* r, void* x, int* coarse_iters);
+
+/* SYNCHRONOUS.  Solve D_DW psi = eta (one field of both parities; psi holds
+ * the initial guess) as H_DW psi = Gamma_5 eta by flexible GCR with the
+ * V(1,1) cycle as right preconditioner (pGCR(H_DW) of Algorithms A / B):
+ * each direction z = V(1,1) r, w = H_DW z, w made orthonormal to the
+ * earlier w by modified Gram-Schmidt (the same combination applied to z),
+ * psi += <w, r> z, r -= <w, r> w; restarted from the true residual every
+ * nkrylov directions.  Stops when ||r|| <= tol ||Gamma_5 eta||.  iters,
+ * true_rel_resid (||Gamma_5 eta - H_DW psi|| / ||eta||) and coarse_iters (the
+ * coarse CG iterations of all cycles) are host outputs, each may be NULL.
+ * Reports progress through dwf_set_progress.  Returns DWF_ENOCONV after
+ * maxiter directions or when stopped by the progress callback. */
+int dwf_hdcr_solve(dwf_hdcr hd, const void* eta, void* psi, double tol, int maxiter, int* iters,
+                   double* true_rel_resid, int* coarse_iters);
 
 /* ---- HMC force ------------------------------------------------------------ */
 

@@ -52,6 +52,19 @@ _vp = ctypes.c_void_p
 _i = ctypes.c_int
 _d = ctypes.c_double
 # int (*)(void* user, int iteration, int nrhs, const double* rel_resid)
+class HDCRParams(ctypes.Structure):
+    """dwf_hdcr_params of include/dwf.h."""
+
+    _fields_ = [
+        ("smoother_order", ctypes.c_int),
+        ("smoother_lo", ctypes.c_double),
+        ("smoother_hi", ctypes.c_double),
+        ("coarse_tol", ctypes.c_double),
+        ("coarse_maxiter", ctypes.c_int),
+        ("nkrylov", ctypes.c_int),
+    ]
+
+
 PROGRESS_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double))
 
 # name -> (restype, argtypes); mirrors include/dwf.h
@@ -82,6 +95,19 @@ _PROTOS = {
     "dwf_set_schur_form": (_i, [_vp, _i]),
     "dwf_solve_unprec": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p]),
     "dwf_set_blocks": (_i, [_vp, _c_int_p, _c_int_p]),
+    "dwf_set_blocks_ex": (_i, [_vp, _c_int_p, _i, _c_int_p]),
+    "dwf_hdw": (_i, [_vp, _vp, _vp, _i]),
+    "dwf_hdcr_workspace_bytes": (ctypes.c_size_t, [_vp, _i, _i]),
+    "dwf_hdcr_create": (_i, [_vp, _i, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
+    "dwf_hdcr_destroy": (_i, [_vp]),
+    "dwf_hdcr_filter": (_i, [_vp, _i, _d, _d, _vp, _i]),
+    "dwf_hdcr_set_basis": (_i, [_vp, _vp]),
+    "dwf_hdcr_coarse_data": (_vp, [_vp]),
+    "dwf_hdcr_coarse_apply": (_i, [_vp, _vp, _vp]),
+    "dwf_hdcr_coarse_solve": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p]),
+    "dwf_hdcr_smoother": (_i, [_vp, _vp, _vp]),
+    "dwf_hdcr_vcycle": (_i, [_vp, _vp, _vp, _c_int_p]),
+    "dwf_hdcr_solve": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p, _c_int_p]),
     "dwf_chiral_split": (_i, [_vp, _vp, _vp, _i]),
     "dwf_block_scratch_bytes": (ctypes.c_size_t, [_vp, _i]),
     "dwf_block_orthonormalize": (_i, [_vp, _vp, _i, _vp, ctypes.c_size_t]),
@@ -332,17 +358,25 @@ class Operator:
         return r[..., 0] + 1j * r[..., 1]
 
     # ---- coarse-space transfer -----------------------------------------------------
-    def set_blocks(self, block):
-        """Blocks of bx, by, bz, bt 4D sites (all Ls slices); returns the number of blocks."""
+    def set_blocks(self, block, both=False):
+        """Blocks of bx, by, bz, bt 4D sites (all Ls slices); returns the number of blocks.
+        both=True makes the coarse-space calls take fields of both parities."""
         nb = ctypes.c_int()
-        _check(self.lib.dwf_set_blocks(self.h, (ctypes.c_int * 4)(*[int(b) for b in block]), ctypes.byref(nb)))
+        par = DWF_BOTH if both else DWF_EVEN
+        _check(self.lib.dwf_set_blocks_ex(self.h, (ctypes.c_int * 4)(*[int(b) for b in block]), par, ctypes.byref(nb)))
         self.nblocks = nb.value
+        self.coarse_both = bool(both)
         return nb.value
+
+    def hdw(self, inp, out, nrhs=1):
+        """out = H_DW inp = Gamma_5 D_DW inp (packed fields of both parities)."""
+        self._sync_stream()
+        _check(self.lib.dwf_hdw(self.h, _ptr(inp), _ptr(out), nrhs))
 
     def chiral_split(self, vecs, nvec, out=None):
         """out[2k], out[2k+1] = (1 +- Gamma_5) vecs[k] / 2."""
         if out is None:
-            out = self.new_field(2 * nvec)
+            out = self.new_field(2 * nvec, both=getattr(self, "coarse_both", False))
         self._sync_stream()
         _check(self.lib.dwf_chiral_split(self.h, _ptr(vecs), _ptr(out), nvec))
         return out
@@ -371,7 +405,7 @@ class Operator:
     def prolong(self, basis, nvec, coarse, nrhs=1, out=None):
         """out_r = sum_{b,k} coarse[r][b][k] phi_k^b."""
         if out is None:
-            out = self.new_field(nrhs)
+            out = self.new_field(nrhs, both=getattr(self, "coarse_both", False))
         self._sync_stream()
         _check(self.lib.dwf_prolong(self.h, _ptr(basis), nvec, _ptr(coarse.contiguous()), nrhs, _ptr(out)))
         return out
@@ -438,6 +472,105 @@ class Operator:
         if getattr(self, "h", None):
             self.lib.dwf_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HDCR:
+    """Two-level HDCR solver (pGCR(H_DW) with the V(1,1) preconditioner) on an
+    FP64 :class:`Operator` whose blocks were set with ``set_blocks(block, both=True)``."""
+
+    def __init__(self, op, nvec, smoother_order=12, smoother_lo=0.5, smoother_hi=60.0, coarse_tol=0.02,
+                 coarse_maxiter=1000, nkrylov=8):
+        import torch
+
+        self.op, self.lib, self.nvec = op, op.lib, nvec
+        self.params = HDCRParams(smoother_order, smoother_lo, smoother_hi, coarse_tol, coarse_maxiter, nkrylov)
+        nbytes = self.lib.dwf_hdcr_workspace_bytes(op.h, nvec, nkrylov)
+        if nbytes == 0:
+            raise DWFError(DWF_EINVAL, "set DWF_BOTH blocks first; nvec and nkrylov must be in [1, 64]")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=op.device)
+        hd = _vp()
+        op._sync_stream()
+        _check(self.lib.dwf_hdcr_create(op.h, nvec, ctypes.byref(self.params), _ptr(self.ws), nbytes, ctypes.byref(hd)))
+        self.hd = hd
+        self.basis = None
+
+    def coarse_vector(self):
+        import torch
+
+        return torch.zeros((self.op.nblocks, self.nvec), dtype=torch.complex128, device=self.op.device)
+
+    def filter(self, vecs, nvecs, order, lo, hi):
+        """vecs <- T_order(x(D^dag D)) vecs for nvecs fields of both parities."""
+        self.op._sync_stream()
+        _check(self.lib.dwf_hdcr_filter(self.hd, order, lo, hi, _ptr(vecs), nvecs))
+
+    def set_basis(self, basis):
+        """Build the little Dirac operator of H_DW on ``basis`` (kept referenced)."""
+        self.op._sync_stream()
+        self.basis = basis
+        _check(self.lib.dwf_hdcr_set_basis(self.hd, _ptr(basis)))
+
+    def coarse_operator(self):
+        """The stencil as a complex128 tensor [nblocks, 9, nvec(k), nvec(j)] viewing the workspace."""
+        import torch
+
+        n, nb = self.nvec, self.op.nblocks
+        off = self.lib.dwf_hdcr_coarse_data(self.hd) - self.ws.data_ptr()
+        raw = self.ws[off : off + nb * 9 * n * n * 16]
+        return raw.view(torch.complex128).view(nb, 9, n, n)
+
+    def coarse_apply(self, x, y=None):
+        if y is None:
+            y = self.coarse_vector()
+        self.op._sync_stream()
+        _check(self.lib.dwf_hdcr_coarse_apply(self.hd, _ptr(x), _ptr(y)))
+        return y
+
+    def coarse_solve(self, d, c=None, tol=1e-10, maxiter=10000):
+        if c is None:
+            c = self.coarse_vector()
+        it = ctypes.c_int()
+        self.op._sync_stream()
+        _check(self.lib.dwf_hdcr_coarse_solve(self.hd, _ptr(d), _ptr(c), tol, maxiter, ctypes.byref(it)))
+        return c, it.value
+
+    def smoother(self, r, out=None):
+        if out is None:
+            out = self.op.new_field(1, both=True)
+        self.op._sync_stream()
+        _check(self.lib.dwf_hdcr_smoother(self.hd, _ptr(r), _ptr(out)))
+        return out
+
+    def vcycle(self, r, x=None):
+        if x is None:
+            x = self.op.new_field(1, both=True)
+        ci = ctypes.c_int()
+        self.op._sync_stream()
+        _check(self.lib.dwf_hdcr_vcycle(self.hd, _ptr(r), _ptr(x), ctypes.byref(ci)))
+        return x, ci.value
+
+    def solve(self, eta, psi, tol=1e-10, maxiter=1000, allow_noconv=False):
+        """D_DW psi = eta; returns (outer iterations, true relative residual, coarse iterations)."""
+        it, ci = ctypes.c_int(), ctypes.c_int()
+        res = ctypes.c_double()
+        self.op._sync_stream()
+        _check(
+            self.lib.dwf_hdcr_solve(self.hd, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res),
+                                    ctypes.byref(ci)),
+            allow=(DWF_ENOCONV,) if allow_noconv else (),
+        )
+        return it.value, res.value, ci.value
+
+    def close(self):
+        if getattr(self, "hd", None):
+            self.lib.dwf_hdcr_destroy(self.hd)
+            self.hd = None
 
     def __del__(self):
         try:

@@ -14,9 +14,10 @@
 using namespace dwf;
 
 namespace {
-
 thread_local std::string g_err = "no error";
+}  // namespace
 
+namespace dwf {
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -27,11 +28,19 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                          \
-  do {                                                                                         \
-    hipError_t e_ = (expr);                                                                    \
-    if (e_ != hipSuccess) return fail(DWF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));       \
-  } while (0)
+int check_h(dwf_handle h) {
+  if (!h) return fail(DWF_EINVAL, "null handle");
+  return DWF_OK;
+}
+
+int sync(dwf_context* c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(DWF_EHIP, "stream synchronize: %s", hipGetErrorString(e));
+  return DWF_OK;
+}
+}  // namespace dwf
+
+namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int GS_MAX = 256;
@@ -108,7 +117,8 @@ size_t carve(dwf_context* c, const int dims[4], int Ls, int prec, int max_nrhs, 
     }
   }
   d->order = reinterpret_cast<int*>(take((size_t)2 * V4h * sizeof(int)));
-  d->bsite = reinterpret_cast<int*>(take((size_t)V4h * sizeof(int)));
+  d->bsite = reinterpret_cast<int*>(take((size_t)2 * V4h * sizeof(int)));
+  d->bnbr = reinterpret_cast<int*>(take((size_t)8 * V4h * sizeof(int)));
   d->hop_partials = max_cg_rhs > 0 ? reinterpret_cast<double*>(take((size_t)max_cg_rhs * V4h * sizeof(double)))
                                     : nullptr;
   int pc = chunk;
@@ -117,11 +127,6 @@ size_t carve(dwf_context* c, const int dims[4], int Ls, int prec, int max_nrhs, 
   d->scalars = reinterpret_cast<double*>(take((size_t)(chunk * NSCAL) * sizeof(double)));
   d->coef = reinterpret_cast<double*>(take((size_t)(4 * GS_MAX + 8) * sizeof(double)));
   return off;
-}
-
-int check_h(dwf_handle h) {
-  if (!h) return fail(DWF_EINVAL, "null handle");
-  return DWF_OK;
 }
 
 size_t fbytes(const dwf_context* c, int prec) { return field_bytes_rhs(c, prec); }
@@ -244,12 +249,6 @@ hipError_t cheb_step(dwf_context* c, int prec, const char* in, char* out, const 
   b.w = w;
   b.cw = cw;
   return launch_hop(c, prec, b, DWF_EVEN, 1, EPI_CHEB, n);
-}
-
-int sync(dwf_context* c) {
-  hipError_t e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return fail(DWF_EHIP, "stream synchronize: %s", hipGetErrorString(e));
-  return DWF_OK;
 }
 
 int read_scalars(dwf_context* c, int nrhs, std::vector<double>& out) {
@@ -993,9 +992,11 @@ static bool build_order(const Geom& g, int mode, std::vector<int>& ord) {
 // Coarse-space transfer (blocks, chirality split, block orthonormalisation,
 // restriction, prolongation)
 // ---------------------------------------------------------------------------
-int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks) {
+int dwf_set_blocks_ex(dwf_handle h, const int block[4], int parity, int* nblocks) {
   if (int r = check_h(h)) return r;
   if (!block) return fail(DWF_EINVAL, "dwf_set_blocks: block is NULL");
+  if (parity != DWF_EVEN && parity != DWF_BOTH) return fail(DWF_EINVAL, "dwf_set_blocks: parity must be DWF_EVEN or DWF_BOTH");
+  const bool both = parity == DWF_BOTH;
   const Geom& g = h->g;
   const int ext[4] = {g.X, g.Y, g.Z, g.T};
   for (int i = 0; i < 4; ++i)
@@ -1004,35 +1005,53 @@ int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks) {
                   i, ext[i]);
   const int vol = block[0] * block[1] * block[2] * block[3];
   if (vol % 2) return fail(DWF_EINVAL, "dwf_set_blocks: the block volume must be even");
-  const int nsb = vol / 2;
+  const int nsb = both ? vol : vol / 2;
   if ((long long)nsb * g.Ls > 512)
-    return fail(DWF_EINVAL, "dwf_set_blocks: even sites per block x Ls = %lld exceeds 512", (long long)nsb * g.Ls);
-  const int nx = g.X / block[0], ny = g.Y / block[1], nz = g.Z / block[2], nt = g.T / block[3];
-  const long long nb = (long long)nx * ny * nz * nt;
-  std::vector<int> tab((size_t)nb * nsb);
-  for (int bt = 0; bt < nt; ++bt)
-    for (int bz = 0; bz < nz; ++bz)
-      for (int by = 0; by < ny; ++by)
-        for (int bx = 0; bx < nx; ++bx) {
-          const long long b = ((long long)(bt * nz + bz) * ny + by) * nx + bx;
-          int j = 0;
+    return fail(DWF_EINVAL, "dwf_set_blocks: %s per block x Ls = %lld exceeds 512", both ? "sites" : "even sites",
+                (long long)nsb * g.Ls);
+  if (both && 2 * g.V4h > (1LL << 31) - 1) return fail(DWF_EINVAL, "dwf_set_blocks: lattice too large for DWF_BOTH");
+  const int n[4] = {g.X / block[0], g.Y / block[1], g.Z / block[2], g.T / block[3]};
+  const long long nb = (long long)n[0] * n[1] * n[2] * n[3];
+  std::vector<int> tab((size_t)nb * nsb), nbt((size_t)nb * 8);
+  for (int bt = 0; bt < n[3]; ++bt)
+    for (int bz = 0; bz < n[2]; ++bz)
+      for (int by = 0; by < n[1]; ++by)
+        for (int bx = 0; bx < n[0]; ++bx) {
+          const long long b = ((long long)(bt * n[2] + bz) * n[1] + by) * n[0] + bx;
+          // neighbouring block in hop direction d = 2 mu + (0 forward, 1 backward)
+          const int bc[4] = {bx, by, bz, bt};
+          for (int d = 0; d < 8; ++d) {
+            int c[4] = {bc[0], bc[1], bc[2], bc[3]};
+            const int mu = d / 2;
+            c[mu] = (c[mu] + (d % 2 ? n[mu] - 1 : 1)) % n[mu];
+            nbt[(size_t)b * 8 + d] = (int)(((long long)(c[3] * n[2] + c[2]) * n[1] + c[1]) * n[0] + c[0]);
+          }
+          int j = 0, odd = 0;
           for (int t = bt * block[3]; t < (bt + 1) * block[3]; ++t)
             for (int z = bz * block[2]; z < (bz + 1) * block[2]; ++z)
               for (int y = by * block[1]; y < (by + 1) * block[1]; ++y)
-                for (int x = bx * block[0]; x < (bx + 1) * block[0]; ++x)
-                  if (((x + y + z + t) & 1) == 0) {
-                    if (j == nsb) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
-                    tab[(size_t)b * nsb + j++] = (int)half_index(g, x, y, z, t);
-                  }
-          if (j != nsb) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
+                for (int x = bx * block[0]; x < (bx + 1) * block[0]; ++x) {
+                  const int par = (x + y + z + t) & 1;
+                  odd += par;
+                  if (par && !both) continue;
+                  if (j == nsb) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
+                  tab[(size_t)b * nsb + j++] = (int)(half_index(g, x, y, z, t) + par * g.V4h);
+                }
+          if (2 * odd != vol) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
         }
   HIP_TRY(hipMemcpyAsync(h->bsite, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipMemcpyAsync(h->bnbr, nbt.data(), nbt.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   for (int i = 0; i < 4; ++i) h->blk[i] = block[i];
   h->nb = (int)nb;
   h->nsb = nsb;
+  h->coarse_both = both ? 1 : 0;
   if (nblocks) *nblocks = (int)nb;
   return DWF_OK;
+}
+
+int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks) {
+  return dwf_set_blocks_ex(h, block, DWF_EVEN, nblocks);
 }
 
 static int check_blocks(dwf_handle h, int nvec, const char* who) {

@@ -1,10 +1,13 @@
-// Coarse-space transfer of the two-level method on even-parity fields.
+// Coarse-space transfer of the two-level method.
 //
 // Blocks (Two level preconditioner section): 4D boxes of bx*by*bz*bt sites
-// tiling the lattice, each taken with all Ls slices; a block holds nsb =
-// bx*by*bz*bt/2 even sites, listed in `bsite[b * nsb + j]` (half-lattice
-// index, block-local lexicographic order).  The blocked basis phi_k^b is a
-// field phi_k restricted to block b.
+// tiling the lattice, each taken with all Ls slices.  On even-parity fields a
+// block holds nsb = bx*by*bz*bt/2 even sites, listed in `bsite[b * nsb + j]`
+// (half-lattice index, block-local lexicographic order).  On fields of both
+// parities (packed "both" layout: the even halves of all n fields, then the
+// odd halves) a block lists all nsb = bx*by*bz*bt sites, an odd site h as
+// h + V4h; its data lies n half fields further on (the parity stride).  The
+// blocked basis phi_k^b is a field phi_k restricted to block b.
 //
 // * chiral_split: P+- v = (v +- Gamma_5 v)/2 with (Gamma_5 v)_s = gamma_5
 //   v_{Ls-1-s}: the five-dimensional chirality used when the domain-wall
@@ -85,8 +88,9 @@ __device__ __forceinline__ void group_sum(double (&v)[NV], double* red) {
 
 struct BlockArgs {
   Geom g;
-  const int* bsite;  // [nb][nsb]
+  const int* bsite;  // [nb][nsb]; odd sites (fields of both parities) as h + V4h
   int nsb, nb;
+  size_t basis_ps, v_ps, out_ps;  // byte offset of the odd halves (fields of both parities)
   const char* basis;  // nvec fields, stride `stride`
   int nvec;
   size_t stride;
@@ -97,6 +101,13 @@ struct BlockArgs {
   int per_block;       // block_dot: lay coef out as [nb][nrhs][nvec] (each block's Gram matrix contiguous)
   const double* wmat;  // block_combine in-place mode: complex [nb][nvec][nvec], W[j][k] at (j * nvec + k)
 };
+
+// Half-lattice site and parity of a block-table entry.
+__device__ __forceinline__ int split_site(long long V4h, long long& h) {
+  const int par = h >= V4h ? 1 : 0;
+  h -= par * V4h;
+  return par;
+}
 
 // c[r][b][k] = <phi_k^b, v_r> for the RT right-hand sides r = blockIdx.y * RT + ...
 template <int P, int RT>
@@ -109,19 +120,22 @@ __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
   const int p = threadIdx.x;
   const bool live = p < np;
   long long h = 0;
-  int s = 0;
+  int s = 0, par = 0;
   if (live) {
     const int j = p / a.g.Ls;
     s = p - j * a.g.Ls;
     h = a.bsite[(size_t)b * a.nsb + j];
+    par = split_site(a.g.V4h, h);
   }
+  const char* vb = a.v + par * a.v_ps;
+  const char* bb = a.basis + par * a.basis_ps;
   cplx<R> v[RT][12];
 #pragma unroll
   for (int r = 0; r < RT; ++r) {
     const bool use = live && (r0 + r < a.nrhs);
 #pragma unroll
     for (int c = 0; c < 12; ++c) v[r][c] = {0, 0};
-    if (use) Store<P>::load(a.v + (size_t)(r0 + r) * a.stride, a.g.V4h, a.g.Ls, h, s, v[r]);
+    if (use) Store<P>::load(vb + (size_t)(r0 + r) * a.stride, a.g.V4h, a.g.Ls, h, s, v[r]);
   }
   // a Gram matrix (per_block) is Hermitian and its Cholesky factorisation reads
   // only the entries with basis index <= rhs index: stop at the tile's last rhs
@@ -134,7 +148,7 @@ __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
     for (int kk = 0; kk < KG; ++kk) {
       if (live && k0 + kk < kend) {
         cplx<R> f[12];
-        Store<P>::load(a.basis + (size_t)(k0 + kk) * a.stride, a.g.V4h, a.g.Ls, h, s, f);
+        Store<P>::load(bb + (size_t)(k0 + kk) * a.stride, a.g.V4h, a.g.Ls, h, s, f);
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
           double re = 0, im = 0;
@@ -206,9 +220,10 @@ __global__ void __launch_bounds__(256) block_gram_kernel(BlockArgs a, int chunk)
       const int j = item / cs, pl = item - j * cs;  // consecutive threads: consecutive 5D sites
       const int p = p0 + pl;
       const int site = p / Ls, s = p - site * Ls;
-      const long long h = a.bsite[(size_t)b * a.nsb + site];
+      long long h = a.bsite[(size_t)b * a.nsb + site];
+      const int par = split_site(a.g.V4h, h);
       cplx<R> f[12];
-      Store<P>::load(a.basis + (size_t)j * a.stride, a.g.V4h, Ls, h, s, f);
+      Store<P>::load(a.basis + par * a.basis_ps + (size_t)j * a.stride, a.g.V4h, Ls, h, s, f);
 #pragma unroll
       for (int c = 0; c < 12; ++c) sm[(size_t)(pl * 12 + c) * n + j] = f[c];
     }
@@ -269,12 +284,15 @@ __global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
   const int p = threadIdx.x;
   const bool live = p < np;
   long long h = 0;
-  int s = 0;
+  int s = 0, par = 0;
   if (live) {
     const int j = p / a.g.Ls;
     s = p - j * a.g.Ls;
     h = a.bsite[(size_t)b * a.nsb + j];
+    par = split_site(a.g.V4h, h);
   }
+  const char* bb = a.basis + par * a.basis_ps;
+  char* ob = a.out + par * a.out_ps;
   const int n = a.nvec;
   if (INPLACE) {
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
@@ -308,7 +326,7 @@ __global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
       for (int c = 0; c < 12; ++c) acc[t][c] = {0, 0};
     for (int j = 0; j < jmax; ++j) {
       cplx<R> f[12];
-      Store<P>::load(a.basis + (size_t)j * a.stride, a.g.V4h, a.g.Ls, h, s, f);
+      Store<P>::load(bb + (size_t)j * a.stride, a.g.V4h, a.g.Ls, h, s, f);
 #pragma unroll
       for (int t = 0; t < KT; ++t) {
         // coefficient of phi_j in output t
@@ -329,7 +347,7 @@ __global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
       cplx<R> o[12];
 #pragma unroll
       for (int c = 0; c < 12; ++c) o[c] = {(R)acc[t][c].re, (R)acc[t][c].im};
-      Store<P>::store(a.out + (size_t)k * a.stride, a.g.V4h, a.g.Ls, h, s, o);
+      Store<P>::store(ob + (size_t)k * a.stride, a.g.V4h, a.g.Ls, h, s, o);
     }
   }
 }
@@ -411,10 +429,15 @@ hipError_t launch_chiral_split(dwf_context* c, int prec, const char* in, char* o
   const long long n = c->g.V4h * c->g.Ls;
   dim3 grid((unsigned)((n + 255) / 256), nvec);
   const size_t st = field_bytes_rhs(c, prec);
-  switch (prec) {
-    case DWF_F64: hipLaunchKernelGGL(chiral_split_kernel<DWF_F64>, grid, dim3(256), 0, c->stream, c->g, in, out, st); break;
-    case DWF_F32: hipLaunchKernelGGL(chiral_split_kernel<DWF_F32>, grid, dim3(256), 0, c->stream, c->g, in, out, st); break;
-    default: hipLaunchKernelGGL(chiral_split_kernel<DWF_F16S>, grid, dim3(256), 0, c->stream, c->g, in, out, st); break;
+  // fields of both parities: the even halves, then the odd halves (nvec in, 2 nvec out)
+  for (int par = 0; par < (c->coarse_both ? 2 : 1); ++par) {
+    const char* i = in + (size_t)par * nvec * st;
+    char* o = out + (size_t)par * 2 * nvec * st;
+    switch (prec) {
+      case DWF_F64: hipLaunchKernelGGL(chiral_split_kernel<DWF_F64>, grid, dim3(256), 0, c->stream, c->g, i, o, st); break;
+      case DWF_F32: hipLaunchKernelGGL(chiral_split_kernel<DWF_F32>, grid, dim3(256), 0, c->stream, c->g, i, o, st); break;
+      default: hipLaunchKernelGGL(chiral_split_kernel<DWF_F16S>, grid, dim3(256), 0, c->stream, c->g, i, o, st); break;
+    }
   }
   return hipGetLastError();
 }
@@ -428,6 +451,7 @@ static BlockArgs block_args(const dwf_context* c, int prec, const char* basis, i
   a.basis = basis;
   a.nvec = nvec;
   a.stride = field_bytes_rhs(c, prec);
+  a.basis_ps = c->coarse_both ? (size_t)nvec * a.stride : 0;
   return a;
 }
 
@@ -443,6 +467,7 @@ hipError_t launch_block_dot(dwf_context* c, int prec, const char* basis, int nve
   BlockArgs a = block_args(c, prec, basis, nvec);
   a.v = v;
   a.nrhs = nrhs;
+  a.v_ps = c->coarse_both ? (size_t)nrhs * a.stride : 0;
   a.coef = coef;
   a.per_block = per_block ? 1 : 0;
   switch (prec) {
@@ -467,6 +492,7 @@ hipError_t launch_block_prolong(dwf_context* c, int prec, const char* basis, int
   a.coef = const_cast<double*>(coef);
   a.nrhs = nrhs;
   a.out = out;
+  a.out_ps = c->coarse_both ? (size_t)nrhs * a.stride : 0;
   switch (prec) {
     case DWF_F64: combine_t<DWF_F64, 2, false>(c, a); break;
     case DWF_F32: combine_t<DWF_F32, 2, false>(c, a); break;
@@ -479,6 +505,7 @@ hipError_t launch_block_apply(dwf_context* c, int prec, char* basis, int nvec, c
   BlockArgs a = block_args(c, prec, basis, nvec);
   a.wmat = wmat;
   a.out = basis;
+  a.out_ps = a.basis_ps;
   switch (prec) {
     case DWF_F64: combine_t<DWF_F64, 2, true>(c, a); break;
     case DWF_F32: combine_t<DWF_F32, 2, true>(c, a); break;

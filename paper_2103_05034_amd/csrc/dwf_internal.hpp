@@ -312,10 +312,14 @@ struct dwf_context {
   int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
   int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
   int schur_form;  // 1: M_ee - M_eo M_oo^{-1} M_oe; 2: 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe
-  // coarse-space blocks: extents, count, even sites per block, their half-lattice indices [nb][nsb]
+  // coarse-space blocks: extents, count, sites per block and their indices [nb][nsb] (even sites
+  // for even-parity fields; all sites, odd ones as h + V4h, for fields of both parities), and the
+  // neighbouring block in each of the 8 hop directions [nb][8]
   int blk[4];
   int nb, nsb;
+  int coarse_both;
   int* bsite;
+  int* bnbr;
   // progress reporting of the synchronous solvers
   dwf_progress_fn progress_fn;
   void* progress_user;

@@ -10,6 +10,17 @@ inline size_t field_bytes_rhs(const dwf_context* ctx, int prec) {
   return spinor_bytes(prec) * (size_t)ctx->g.Ls * (size_t)ctx->g.V4h;
 }
 
+// Host-side error reporting shared by the entry points: records the message
+// returned by dwf_last_error and returns code.
+int fail(int code, const char* fmt, ...);
+int check_h(dwf_handle h);             // DWF_EINVAL for a null handle
+int sync(dwf_context* c);              // synchronise the handle's stream
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return ::dwf::fail(DWF_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
 void timing_begin(dwf_context* ctx);
 void timing_end(dwf_context* ctx);
 

@@ -1,0 +1,317 @@
+"""GPU parity of the two-level HDCR solver against the oracle, through the C ABI:
+both-parity blocks (chirality split, restriction, prolongation, orthonormalisation),
+H_DW, the D_DW^dag D_DW setup filter, the little Dirac operator, its apply and CGNR
+solve, the smoother, one V(1,1) cycle and the full pGCR solve.
+
+The oracle always runs on the values the GPU holds (the packed basis unpacked again).
+At 16^3x32, Ls = 16 with the Algorithm B blocks (2^4 x Ls) the stencil is checked on
+lattice patches around sampled blocks (the oracle applies H_DW to each blocked basis
+vector inside a patch wide enough that the patch's own periodicity never enters), and
+its Hermiticity is checked for every block."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import coarse as C
+from oracle import hdcr as H
+from oracle import krylov
+from oracle import lattice as L
+from tests.gpu_util import M5, MF, dev_tensor, make_operator, pack, rel, take_patch, unpack
+
+pytestmark = pytest.mark.gpu
+
+F64, BOTH = 0, 2
+DIMS, LS, BLOCK = (8, 4, 4, 4), 4, (2, 2, 2, 2)  # block grid 4 x 2 x 2 x 2
+LO, HI, ORDER = 0.15, 70.0, 12
+
+
+def host(t):
+    import torch
+
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def block_coords(dims, block):
+    n = [d // b for d, b in zip(dims, block)]
+    nb = int(np.prod(n))
+    out = []
+    for b in range(nb):
+        out.append((b % n[0], (b // n[0]) % n[1], (b // (n[0] * n[1])) % n[2], b // (n[0] * n[1] * n[2])))
+    return out, n
+
+
+def block_index(c, n):
+    return ((c[3] * n[2] + c[2]) * n[1] + c[1]) * n[0] + c[0]
+
+
+def dense_from_stencil(S, dims, block):
+    """[nb, 9, n(k), n(j)] stencil -> dense [nb*n, nb*n] with the (j, k) convention of the oracle."""
+    coords, ng = block_coords(dims, block)
+    nb, _, n, _ = S.shape
+    A = np.zeros((nb * n, nb * n), dtype=np.complex128)
+    for b, c in enumerate(coords):
+        for d in range(9):
+            if d == 8:
+                t = b
+            else:
+                mu, back = d // 2, d % 2
+                cc = list(c)
+                cc[mu] = (cc[mu] + (ng[mu] - 1 if back else 1)) % ng[mu]
+                t = block_index(cc, ng)
+            A[b * n : (b + 1) * n, t * n : (t + 1) * n] += S[b, d].T
+    return A
+
+
+@pytest.fixture(scope="module")
+def setup():
+    """12 Gaussian fields filtered on the GPU (T_100 of D^dag D over [0.15, 70]),
+    chirally split and block-orthonormalised on the GPU; the solver built on them."""
+    import paper_2103_05034_amd as dwf
+
+    U = synth.gauge_links(DIMS, 0.3, seed=18)
+    op, _ = make_operator(DIMS, LS, prec=F64, max_nrhs=64, max_cg_rhs=2, U=U)
+    op.set_blocks(BLOCK, both=True)
+    nraw = 12
+    raw = pack(op, synth.gaussian_fermion_batch(DIMS, LS, nraw, 19), BOTH)
+    hd = dwf.HDCR(op, 2 * nraw, smoother_order=ORDER, smoother_lo=LO, smoother_hi=HI, coarse_tol=0.02, nkrylov=8)
+    hd.filter(raw, nraw, 100, LO, HI)
+    basis = op.chiral_split(raw, nraw)
+    op.block_orthonormalize(basis, 2 * nraw)
+    hd.set_basis(basis)
+    Q = list(unpack(op, basis, 2 * nraw, BOTH))
+    A = H.coarse_operator(lambda v: L.hdw(U, v, M5, MF), Q, DIMS, BLOCK)  # the oracle's, on the held basis
+    return op, U, hd, basis, Q, A
+
+
+def test_both_parity_transfer_matches_oracle():
+    dims, Ls, block = DIMS, LS, BLOCK
+    op, U = make_operator(dims, Ls, prec=F64, max_nrhs=16, max_cg_rhs=2)
+    nb = op.set_blocks(block, both=True)
+    assert nb == C.nblocks(dims, block)
+    V = synth.gaussian_fermion_batch(dims, Ls, 3, 30)
+    buf = pack(op, V, BOTH)
+    split = unpack(op, op.chiral_split(buf, 3), 6, BOTH)
+    for k in range(3):
+        p, m = C.chiral_split(V[k])
+        assert np.array_equal(split[2 * k], p) and np.array_equal(split[2 * k + 1], m)
+    basis = pack(op, split, BOTH)
+    op.block_orthonormalize(basis, 6)
+    Q = unpack(op, basis, 6, BOTH)
+    Qo, _ = C.block_orthonormalize(list(split), dims, block)
+    for k in range(6):
+        assert np.max(np.abs(Q[k] - Qo[k])) < 1e-12 * np.max(np.abs(Qo[k]))
+    W = synth.gaussian_fermion_batch(dims, Ls, 2, 31)
+    c = host(op.restrict(basis, 6, pack(op, W, BOTH), 2))
+    for r in range(2):
+        want = C.restrict(list(Q), W[r], dims, block)
+        assert np.max(np.abs(c[r] - want)) < 1e-13 * np.max(np.abs(want))
+    cc = np.random.default_rng(32).standard_normal((2, nb, 6)) + 1j * np.random.default_rng(33).standard_normal((2, nb, 6))
+    got = unpack(op, op.prolong(basis, 6, dev_tensor(cc), 2), 2, BOTH)
+    for r in range(2):
+        want = C.prolong(list(Q), cc[r], dims, block)
+        assert np.max(np.abs(got[r] - want)) < 1e-14 * np.max(np.abs(want)) * 10
+
+
+def test_hdw_matches_oracle():
+    op, U = make_operator(DIMS, LS, prec=F64, max_nrhs=2, max_cg_rhs=1)
+    V = synth.gaussian_fermion_batch(DIMS, LS, 2, 34)
+    out = op.new_field(2, both=True)
+    op.hdw(pack(op, V, BOTH), out, 2)
+    got = unpack(op, out, 2, BOTH)
+    for k in range(2):
+        assert rel(got[k], L.hdw(U, V[k], M5, MF)) < 1e-13
+
+
+def test_setup_filter_matches_oracle(setup):
+    op, U, hd, _, _, _ = setup
+    V = synth.gaussian_fermion_batch(DIMS, LS, 2, 35)
+    buf = pack(op, V, BOTH)
+    hd.filter(buf, 2, 9, 0.2, 60.0)
+    got = unpack(op, buf, 2, BOTH)
+    for k in range(2):
+        want, _ = krylov.chebyshev_filter(lambda v: H.hdw_normal(U, v, M5, MF), V[k], 9, 0.2, 60.0)
+        assert rel(got[k], want) < 1e-12
+
+
+def test_coarse_operator_matches_oracle(setup):
+    op, U, hd, _, Q, A = setup
+    S = host(hd.coarse_operator())
+    A_gpu = dense_from_stencil(S, DIMS, BLOCK)
+    assert np.max(np.abs(A_gpu - A)) < 1e-12 * np.max(np.abs(A))
+    assert np.max(np.abs(A_gpu - A_gpu.conj().T)) < 1e-12 * np.max(np.abs(A))
+
+
+def test_coarse_apply_and_solve(setup):
+    op, U, hd, _, Q, _ = setup
+    S = host(hd.coarse_operator())
+    A = dense_from_stencil(S, DIMS, BLOCK)
+    rng = np.random.default_rng(36)
+    nb, n = op.nblocks, hd.nvec
+    x = rng.standard_normal((nb, n)) + 1j * rng.standard_normal((nb, n))
+    y = host(hd.coarse_apply(dev_tensor(x)))
+    assert np.max(np.abs(y.ravel() - A @ x.ravel())) < 1e-13 * np.max(np.abs(y))
+    # the coarse system is ill-conditioned (CG on A^2), so iterates are compared over a fixed
+    # 25 iterations, before rounding makes the two sequences drift apart
+    c, it = hd.coarse_solve(dev_tensor(x), tol=1e-30, maxiter=25)
+    ref = H.coarse_solve(A, x.ravel(), tol=1e-30, maxiter=25)
+    assert it == ref.iterations == 25
+    assert float(np.linalg.norm(host(c).ravel() - ref.x) / np.linalg.norm(ref.x)) < 1e-10
+    # converged to 1e-10 (some 470 iterations): the count stays within 2 % of the oracle's
+    c, it = hd.coarse_solve(dev_tensor(x), tol=1e-10, maxiter=5000)
+    ref = H.coarse_solve(A, x.ravel(), tol=1e-10, maxiter=5000)
+    assert abs(it - ref.iterations) <= max(2, 0.02 * ref.iterations)
+    # true normal residual: the GPU's reaches what the oracle's FP64 CG reaches
+    Ah, cg = A.conj().T, host(c).ravel()
+    bn = np.linalg.norm(Ah @ x.ravel())
+    t_gpu = np.linalg.norm(Ah @ (x.ravel() - A @ cg)) / bn
+    t_ref = np.linalg.norm(Ah @ (x.ravel() - A @ ref.x)) / bn
+    assert t_gpu <= 10 * max(t_ref, 1e-10)
+
+
+def test_smoother_matches_oracle(setup):
+    op, U, hd, _, _, _ = setup
+    r = synth.gaussian_fermion(DIMS, LS, seed=37)
+    got = unpack(op, hd.smoother(pack(op, r[None], BOTH)), 1, BOTH)[0]
+    assert rel(got, H.smoother(U, r, M5, MF, LO, HI, ORDER)) < 1e-12
+
+
+def test_vcycle_matches_oracle(setup):
+    """With the coarse CG run for a fixed 20 iterations on both sides the cycle is the
+    oracle's to rounding (a tolerance would leave the ill-conditioned coarse iterates free to
+    drift apart by rounding); at the Algorithm A / B tolerance 0.02 the coarse CG takes the
+    oracle's iteration count."""
+    import paper_2103_05034_amd as dwf
+
+    op, U, hd, basis, Q, A = setup
+    r0 = synth.gaussian_fermion(DIMS, LS, seed=38)
+    r0_d = pack(op, r0[None], BOTH)
+    fixed = dwf.HDCR(op, hd.nvec, smoother_order=ORDER, smoother_lo=LO, smoother_hi=HI, coarse_tol=1e-30,
+                     coarse_maxiter=20, nkrylov=2)
+    fixed.set_basis(basis)
+    x, ci = fixed.vcycle(r0_d)
+    assert ci == 20
+    lv = H.Level(U, M5, MF, Q, A, DIMS, BLOCK, LO, HI, ORDER, coarse_tol=1e-30, coarse_maxiter=20)
+    want = H.vcycle(lv, r0)
+    assert rel(unpack(op, x, 1, BOTH)[0], want) < 1e-10
+    fixed.close()
+    # the loose coarse solve: the same iteration count as the oracle's first coarse solve
+    x, ci = hd.vcycle(r0_d)
+    lv = H.Level(U, M5, MF, Q, A, DIMS, BLOCK, LO, HI, ORDER, coarse_tol=0.02)
+    r1 = r0 - lv.M(lv.S(r0))
+    ref = H.coarse_solve(A, H.restrict(Q, r1, DIMS, BLOCK), 0.02)
+    assert abs(ci - ref.iterations) <= 1
+    if ci == ref.iterations:
+        assert rel(unpack(op, x, 1, BOTH)[0], H.vcycle(lv, r0)) < 1e-5
+
+
+def test_hdcr_solve_matches_oracle(setup):
+    op, U, hd, _, Q, A = setup
+    eta = synth.gaussian_fermion(DIMS, LS, seed=20)
+    psi = op.new_field(1, both=True)
+    it, res, ci = hd.solve(pack(op, eta[None], BOTH), psi, tol=1e-10, maxiter=100)
+    got = unpack(op, psi, 1, BOTH)[0]
+    assert res < 1.5e-10 and ci > 0
+    assert rel(L.ddw(U, got, M5, MF), eta) < 2e-10
+    lv = H.Level(U, M5, MF, Q, A, DIMS, BLOCK, LO, HI, ORDER, coarse_tol=0.02)
+    ref = H.hdcr_solve(lv, eta, tol=1e-10, maxiter=100, nkrylov=8)
+    assert ref.converged and abs(it - ref.iterations) <= 1
+    assert rel(got, ref.x) < 1e-7  # both within kappa(H_DW) ~ 300 times 1e-10 of the solution
+
+
+def test_hdcr_rejects_bad_use():
+    import paper_2103_05034_amd as dwf
+
+    op, U = make_operator(DIMS, LS, prec=F64, max_nrhs=8, max_cg_rhs=2)
+    op.set_blocks(BLOCK)  # even-parity blocks: no HDCR
+    with pytest.raises(dwf.DWFError):
+        dwf.HDCR(op, 4)
+    op.set_blocks(BLOCK, both=True)
+    hd = dwf.HDCR(op, 4)
+    psi = op.new_field(1, both=True)
+    with pytest.raises(dwf.DWFError) as e:  # no basis yet
+        hd.solve(op.new_field(1, both=True), psi)
+    assert e.value.code == dwf.DWF_EINVAL
+    op.set_blocks((4, 2, 2, 2), both=True)  # blocks changed under the solver
+    with pytest.raises(dwf.DWFError) as e:
+        hd.smoother(op.new_field(1, both=True))
+    assert "blocks changed" in str(e.value)
+
+
+def test_fullsize_algorithm_b_stencil_on_patches():
+    """16^3x32, Ls = 16, 2^4 blocks on both parities, 16 basis vectors: stencil entries of
+    sampled blocks against the oracle on 6^4 patches, and A = A^dag over every block."""
+    import paper_2103_05034_amd as dwf
+    import torch
+
+    dims, Ls, block = (16, 16, 16, 32), 16, (2, 2, 2, 2)
+    U = synth.gauge_links(dims, 0.2, seed=0)
+    op, _ = make_operator(dims, Ls, prec=F64, max_nrhs=16, max_cg_rhs=2, U=U)
+    nb = op.set_blocks(block, both=True)
+    nraw = 8
+    raw = op.new_field(nraw, both=True)
+    fb = op.field_bytes(1)
+    for k in range(nraw):  # pack one field at a time into the both layout (even half k, odd half nraw + k)
+        one = pack(op, synth.gaussian_fermion_batch(dims, Ls, 1, 200 + k), BOTH)
+        raw[k * fb : (k + 1) * fb] = one[:fb]
+        raw[(nraw + k) * fb : (nraw + k + 1) * fb] = one[fb:]
+    hd = dwf.HDCR(op, 2 * nraw, smoother_lo=0.5, smoother_hi=70.0, nkrylov=4)
+    hd.filter(raw, nraw, 20, 0.5, 70.0)
+    basis = op.chiral_split(raw, nraw)
+    op.block_orthonormalize(basis, 2 * nraw)
+    hd.set_basis(basis)
+    S = hd.coarse_operator()  # [nb, 9, k, j] on the device
+    n = 2 * nraw
+    # Hermiticity over the whole block grid: point d of block b is the adjoint of the
+    # opposite point of the neighbour, the self point is Hermitian
+    coords, ng = block_coords(dims, block)
+    nbr = np.zeros((nb, 8), dtype=np.int64)
+    for b, c in enumerate(coords):
+        for d in range(8):
+            cc = list(c)
+            mu = d // 2
+            cc[mu] = (cc[mu] + (ng[mu] - 1 if d % 2 else 1)) % ng[mu]
+            nbr[b, d] = block_index(cc, ng)
+    nbr_t = torch.from_numpy(nbr).cuda()
+    scale = S.abs().max().item()
+    for d in range(8):
+        opp = d ^ 1
+        back = S[nbr_t[:, d], opp]  # [nb, k, j] of the neighbour towards b
+        assert (S[:, d] - back.transpose(1, 2).conj()).abs().max().item() < 1e-12 * scale
+    assert (S[:, 8] - S[:, 8].transpose(1, 2).conj()).abs().max().item() < 1e-12 * scale
+    # sampled blocks against the oracle on a 6^4 patch (the block plus two sites each way)
+    Sh = host(S)
+    samples = [(0, 0, 0, 0), (3, 5, 7, 11)]
+    idxs = []
+    for bc in samples:
+        origin = [bc[i] * block[i] - 2 for i in range(4)]  # even coordinates: the patch keeps the parity
+        idxs.append([np.arange(o, o + 6) % L for o, L in zip(origin, dims)])
+    patches = [[] for _ in samples]
+    one = op.new_field(1, both=True)
+    for k in range(n):  # one basis vector at a time: its even and odd halves into a single field
+        one[:fb] = basis[k * fb : (k + 1) * fb]
+        one[fb:] = basis[(n + k) * fb : (n + k + 1) * fb]
+        q = unpack(op, one, 1, BOTH)[0]
+        for i, idx in enumerate(idxs):
+            patches[i].append(take_patch(q, idx, -3))
+        del q
+    for bc, idx, Qp in zip(samples, idxs, patches):
+        b = block_index(bc, ng)
+        Up = take_patch(U, idx, -4)  # links [T][Z][Y][X][mu][a][b]: x is 4th from the end
+        pdims, pblock = (6, 6, 6, 6), block
+        centre = block_index((1, 1, 1, 1), (3, 3, 3, 3))
+        for k in range(n):
+            phib = H.blocked(Qp[k], centre, pdims, pblock)
+            col = C.restrict(Qp, L.hdw(Up, phib, M5, MF), pdims, pblock)  # [patch blocks, j]
+            # self point and the eight neighbours
+            assert np.max(np.abs(col[centre] - Sh[b, 8, k])) < 1e-12 * scale
+            for d in range(8):
+                cc = [1, 1, 1, 1]
+                mu = d // 2
+                cc[mu] += 1 if d % 2 else -1  # block a with a + dir(d) = b
+                a_patch = block_index(cc, (3, 3, 3, 3))
+                a_full = nbr[b, d ^ 1]
+                # <phi_j^a | H | phi_k^b> is point d of block a
+                assert np.max(np.abs(col[a_patch] - Sh[a_full, d, k])) < 1e-12 * scale
+    hd.close()
