@@ -309,6 +309,15 @@ int dwf_hdcr_destroy(dwf_hdcr hd);
  * operator that Algorithms A / B coarsen.  No normalisation. */
 int dwf_hdcr_filter(dwf_hdcr hd, int order, double lo, double hi, void* vecs, int nvecs);
 
+/* The recursive series of the setup on the same operator A = D_DW^dag D_DW:
+ * out_series[0] = T_m(x_[lam_lo, lam_max](A)) eta, then out_series[k] =
+ * T_{k delta}(2 A / lam_max - 1) out_series[0] for k = 1..nvec-1 (Deflation
+ * basis setup section; m + (nvec - 1) delta applications of A).  eta: one
+ * field of both parities, unchanged; out_series: nvec fields in the packed
+ * "both" layout, distinct from eta. */
+int dwf_hdcr_series(dwf_hdcr hd, int m, double lam_lo, double lam_max, int delta, int nvec, const void* eta,
+                    void* out_series);
+
 /* SYNCHRONOUS.  Use basis (nvec packed "both" fields, normally chirally split
  * and block-orthonormalised with the DWF_BOTH blocks) as the blocked basis
  * phi_k^b and build the little Dirac operator A^{ab}_{jk} = <phi_j^a | H_DW |

@@ -101,6 +101,7 @@ _PROTOS = {
     "dwf_hdcr_create": (_i, [_vp, _i, _vp, _vp, ctypes.c_size_t, ctypes.POINTER(_vp)]),
     "dwf_hdcr_destroy": (_i, [_vp]),
     "dwf_hdcr_filter": (_i, [_vp, _i, _d, _d, _vp, _i]),
+    "dwf_hdcr_series": (_i, [_vp, _i, _d, _d, _i, _i, _vp, _vp]),
     "dwf_hdcr_set_basis": (_i, [_vp, _vp]),
     "dwf_hdcr_coarse_data": (_vp, [_vp]),
     "dwf_hdcr_coarse_apply": (_i, [_vp, _vp, _vp]),
@@ -509,6 +510,15 @@ class HDCR:
         """vecs <- T_order(x(D^dag D)) vecs for nvecs fields of both parities."""
         self.op._sync_stream()
         _check(self.lib.dwf_hdcr_filter(self.hd, order, lo, hi, _ptr(vecs), nvecs))
+
+    def series(self, eta, m, lam_lo, lam_max, delta, nvec, out=None):
+        """The setup series from one field eta: out[0] = T_m(x_[lam_lo, lam_max](D^dag D)) eta,
+        out[k] = T_{k delta}(2 D^dag D / lam_max - 1) out[0] (nvec fields of both parities)."""
+        if out is None:
+            out = self.op.new_field(nvec, both=True)
+        self.op._sync_stream()
+        _check(self.lib.dwf_hdcr_series(self.hd, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out)))
+        return out
 
     def set_basis(self, basis):
         """Build the little Dirac operator of H_DW on ``basis`` (kept referenced)."""

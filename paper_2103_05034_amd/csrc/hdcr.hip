@@ -549,6 +549,30 @@ int vcycle(dwf_hdcr_s* hd, const char* r0, char* x) {
   return DWF_OK;
 }
 
+// v <- T_order(x(D^dag D)) v in place, x(A) = 2 (A - lo)/(hi - lo) - 1 (work fields 0, 1)
+int filter_one(dwf_hdcr_s* hd, int order, double lo, double hi, BFm v) {
+  if (order == 0) return DWF_OK;
+  dwf_context* c = hd->h;
+  const double w = hi - lo;
+  const BFm tmp = whole(hd, work_f(hd, 0));
+  const BF vc{v.e, v.o};
+  // T_1 = x(A) v, then T_{j+1} = 2 x(A) T_j - T_{j-1} over the older buffer
+  HIP_TRY(ddagd_step(c, vc, whole(hd, work_f(hd, 1)), vc, vc, 2.0 / w, -(hi + lo) / w, 0.0, BF{nullptr, nullptr},
+                     0.0, tmp));
+  BFm prev = v, cur = whole(hd, work_f(hd, 1));
+  for (int j = 1; j < order; ++j) {
+    HIP_TRY(ddagd_step(c, BF{cur.e, cur.o}, prev, BF{cur.e, cur.o}, BF{prev.e, prev.o}, 4.0 / w, -2.0 * (hi + lo) / w,
+                       -1.0, BF{nullptr, nullptr}, 0.0, tmp));
+    std::swap(prev, cur);
+  }
+  if (cur.e != v.e) {
+    const long long nh = (long long)(hd->fb / 16);
+    HIP_TRY(caxpby(hd, nh, cur.e, 1, 0, 0, v.e));
+    HIP_TRY(caxpby(hd, nh, cur.o, 1, 0, 0, v.o));
+  }
+  return DWF_OK;
+}
+
 int check_hd(dwf_hdcr hd, bool need_basis) {
   if (!hd) return fail(DWF_EINVAL, "null HDCR handle");
   const dwf_context* h = hd->h;
@@ -679,29 +703,48 @@ int dwf_hdcr_coarse_solve(dwf_hdcr hd, const void* d, void* c, double tol, int m
 int dwf_hdcr_filter(dwf_hdcr hd, int order, double lo, double hi, void* vecs, int nvecs) {
   if (int r = check_hd(hd, false)) return r;
   if (!vecs || nvecs < 1 || order < 0 || !(hi > lo)) return fail(DWF_EINVAL, "dwf_hdcr_filter: bad argument");
-  if (order == 0) return DWF_OK;
-  dwf_context* c = hd->h;
-  const double w = hi - lo;
   char* V = reinterpret_cast<char*>(vecs);
-  char* tmp = work_f(hd, 0);
-  char* T = work_f(hd, 1);
-  for (int k = 0; k < nvecs; ++k) {
-    BFm v{V + (size_t)k * hd->fb, V + (size_t)(nvecs + k) * hd->fb};
-    BF vc{v.e, v.o};
-    // T_1 = x(A) v, then T_{j+1} = 2 x(A) T_j - T_{j-1} over the older buffer
-    HIP_TRY(ddagd_step(c, vc, whole(hd, T), vc, vc, 2.0 / w, -(hi + lo) / w, 0.0, BF{nullptr, nullptr}, 0.0,
-                       whole(hd, tmp)));
-    BFm prev = v, cur = whole(hd, T);
-    for (int j = 1; j < order; ++j) {
-      HIP_TRY(ddagd_step(c, BF{cur.e, cur.o}, prev, BF{cur.e, cur.o}, BF{prev.e, prev.o}, 4.0 / w,
-                         -2.0 * (hi + lo) / w, -1.0, BF{nullptr, nullptr}, 0.0, whole(hd, tmp)));
-      std::swap(prev, cur);
+  for (int k = 0; k < nvecs; ++k)
+    if (int rc = filter_one(hd, order, lo, hi, BFm{V + (size_t)k * hd->fb, V + (size_t)(nvecs + k) * hd->fb})) return rc;
+  return DWF_OK;
+}
+
+int dwf_hdcr_series(dwf_hdcr hd, int m, double lam_lo, double lam_max, int delta, int nvec, const void* eta,
+                    void* out_series) {
+  if (int r = check_hd(hd, false)) return r;
+  if (!eta || !out_series || eta == out_series || m < 0 || delta < 1 || nvec < 1 || !(lam_max > lam_lo) ||
+      !(lam_max > 0))
+    return fail(DWF_EINVAL, "dwf_hdcr_series: bad argument");
+  dwf_context* c = hd->h;
+  const size_t fb = hd->fb;
+  const long long nh = (long long)(fb / 16);
+  char* S = reinterpret_cast<char*>(out_series);
+  auto slot = [&](int k) { return BFm{S + (size_t)k * fb, S + (size_t)(nvec + k) * fb}; };
+  auto cp = [&](BF from, BFm to) -> hipError_t {
+    hipError_t e = caxpby(hd, nh, from.e, 1, 0, 0, to.e);
+    return e != hipSuccess ? e : caxpby(hd, nh, from.o, 1, 0, 0, to.o);
+  };
+  const char* e = reinterpret_cast<const char*>(eta);
+  // phi_0 = T_m(x_[lam_lo, lam_max](A)) eta
+  const BFm s0 = slot(0);
+  HIP_TRY(cp(BF{e, e + fb}, s0));
+  if (int rc = filter_one(hd, m, lam_lo, lam_max, s0)) return rc;
+  if (nvec == 1) return DWF_OK;
+  // phi_k = T_{k delta}(2A/lam_max - 1) phi_0 from a second recurrence
+  const BF s0c{s0.e, s0.o};
+  BFm prev = whole(hd, work_f(hd, 1)), cur = whole(hd, work_f(hd, 2));
+  const BFm tmp = whole(hd, work_f(hd, 0));
+  HIP_TRY(cp(s0c, prev));
+  HIP_TRY(ddagd_step(c, s0c, cur, s0c, s0c, 2.0 / lam_max, -1.0, 0.0, BF{nullptr, nullptr}, 0.0, tmp));
+  int recorded = 1;
+  for (int n = 1; recorded < nvec; ++n) {
+    if (n % delta == 0) {
+      HIP_TRY(cp(BF{cur.e, cur.o}, slot(recorded)));
+      if (++recorded == nvec) break;
     }
-    if (cur.e != v.e) {
-      const long long nh = (long long)(hd->fb / 16);
-      HIP_TRY(caxpby(hd, nh, cur.e, 1, 0, 0, v.e));
-      HIP_TRY(caxpby(hd, nh, cur.o, 1, 0, 0, v.o));
-    }
+    HIP_TRY(ddagd_step(c, BF{cur.e, cur.o}, prev, BF{cur.e, cur.o}, BF{prev.e, prev.o}, 4.0 / lam_max, -2.0, -1.0,
+                       BF{nullptr, nullptr}, 0.0, tmp));
+    std::swap(prev, cur);
   }
   return DWF_OK;
 }

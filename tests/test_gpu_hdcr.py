@@ -135,6 +135,17 @@ def test_setup_filter_matches_oracle(setup):
         assert rel(got[k], want) < 1e-12
 
 
+def test_setup_series_matches_oracle(setup):
+    op, U, hd, _, _, _ = setup
+    eta = synth.gaussian_fermion(DIMS, LS, seed=39)
+    out = hd.series(pack(op, eta[None], BOTH), 7, 0.1, 60.0, 3, 3)
+    got = unpack(op, out, 3, BOTH)
+    want, count = krylov.chebyshev_series(lambda v: H.hdw_normal(U, v, M5, MF), eta, 7, 0.1, 60.0, 3, 3)
+    assert count == 7 + 2 * 3
+    for k in range(3):
+        assert rel(got[k], want[k]) < 1e-12
+
+
 def test_coarse_operator_matches_oracle(setup):
     op, U, hd, _, Q, A = setup
     S = host(hd.coarse_operator())
