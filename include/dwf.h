@@ -274,14 +274,18 @@ int dwf_hdw(dwf_handle h, const void* in, void* out, int nrhs);
  * S_cheb([smoother_lo, smoother_hi], smoother_order) of the Chebyshev
  * smoothers section with M = H_DW; the coarse solve, CG on the normal
  * equations of the little Dirac operator stopped at relative residual
- * coarse_tol of those equations or after coarse_maxiter iterations; and the
- * outer GCR restarted every nkrylov directions. */
+ * coarse_tol of those equations or after coarse_maxiter iterations; the
+ * outer GCR restarted every nkrylov directions; and the storage of the
+ * little Dirac operator, coarse_prec = DWF_F64 (0, the default of a zeroed
+ * struct) or DWF_F32 (complex64 entries, half the bytes of each coarse
+ * matvec; coarse vectors and all sums stay FP64). */
 typedef struct {
   int smoother_order;
   double smoother_lo, smoother_hi;
   double coarse_tol;
   int coarse_maxiter;
   int nkrylov;
+  int coarse_prec;
 } dwf_hdcr_params;
 
 typedef struct dwf_hdcr_s* dwf_hdcr;
@@ -326,7 +330,7 @@ int dwf_hdcr_series(dwf_hdcr hd, int m, double lam_lo, double lam_max, int delta
 int dwf_hdcr_set_basis(dwf_hdcr hd, const void* basis);
 
 /* Device pointer to the little Dirac operator, a 9-point stencil over the
- * block grid: complex128 [nblocks][9][nvec][nvec], entry (j, k) of stencil
+ * block grid: complex128 (complex64 with coarse_prec = DWF_F32) [nblocks][9][nvec][nvec], entry (j, k) of stencil
  * point d at (d * nvec + k) * nvec + j.  Point d < 8 couples block b to the
  * block that hop direction d leads to (d = 2 mu + 0 forward / 1 backward,
  * mu = x, y, z, t), point 8 to b itself.  NULL for a null solver. */

@@ -62,6 +62,7 @@ class HDCRParams(ctypes.Structure):
         ("coarse_tol", ctypes.c_double),
         ("coarse_maxiter", ctypes.c_int),
         ("nkrylov", ctypes.c_int),
+        ("coarse_prec", ctypes.c_int),
     ]
 
 
@@ -486,11 +487,12 @@ class HDCR:
     FP64 :class:`Operator` whose blocks were set with ``set_blocks(block, both=True)``."""
 
     def __init__(self, op, nvec, smoother_order=12, smoother_lo=0.5, smoother_hi=60.0, coarse_tol=0.02,
-                 coarse_maxiter=1000, nkrylov=8):
+                 coarse_maxiter=1000, nkrylov=8, coarse_prec=DWF_F64):
         import torch
 
         self.op, self.lib, self.nvec = op, op.lib, nvec
-        self.params = HDCRParams(smoother_order, smoother_lo, smoother_hi, coarse_tol, coarse_maxiter, nkrylov)
+        self.params = HDCRParams(smoother_order, smoother_lo, smoother_hi, coarse_tol, coarse_maxiter, nkrylov,
+                                 coarse_prec)
         nbytes = self.lib.dwf_hdcr_workspace_bytes(op.h, nvec, nkrylov)
         if nbytes == 0:
             raise DWFError(DWF_EINVAL, "set DWF_BOTH blocks first; nvec and nkrylov must be in [1, 64]")
@@ -527,13 +529,15 @@ class HDCR:
         _check(self.lib.dwf_hdcr_set_basis(self.hd, _ptr(basis)))
 
     def coarse_operator(self):
-        """The stencil as a complex128 tensor [nblocks, 9, nvec(k), nvec(j)] viewing the workspace."""
+        """The stencil as a complex128 (complex64 with coarse_prec=DWF_F32) tensor
+        [nblocks, 9, nvec(k), nvec(j)] viewing the workspace."""
         import torch
 
         n, nb = self.nvec, self.op.nblocks
+        f32 = self.params.coarse_prec == DWF_F32
         off = self.lib.dwf_hdcr_coarse_data(self.hd) - self.ws.data_ptr()
-        raw = self.ws[off : off + nb * 9 * n * n * 16]
-        return raw.view(torch.complex128).view(nb, 9, n, n)
+        raw = self.ws[off : off + nb * 9 * n * n * (8 if f32 else 16)]
+        return raw.view(torch.complex64 if f32 else torch.complex128).view(nb, 9, n, n)
 
     def coarse_apply(self, x, y=None):
         if y is None:

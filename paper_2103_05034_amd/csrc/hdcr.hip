@@ -187,8 +187,14 @@ __global__ void __launch_bounds__(CB) coarsen_kernel(CoarsenArgs a) {
   Store<DWF_F64>::store(a.out + ((size_t)p * 9 + 8) * a.fb, V4h, Ls, h, s, o);
 }
 
+// Stencil storage: complex128, or complex64 (the coarse solve's tolerance of a
+// few per cent does not need FP64 matrix entries; vectors and sums stay FP64).
+__device__ __forceinline__ void put(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void put(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
 // A[b][r][k][j] = coef[r][b][j] for basis vector k.
-__global__ void __launch_bounds__(CB) coarse_scatter_kernel(const double2* __restrict__ coef, double2* __restrict__ A,
+template <class T>
+__global__ void __launch_bounds__(CB) coarse_scatter_kernel(const double2* __restrict__ coef, T* __restrict__ A,
                                                             int nb, int n, int k) {
   const long long i = (long long)blockIdx.x * CB + threadIdx.x;
   if (i >= (long long)9 * nb * n) return;
@@ -196,12 +202,13 @@ __global__ void __launch_bounds__(CB) coarse_scatter_kernel(const double2* __res
   const long long rb = i / n;
   const int b = (int)(rb % nb);
   const int r = (int)(rb / nb);
-  A[(((size_t)b * 9 + r) * n + k) * n + j] = coef[i];
+  put(&A[(((size_t)b * 9 + r) * n + k) * n + j], coef[i]);
 }
 
 // y[b] = sum_r A[b][r] x[neighbour_r(b)]: one workgroup per block, lane j
 // computes row j; the nine input vectors pass through LDS.
-__global__ void __launch_bounds__(64) coarse_matvec_kernel(const double2* __restrict__ A, const int* __restrict__ bnbr,
+template <class T>
+__global__ void __launch_bounds__(64) coarse_matvec_kernel(const T* __restrict__ A, const int* __restrict__ bnbr,
                                                            int n, const double2* __restrict__ x,
                                                            double2* __restrict__ y) {
   __shared__ double2 xs[9 * 64];
@@ -215,10 +222,11 @@ __global__ void __launch_bounds__(64) coarse_matvec_kernel(const double2* __rest
   const int j = threadIdx.x;
   if (j >= n) return;
   double re = 0, im = 0;
-  const double2* Ab = A + (size_t)b * 9 * n * n;
+  const T* Ab = A + (size_t)b * 9 * n * n;
   for (int r = 0; r < 9; ++r)
     for (int k = 0; k < n; ++k) {
-      const double2 m = Ab[((size_t)r * n + k) * n + j];
+      const T ms = Ab[((size_t)r * n + k) * n + j];
+      const double2 m = make_double2((double)ms.x, (double)ms.y);
       const double2 v = xs[r * n + k];
       re = fma(m.x, v.x, fma(-m.y, v.y, re));
       im = fma(m.x, v.y, fma(m.y, v.x, im));
@@ -291,6 +299,86 @@ __global__ void __launch_bounds__(CB) caxpby_kernel(long long n, const double2* 
   y[i] = o;
 }
 
+// Device scalars of the coarse CG (one solve at a time).
+enum CgSlot { CS_RR = 0, CS_QQ, CS_ALPHA, CS_STOP, CS_ACTIVE, CS_ITERS, CS_RRN, CS_BETA, CS_FLAG, CS_TMP, CS_N = 16 };
+
+// cs[slot] = sum of the CRED real partials
+__global__ void __launch_bounds__(CB) csum1_kernel(const double* __restrict__ part, double* __restrict__ cs, int slot) {
+  double re = 0, im = 0;
+  for (int i = threadIdx.x; i < CRED; i += CB) re += part[i];
+  tree2(re, im);
+  if (threadIdx.x == 0) cs[slot] = re;
+}
+
+__global__ void ccg_init_kernel(double* cs, double tol2) {
+  const double bb = cs[CS_RR];
+  cs[CS_STOP] = tol2 * bb;
+  cs[CS_ACTIVE] = (bb > 0 && bb > cs[CS_STOP]) ? 1.0 : 0.0;
+  cs[CS_ITERS] = 0;
+  cs[CS_FLAG] = 0;
+  cs[CS_ALPHA] = 0;
+  cs[CS_BETA] = 0;
+}
+
+// alpha = |r|^2 / |A p|^2 while the solve is active, else 0 (the iteration is a no-op)
+__global__ void ccg_alpha_kernel(double* cs) {
+  double a = 0.0;
+  if (cs[CS_ACTIVE] != 0.0) {
+    a = cs[CS_RR] / cs[CS_QQ];
+    if (!(cs[CS_QQ] > 0.0) || !isfinite(a)) {
+      cs[CS_FLAG] = 1.0;
+      cs[CS_ACTIVE] = 0.0;
+      a = 0.0;
+    }
+  }
+  cs[CS_ALPHA] = a;
+}
+
+// beta = |r_new|^2 / |r|^2; count the iteration; retire once |r_new|^2 <= tol^2 |b'|^2
+__global__ void ccg_beta_kernel(double* cs) {
+  if (cs[CS_ACTIVE] != 0.0) {
+    const double rn = cs[CS_RRN];
+    cs[CS_BETA] = rn / cs[CS_RR];
+    cs[CS_RR] = rn;
+    cs[CS_ITERS] += 1.0;
+    if (!(rn > cs[CS_STOP])) cs[CS_ACTIVE] = 0.0;
+  } else {
+    cs[CS_BETA] = 0.0;
+  }
+}
+
+// r -= alpha w with the partial sums of |r|^2
+__global__ void __launch_bounds__(CB) caxpy_norm_kernel(long long n, const double2* __restrict__ w,
+                                                        const double* __restrict__ cs, double2* __restrict__ r,
+                                                        double* __restrict__ part) {
+  const double a = cs[CS_ALPHA];
+  double s = 0, dummy = 0;
+  for (long long i = (long long)blockIdx.x * CB + threadIdx.x; i < n; i += (long long)CRED * CB) {
+    const double2 v = w[i];
+    double2 o = r[i];
+    o.x -= a * v.x;
+    o.y -= a * v.y;
+    r[i] = o;
+    s = fma(o.x, o.x, fma(o.y, o.y, s));
+  }
+  tree2(s, dummy);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// c += alpha p; p = r + beta p
+__global__ void __launch_bounds__(CB) ccg_xp_kernel(long long n, double2* __restrict__ c, double2* __restrict__ p,
+                                                    const double2* __restrict__ r, const double* __restrict__ cs) {
+  const long long i = (long long)blockIdx.x * CB + threadIdx.x;
+  if (i >= n) return;
+  const double a = cs[CS_ALPHA], b = cs[CS_BETA];
+  const double2 pv = p[i], rv = r[i];
+  double2 cv = c[i];
+  cv.x += a * pv.x;
+  cv.y += a * pv.y;
+  c[i] = cv;
+  p[i] = make_double2(rv.x + b * pv.x, rv.y + b * pv.y);
+}
+
 unsigned blocks_for(long long n) { return (unsigned)((n + CB - 1) / CB); }
 
 }  // namespace
@@ -304,7 +392,7 @@ struct dwf_hdcr_s {
   int nvec, nk, nb;
   dwf_hdcr_params prm;
   const char* basis;   // caller's basis (packed both layout, nvec fields), set by dwf_hdcr_set_basis
-  double2* A;          // [nb][9][n][n]
+  void* A;             // [nb][9][n][n], complex128 or complex64 (prm.coarse_prec)
   double2* coef;       // [9][nb][n]
   double2* cv[7];      // coarse vectors: d, c, r, p, q, w, b'
   double* part;        // [2][CRED] partials, then 2 result doubles
@@ -344,10 +432,10 @@ size_t carve_hdcr(dwf_hdcr_s* d, const dwf_context* h, int nvec, int nk, char* b
   };
   dwf_hdcr_s tmp;
   dwf_hdcr_s* x = d ? d : &tmp;
-  x->A = reinterpret_cast<double2*>(take((size_t)h->nb * 9 * nvec * nvec * 16));
+  x->A = take((size_t)h->nb * 9 * nvec * nvec * 16);  // sized for complex128
   x->coef = reinterpret_cast<double2*>(take(9 * cvb));
   for (int i = 0; i < 7; ++i) x->cv[i] = reinterpret_cast<double2*>(take(cvb));
-  x->part = reinterpret_cast<double*>(take((2 * CRED + 2) * sizeof(double)));
+  x->part = reinterpret_cast<double*>(take((2 * CRED + 2 + CS_N) * sizeof(double)));
   x->work = take(9 * 2 * fb);
   x->gb = take(2 * fb);
   x->gr = take(2 * fb);
@@ -487,38 +575,62 @@ int smoother(dwf_hdcr_s* hd, const char* r, char* out) {
 }
 
 hipError_t coarse_matvec(dwf_hdcr_s* hd, const double2* x, double2* y) {
-  hipLaunchKernelGGL(coarse_matvec_kernel, dim3(hd->nb), dim3(64), 0, hd->h->stream, hd->A, hd->h->bnbr, hd->nvec, x,
-                     y);
+  if (hd->prm.coarse_prec == DWF_F32)
+    hipLaunchKernelGGL(coarse_matvec_kernel<float2>, dim3(hd->nb), dim3(64), 0, hd->h->stream,
+                       reinterpret_cast<const float2*>(hd->A), hd->h->bnbr, hd->nvec, x, y);
+  else
+    hipLaunchKernelGGL(coarse_matvec_kernel<double2>, dim3(hd->nb), dim3(64), 0, hd->h->stream,
+                       reinterpret_cast<const double2*>(hd->A), hd->h->bnbr, hd->nvec, x, y);
   return hipGetLastError();
 }
 
-// c = A^{-1} d by CG on A^2 c = A d from c = 0; stops when |A d - A^2 c| <= tol |A d|
+// c = A^{-1} d by CG on A^2 c = A d from c = 0; stops when |A d - A^2 c| <= tol |A d|.
+// The scalars stay on the device: once converged the remaining iterations of a batch
+// are no-ops (alpha = 0), and the host looks at the state every CG_BATCH iterations.
+constexpr int CG_BATCH = 8;
+
 int coarse_cgnr(dwf_hdcr_s* hd, const double2* d, double2* cvec, double tol, int maxiter, int* iters) {
+  dwf_context* c = hd->h;
   const long long n = coarse_len(hd);
   double2 *r = hd->cv[2], *p = hd->cv[3], *q = hd->cv[4], *w = hd->cv[5], *bp = hd->cv[6];
+  double* cs = hd->part + 2 * CRED + 2;
+  auto norm_into = [&](const double2* v, int slot) {
+    hipLaunchKernelGGL(cdot_kernel, dim3(CRED), dim3(CB), 0, c->stream, n, v, v, hd->part);
+    hipLaunchKernelGGL(csum1_kernel, dim3(1), dim3(CB), 0, c->stream, hd->part, cs, slot);
+  };
   HIP_TRY(coarse_matvec(hd, d, bp));
   HIP_TRY(caxpby(hd, n, nullptr, 0, 0, 0, cvec));
   HIP_TRY(caxpby(hd, n, bp, 1, 0, 0, r));
   HIP_TRY(caxpby(hd, n, bp, 1, 0, 0, p));
-  double rr = 0, bb = 0;
-  if (int rc = cnorm2(hd, n, r, rr)) return rc;
-  bb = rr;
-  int it = 0;
-  while (bb > 0 && rr > tol * tol * bb && it < maxiter) {
-    HIP_TRY(coarse_matvec(hd, p, q));
-    double pap = 0;
-    if (int rc = cnorm2(hd, n, q, pap)) return rc;
-    const double alpha = rr / pap;
-    if (!(pap > 0) || !std::isfinite(alpha)) return fail(DWF_EBREAKDOWN, "coarse CG breakdown");
-    HIP_TRY(caxpby(hd, n, p, alpha, 0, 1, cvec));
-    HIP_TRY(coarse_matvec(hd, q, w));
-    HIP_TRY(caxpby(hd, n, w, -alpha, 0, 1, r));
-    double rn = 0;
-    if (int rc = cnorm2(hd, n, r, rn)) return rc;
-    HIP_TRY(caxpby(hd, n, r, 1, 0, rn / rr, p));
-    rr = rn;
-    ++it;
+  norm_into(r, CS_RR);
+  hipLaunchKernelGGL(ccg_init_kernel, dim3(1), dim3(1), 0, c->stream, cs, tol * tol);
+  HIP_TRY(hipGetLastError());
+  double st[CS_N];
+  auto read_state = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(st, cs, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return DWF_OK;
+  };
+  if (int rc = read_state()) return rc;
+  const unsigned gb = blocks_for(n);
+  for (int done = 0; st[CS_ACTIVE] != 0.0 && done < maxiter;) {
+    const int batch = std::min(CG_BATCH, maxiter - done);
+    for (int k = 0; k < batch; ++k) {
+      HIP_TRY(coarse_matvec(hd, p, q));                       // q = A p
+      norm_into(q, CS_QQ);                                    // |q|^2 = p.A^2 p
+      hipLaunchKernelGGL(ccg_alpha_kernel, dim3(1), dim3(1), 0, c->stream, cs);
+      HIP_TRY(coarse_matvec(hd, q, w));                       // w = A^2 p
+      hipLaunchKernelGGL(caxpy_norm_kernel, dim3(CRED), dim3(CB), 0, c->stream, n, w, cs, r, hd->part);
+      hipLaunchKernelGGL(csum1_kernel, dim3(1), dim3(CB), 0, c->stream, hd->part, cs, (int)CS_RRN);
+      hipLaunchKernelGGL(ccg_beta_kernel, dim3(1), dim3(1), 0, c->stream, cs);
+      hipLaunchKernelGGL(ccg_xp_kernel, dim3(gb), dim3(CB), 0, c->stream, n, cvec, p, r, cs);
+      HIP_TRY(hipGetLastError());
+    }
+    done += batch;
+    if (int rc = read_state()) return rc;
+    if (st[CS_FLAG] != 0.0) return fail(DWF_EBREAKDOWN, "coarse CG breakdown");
   }
+  const int it = (int)st[CS_ITERS];
   if (iters) *iters = it;
   hd->coarse_iters += it;
   return DWF_OK;
@@ -626,6 +738,8 @@ int dwf_hdcr_create(dwf_handle h, int nvec, const dwf_hdcr_params* prm, void* ws
   if (!h->coarse_both || h->nb <= 0) return fail(DWF_EINVAL, "dwf_hdcr_create: call dwf_set_blocks_ex with DWF_BOTH first");
   if (nvec < 1 || nvec > 64) return fail(DWF_EINVAL, "dwf_hdcr_create: nvec must be in [1, 64]");
   if (prm->nkrylov < 1 || prm->nkrylov > 64) return fail(DWF_EINVAL, "dwf_hdcr_create: nkrylov must be in [1, 64]");
+  if (prm->coarse_prec != DWF_F64 && prm->coarse_prec != DWF_F32)
+    return fail(DWF_EINVAL, "dwf_hdcr_create: coarse_prec must be DWF_F64 or DWF_F32");
   if (prm->smoother_order < 1 || !(prm->smoother_lo > 0) || !(prm->smoother_hi > prm->smoother_lo))
     return fail(DWF_EINVAL, "dwf_hdcr_create: smoother needs order >= 1 and 0 < lo < hi");
   if (!(prm->coarse_tol > 0) || prm->coarse_maxiter < 1)
@@ -678,8 +792,12 @@ int dwf_hdcr_set_basis(dwf_hdcr hd, const void* basis) {
     // the nine fields as a both-layout array of 9 rhs: restrict all of them
     HIP_TRY(launch_block_dot(c, DWF_F64, hd->basis, n, hd->work, 9, reinterpret_cast<double*>(hd->coef), false));
     const long long m = (long long)9 * hd->nb * n;
-    hipLaunchKernelGGL(coarse_scatter_kernel, dim3(blocks_for(m)), dim3(CB), 0, c->stream, hd->coef, hd->A, hd->nb, n,
-                       k);
+    if (hd->prm.coarse_prec == DWF_F32)
+      hipLaunchKernelGGL(coarse_scatter_kernel<float2>, dim3(blocks_for(m)), dim3(CB), 0, c->stream, hd->coef,
+                         reinterpret_cast<float2*>(hd->A), hd->nb, n, k);
+    else
+      hipLaunchKernelGGL(coarse_scatter_kernel<double2>, dim3(blocks_for(m)), dim3(CB), 0, c->stream, hd->coef,
+                         reinterpret_cast<double2*>(hd->A), hd->nb, n, k);
     HIP_TRY(hipGetLastError());
   }
   return sync(c);

@@ -231,6 +231,34 @@ def test_hdcr_solve_matches_oracle(setup):
     assert rel(got, ref.x) < 1e-7  # both within kappa(H_DW) ~ 300 times 1e-10 of the solution
 
 
+def test_fp32_coarse_operator(setup):
+    """coarse_prec = DWF_F32: the stencil is the FP64 one rounded to complex64, the apply
+    accumulates in FP64, and the solve still reaches 1e-10 in about the FP64 iterations."""
+    import paper_2103_05034_amd as dwf
+
+    op, U, hd, basis, Q, A = setup
+    hd32 = dwf.HDCR(op, hd.nvec, smoother_order=ORDER, smoother_lo=LO, smoother_hi=HI, coarse_tol=0.02, nkrylov=8,
+                    coarse_prec=dwf.DWF_F32)
+    hd32.set_basis(basis)
+    S32 = host(hd32.coarse_operator())
+    assert S32.dtype == np.complex64
+    S64 = host(hd.coarse_operator())
+    assert np.array_equal(S32, S64.astype(np.complex64))
+    A32 = dense_from_stencil(S32.astype(np.complex128), DIMS, BLOCK)
+    assert np.max(np.abs(A32 - A)) < 1e-6 * np.max(np.abs(A))
+    x = np.random.default_rng(40).standard_normal((op.nblocks, hd.nvec)) + 0j
+    y = host(hd32.coarse_apply(dev_tensor(x)))
+    assert np.max(np.abs(y.ravel() - A32 @ x.ravel())) < 1e-13 * np.max(np.abs(y))
+    eta = synth.gaussian_fermion(DIMS, LS, seed=20)
+    eta_d = pack(op, eta[None], BOTH)
+    psi64, psi32 = op.new_field(1, both=True), op.new_field(1, both=True)
+    it64, _, _ = hd.solve(eta_d, psi64, tol=1e-10, maxiter=100)
+    it32, res32, _ = hd32.solve(eta_d, psi32, tol=1e-10, maxiter=100)
+    assert res32 < 1.5e-10 and it32 <= it64 + 2
+    assert rel(L.ddw(U, unpack(op, psi32, 1, BOTH)[0], M5, MF), eta) < 2e-10
+    hd32.close()
+
+
 def test_hdcr_rejects_bad_use():
     import paper_2103_05034_amd as dwf
 
