@@ -218,7 +218,12 @@ __global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __rest
     vload<PX>(x + rhs * sx, g, i, vx);
 #pragma unroll
     for (int c = 0; c < 12; ++c) vx[c] = {fma(alpha, vp[c].re, vx[c].re), fma(alpha, vp[c].im, vx[c].im)};
-    vstore<PX>(x + rhs * sx, g, i, vx);
+    if constexpr (PX == DWF_F64) {  // x is read again only by the next iteration's update
+      const long long h = i / g.Ls;
+      Store<DWF_F64>::store_nt(x + rhs * sx, g.V4h, g.Ls, h, (int)(i - h * g.Ls), vx);
+    } else {
+      vstore<PX>(x + rhs * sx, g, i, vx);
+    }
   }
   vload<PR>(r + rhs * sr, g, i, vr);
 #pragma unroll

@@ -86,6 +86,19 @@ struct Store<DWF_F64> {
 #pragma unroll
     for (int c = 0; c < 12; ++c) p[(size_t)c * Ls] = make_double2(v[c].re, v[c].im);
   }
+  // The same with non-temporal stores, for an output that the kernel writing it
+  // does not read back: it then displaces less of the neighbour data in L2.
+  __device__ static void store_nt(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<double> v[12]) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    d2v* p = reinterpret_cast<d2v*>(base) + h * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      d2v t;
+      t.x = v[c].re;
+      t.y = v[c].im;
+      __builtin_nontemporal_store(t, p + (size_t)c * Ls);
+    }
+  }
 };
 
 template <>
