@@ -86,6 +86,16 @@ struct Store<DWF_F64> {
 #pragma unroll
     for (int c = 0; c < 12; ++c) p[(size_t)c * Ls] = make_double2(v[c].re, v[c].im);
   }
+  // non-temporal load of a field that the reading kernel uses once
+  __device__ static void load_nt(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<double> v[12]) {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v* p = reinterpret_cast<const d2v*>(base) + h * 12 * Ls + s;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const d2v t = __builtin_nontemporal_load(p + (size_t)c * Ls);
+      v[c] = {t.x, t.y};
+    }
+  }
   // The same with non-temporal stores, for an output that the kernel writing it
   // does not read back: it then displaces less of the neighbour data in L2.
   __device__ static void store_nt(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<double> v[12]) {
@@ -118,6 +128,29 @@ struct Store<DWF_F32> {
     float4* p = reinterpret_cast<float4*>(base) + h * 6 * Ls + s;
 #pragma unroll
     for (int j = 0; j < 6; ++j) p[(size_t)j * Ls] = make_float4(v[2 * j].re, v[2 * j].im, v[2 * j + 1].re, v[2 * j + 1].im);
+  }  __device__ static void load_nt(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v* p = reinterpret_cast<const f4v*>(base) + h * 6 * Ls + s;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const f4v t = __builtin_nontemporal_load(p + (size_t)j * Ls);
+      v[2 * j] = {t.x, t.y};
+      v[2 * j + 1] = {t.z, t.w};
+    }
+  }
+  // non-temporal, as for FP64
+  __device__ static void store_nt(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    f4v* p = reinterpret_cast<f4v*>(base) + h * 6 * Ls + s;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      f4v t;
+      t.x = v[2 * j].re;
+      t.y = v[2 * j].im;
+      t.z = v[2 * j + 1].re;
+      t.w = v[2 * j + 1].im;
+      __builtin_nontemporal_store(t, p + (size_t)j * Ls);
+    }
   }
 };
 
@@ -137,6 +170,9 @@ struct Store<DWF_F16S> {
       half2v t = p[(size_t)c * Ls];
       v[c] = {(float)t.x * scale, (float)t.y * scale};
     }
+  }
+  __device__ static void load_nt(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
+    load(base, V4h, Ls, h, s, v);  // plain loads: the scale array makes it two streams per spinor
   }
   __device__ static void store(char* base, size_t V4h, int Ls, size_t h, int s, const cplx<float> v[12]) {
     float m = 0.f;
