@@ -37,7 +37,8 @@ constexpr int CB = 256;       // threads per block of the vector kernels
 constexpr int CRED = 1024;    // partial sums of a reduction
 
 // out = a + cb * Gamma_5 b on fields of both parities, one rhs ([2 V4h][12][Ls]
-// complex); a may be null.
+// complex); a may be null or alias out, b must not alias out (it is read at the
+// mirrored slice).
 __global__ void __launch_bounds__(CB) g5_combine_kernel(long long nsite, int Ls, const double2* __restrict__ a,
                                                          const double2* __restrict__ b, double cb,
                                                          double2* __restrict__ out) {
@@ -400,7 +401,7 @@ struct dwf_hdcr_s {
   void* A;             // [nb][9][n][n], complex128 or complex64 (prm.coarse_prec)
   double2* coef;       // [9][nb][n]
   double2* cv[7];      // coarse vectors: d, c, r, p, q, w, b'
-  double* part;        // [2][CRED] partials, then 2 result doubles
+  double* part;        // [2][CRED] partials, 2 result doubles, then the coarse CG's CS_N scalars
   char* work;          // 9 both fields
   char* gb;            // GCR source Gamma_5 eta
   char* gr;            // GCR residual
