@@ -47,9 +47,11 @@ WORKLOADS = {
     "krylov": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, tol=1e-10),
     # Algorithm A: 4x2x4x2 blocks, 40 basis vectors; Algorithm B: 2^4 blocks, 32 (both chirality-split)
     "coarse": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, algos={"A": ((4, 2, 4, 2), 20), "B": ((2, 2, 2, 2), 16)}),
-    # Algorithm B at the HDCR tables' light mass: setup filter (m, lo, hi), smoother (lo, hi, order)
+    # Algorithm B at the HDCR tables' light mass: setup filter (m, lo, hi), smoother (lo, hi, order);
+    # Algorithm A (4x2x4x2 blocks, 20 + 20 chiral vectors) as a second leg
     "hdcr": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.001, eps=0.2, tol=1e-10, block=(2, 2, 2, 2), nraw=16,
-                 filter=(300, 0.05, 70.0), smoother=(0.5, 70.0, 12), coarse_tol=0.02, nkrylov=8),
+                 filter=(300, 0.05, 70.0), smoother=(0.5, 70.0, 12), coarse_tol=0.02, nkrylov=8,
+                 algorithm_a=dict(block=(4, 2, 4, 2), nraw=20)),
 }
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_traffic.json")
@@ -875,6 +877,27 @@ def run_hdcr(args):
     mv_bytes = nb * 9 * n * n * 16 + 2 * nb * n * 16
     ach = mv_bytes / (mv_ms * 1e-3) / 1e9
     hd.close()
+    # Algorithm A: larger blocks, more vectors, a smaller coarse grid (2048 blocks x 40)
+    ca = cfg["algorithm_a"]
+    nb_a = op.set_blocks(ca["block"], both=True)
+    nraw_a, n_a = ca["nraw"], 2 * ca["nraw"]
+    raw_a = op.new_field(nraw_a, both=True)
+    for k in range(nraw_a):
+        one = op.pack(torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=300 + k)[None]).cuda(), dwf.DWF_BOTH)
+        raw_a[k * fb : (k + 1) * fb] = one[:fb]
+        raw_a[(nraw_a + k) * fb : (nraw_a + k + 1) * fb] = one[fb:]
+    hda = dwf.HDCR(op, n_a, smoother_order=cfg["smoother"][2], smoother_lo=cfg["smoother"][0],
+                   smoother_hi=cfg["smoother"][1], coarse_tol=cfg["coarse_tol"], coarse_maxiter=5000,
+                   nkrylov=cfg["nkrylov"], coarse_prec=dwf.DWF_F32)
+    t_fa, _ = _timed(lambda: hda.filter(raw_a, nraw_a, m, lo, hi))
+    basis_a = op.new_field(n_a, both=True)
+    t_oa, _ = _timed(lambda: (op.chiral_split(raw_a, nraw_a, out=basis_a), op.block_orthonormalize(basis_a, n_a)))
+    t_ca, _ = _timed(lambda: hda.set_basis(basis_a))
+    psi = op.new_field(1, both=True)
+    t_a, (it_a, res_a, ci_a) = _timed(lambda: hda.solve(eta, psi, tol=cfg["tol"], maxiter=500))
+    log(f"HDCR Algorithm A (complex64 coarse operator): {it_a} outer, {ci_a} coarse iterations, {t_a:.3f} s, "
+        f"residual {res_a:.2e}; setup {t_fa + t_oa + t_ca:.2f} s")
+    hda.close()
     op.close()
     return {
         "metric": METRIC,
@@ -906,6 +929,11 @@ def run_hdcr(args):
             "coarse_matvec_ms": mv_ms,
             "complex64_coarse_operator": {"outer_iterations": it32, "coarse_iterations": ci32, "solve_s": t32,
                                           "true_rel_residual": res32, "coarse_matvec_ms": mv32_ms},
+            "algorithm_a_complex64": {"block": list(ca["block"]), "blocks": nb_a, "basis_vectors": n_a,
+                                      "outer_iterations": it_a, "coarse_iterations": ci_a, "solve_s": t_a,
+                                      "true_rel_residual": res_a,
+                                      "setup_s": {"filter": t_fa, "split_orthonormalize": t_oa,
+                                                  "coarse_operator": t_ca}},
         },
         "roofline": {
             "bound": "hbm",

@@ -215,7 +215,7 @@ int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
  * block[0..3] = bx, by, bz, bt sites tiling the lattice, each with all Ls
  * slices (the Algorithm A / B table uses 4x2x4x2 and 2^4 at Ls = 16).  Every
  * extent must divide the lattice extent, the block must hold equally many
- * even and odd sites, and (even sites per block) x Ls <= 512.  Blocks are
+ * even and odd sites, and (even sites per block) x Ls <= 1024.  Blocks are
  * numbered lexicographically, bx-block index fastest; *nblocks (host, may be
  * NULL) receives their count.  Builds a table in the handle's workspace;
  * SYNCHRONOUS.  The calls below work on even-parity packed fields of the
@@ -225,7 +225,7 @@ int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks);
 /* As dwf_set_blocks, with parity = DWF_EVEN (the same) or DWF_BOTH: then the
  * coarse-space calls below take fields of both parities in the packed
  * "both" layout (for n fields: the n even halves, then the n odd halves),
- * a block holds all bx*by*bz*bt of its sites (sites per block x Ls <= 512),
+ * a block holds all bx*by*bz*bt of its sites (sites per block x Ls <= 1024),
  * and dwf_chiral_split writes its 2 nvec outputs in the same layout.  The
  * two-level solver (below) coarsens the full-lattice H_DW this way. */
 int dwf_set_blocks_ex(dwf_handle h, const int block[4], int parity, int* nblocks);

@@ -1006,8 +1006,8 @@ int dwf_set_blocks_ex(dwf_handle h, const int block[4], int parity, int* nblocks
   const int vol = block[0] * block[1] * block[2] * block[3];
   if (vol % 2) return fail(DWF_EINVAL, "dwf_set_blocks: the block volume must be even");
   const int nsb = both ? vol : vol / 2;
-  if ((long long)nsb * g.Ls > 512)
-    return fail(DWF_EINVAL, "dwf_set_blocks: %s per block x Ls = %lld exceeds 512", both ? "sites" : "even sites",
+  if ((long long)nsb * g.Ls > 1024)
+    return fail(DWF_EINVAL, "dwf_set_blocks: %s per block x Ls = %lld exceeds 1024", both ? "sites" : "even sites",
                 (long long)nsb * g.Ls);
   if (both && 2 * g.V4h > (1LL << 31) - 1) return fail(DWF_EINVAL, "dwf_set_blocks: lattice too large for DWF_BOTH");
   const int n[4] = {g.X / block[0], g.Y / block[1], g.Z / block[2], g.T / block[3]};

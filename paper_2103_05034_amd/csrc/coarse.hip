@@ -20,9 +20,11 @@
 // * block_cholesky: per block G = R^dag R, then W = R^{-1}.
 //
 // One workgroup owns one block; its lane p = j * Ls + s holds one 5D site of
-// the block.  Spinor loads are contiguous along s as in every other kernel.
+// the block (blocks of more than 512 5D sites: lane p also holds site p + 512).  Spinor loads are contiguous along s as in every other kernel.
 // Sums over a block are reduced in a fixed order (wavefront shuffles, then
 // the waves in index order), so results are reproducible run to run.
+#include <algorithm>
+
 #include "dwf_internal.hpp"
 #include "kernels.hpp"
 
@@ -110,33 +112,42 @@ __device__ __forceinline__ int split_site(long long V4h, long long& h) {
 }
 
 // c[r][b][k] = <phi_k^b, v_r> for the RT right-hand sides r = blockIdx.y * RT + ...
-template <int P, int RT>
+// A lane holds PP of the block's 5D sites (p = lane + q * blockDim.x), so a block
+// may have up to PP * 512 of them.
+template <int P, int RT, int PP>
 __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
   using R = typename Store<P>::real;
   extern __shared__ double red[];
   const int b = blockIdx.x;
   const int r0 = blockIdx.y * RT;
   const int np = a.nsb * a.g.Ls;
-  const int p = threadIdx.x;
-  const bool live = p < np;
-  long long h = 0;
-  int s = 0, par = 0;
-  if (live) {
-    const int j = p / a.g.Ls;
-    s = p - j * a.g.Ls;
-    h = a.bsite[(size_t)b * a.nsb + j];
-    par = split_site(a.g.V4h, h);
-  }
-  const char* vb = a.v + par * a.v_ps;
-  const char* bb = a.basis + par * a.basis_ps;
-  cplx<R> v[RT][12];
+  bool live[PP];
+  long long h[PP];
+  int s[PP], par[PP];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) {
-    const bool use = live && (r0 + r < a.nrhs);
-#pragma unroll
-    for (int c = 0; c < 12; ++c) v[r][c] = {0, 0};
-    if (use) Store<P>::load(vb + (size_t)(r0 + r) * a.stride, a.g.V4h, a.g.Ls, h, s, v[r]);
+  for (int q = 0; q < PP; ++q) {
+    const int p = threadIdx.x + q * blockDim.x;
+    live[q] = p < np;
+    h[q] = 0;
+    s[q] = 0;
+    par[q] = 0;
+    if (live[q]) {
+      const int j = p / a.g.Ls;
+      s[q] = p - j * a.g.Ls;
+      h[q] = a.bsite[(size_t)b * a.nsb + j];
+      par[q] = split_site(a.g.V4h, h[q]);
+    }
   }
+  cplx<R> v[PP][RT][12];
+#pragma unroll
+  for (int q = 0; q < PP; ++q)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const bool use = live[q] && (r0 + r < a.nrhs);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) v[q][r][c] = {0, 0};
+      if (use) Store<P>::load(a.v + par[q] * a.v_ps + (size_t)(r0 + r) * a.stride, a.g.V4h, a.g.Ls, h[q], s[q], v[q][r]);
+    }
   // a Gram matrix (per_block) is Hermitian and its Cholesky factorisation reads
   // only the entries with basis index <= rhs index: stop at the tile's last rhs
   const int kend = a.per_block ? min(a.nvec, r0 + RT) : a.nvec;
@@ -146,21 +157,24 @@ __global__ void __launch_bounds__(512) block_dot_kernel(BlockArgs a) {
     for (int i = 0; i < 2 * RT * KG; ++i) acc[i] = 0;
 #pragma unroll
     for (int kk = 0; kk < KG; ++kk) {
-      if (live && k0 + kk < kend) {
-        cplx<R> f[12];
-        Store<P>::load(bb + (size_t)(k0 + kk) * a.stride, a.g.V4h, a.g.Ls, h, s, f);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          double re = 0, im = 0;
+      for (int q = 0; q < PP; ++q) {
+        if (live[q] && k0 + kk < kend) {
+          cplx<R> f[12];
+          Store<P>::load(a.basis + par[q] * a.basis_ps + (size_t)(k0 + kk) * a.stride, a.g.V4h, a.g.Ls, h[q], s[q], f);
 #pragma unroll
-          for (int c = 0; c < 12; ++c) {  // conj(f) v
-            re = fma((double)f[c].re, (double)v[r][c].re, re);
-            re = fma((double)f[c].im, (double)v[r][c].im, re);
-            im = fma((double)f[c].re, (double)v[r][c].im, im);
-            im = fma(-(double)f[c].im, (double)v[r][c].re, im);
+          for (int r = 0; r < RT; ++r) {
+            double re = acc[2 * (r * KG + kk)], im = acc[2 * (r * KG + kk) + 1];
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {  // conj(f) v
+              re = fma((double)f[c].re, (double)v[q][r][c].re, re);
+              re = fma((double)f[c].im, (double)v[q][r][c].im, re);
+              im = fma((double)f[c].re, (double)v[q][r][c].im, im);
+              im = fma(-(double)f[c].im, (double)v[q][r][c].re, im);
+            }
+            acc[2 * (r * KG + kk)] = re;
+            acc[2 * (r * KG + kk) + 1] = im;
           }
-          acc[2 * (r * KG + kk)] = re;
-          acc[2 * (r * KG + kk) + 1] = im;
         }
       }
     }
@@ -281,18 +295,6 @@ __global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
   extern __shared__ double cs[];  // complex coefficients of the workgroup
   const int b = blockIdx.x;
   const int np = a.nsb * a.g.Ls;
-  const int p = threadIdx.x;
-  const bool live = p < np;
-  long long h = 0;
-  int s = 0, par = 0;
-  if (live) {
-    const int j = p / a.g.Ls;
-    s = p - j * a.g.Ls;
-    h = a.bsite[(size_t)b * a.nsb + j];
-    par = split_site(a.g.V4h, h);
-  }
-  const char* bb = a.basis + par * a.basis_ps;
-  char* ob = a.out + par * a.out_ps;
   const int n = a.nvec;
   if (INPLACE) {
     for (int i = threadIdx.x; i < n * n; i += blockDim.x) {
@@ -314,40 +316,48 @@ __global__ void __launch_bounds__(512) block_combine_kernel(BlockArgs a) {
     }
   }
   __syncthreads();
-  if (!live) return;
-  const int ntiles = INPLACE ? (n + KT - 1) / KT : 1;
-  for (int tile = ntiles - 1; tile >= 0; --tile) {
-    const int k0 = tile * KT;                         // INPLACE: outputs k0 .. k0+KT-1
-    const int jmax = INPLACE ? min(n, k0 + KT) : n;  // inputs j < jmax
-    cplx<double> acc[KT][12];
+  // every lane handles the block's 5D sites p = lane, lane + blockDim.x, ...
+  for (int p = threadIdx.x; p < np; p += blockDim.x) {
+    const int jsite = p / a.g.Ls;
+    const int s = p - jsite * a.g.Ls;
+    long long h = a.bsite[(size_t)b * a.nsb + jsite];
+    const int par = split_site(a.g.V4h, h);
+    const char* bb = a.basis + par * a.basis_ps;
+    char* ob = a.out + par * a.out_ps;
+    const int ntiles = INPLACE ? (n + KT - 1) / KT : 1;
+    for (int tile = ntiles - 1; tile >= 0; --tile) {
+      const int k0 = tile * KT;                         // INPLACE: outputs k0 .. k0+KT-1
+      const int jmax = INPLACE ? min(n, k0 + KT) : n;  // inputs j < jmax
+      cplx<double> acc[KT][12];
 #pragma unroll
-    for (int t = 0; t < KT; ++t)
+      for (int t = 0; t < KT; ++t)
 #pragma unroll
-      for (int c = 0; c < 12; ++c) acc[t][c] = {0, 0};
-    for (int j = 0; j < jmax; ++j) {
-      cplx<R> f[12];
-      Store<P>::load(bb + (size_t)j * a.stride, a.g.V4h, a.g.Ls, h, s, f);
+        for (int c = 0; c < 12; ++c) acc[t][c] = {0, 0};
+      for (int j = 0; j < jmax; ++j) {
+        cplx<R> f[12];
+        Store<P>::load(bb + (size_t)j * a.stride, a.g.V4h, a.g.Ls, h, s, f);
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        // coefficient of phi_j in output t
-        const int idx = INPLACE ? (j * n + k0 + t) : (t * n + j);
-        if (INPLACE && (k0 + t >= n || j > k0 + t)) continue;
-        const double cr = cs[2 * idx], ci = cs[2 * idx + 1];
+        for (int t = 0; t < KT; ++t) {
+          // coefficient of phi_j in output t
+          const int idx = INPLACE ? (j * n + k0 + t) : (t * n + j);
+          if (INPLACE && (k0 + t >= n || j > k0 + t)) continue;
+          const double cr = cs[2 * idx], ci = cs[2 * idx + 1];
 #pragma unroll
-        for (int c = 0; c < 12; ++c) {
-          acc[t][c].re = fma(cr, (double)f[c].re, fma(-ci, (double)f[c].im, acc[t][c].re));
-          acc[t][c].im = fma(cr, (double)f[c].im, fma(ci, (double)f[c].re, acc[t][c].im));
+          for (int c = 0; c < 12; ++c) {
+            acc[t][c].re = fma(cr, (double)f[c].re, fma(-ci, (double)f[c].im, acc[t][c].re));
+            acc[t][c].im = fma(cr, (double)f[c].im, fma(ci, (double)f[c].re, acc[t][c].im));
+          }
         }
       }
-    }
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      const int k = INPLACE ? k0 + t : blockIdx.y * KT + t;
-      if (k >= (INPLACE ? n : a.nrhs)) continue;
-      cplx<R> o[12];
+      for (int t = 0; t < KT; ++t) {
+        const int k = INPLACE ? k0 + t : blockIdx.y * KT + t;
+        if (k >= (INPLACE ? n : a.nrhs)) continue;
+        cplx<R> o[12];
 #pragma unroll
-      for (int c = 0; c < 12; ++c) o[c] = {(R)acc[t][c].re, (R)acc[t][c].im};
-      Store<P>::store(ob + (size_t)k * a.stride, a.g.V4h, a.g.Ls, h, s, o);
+        for (int c = 0; c < 12; ++c) o[c] = {(R)acc[t][c].re, (R)acc[t][c].im};
+        Store<P>::store(ob + (size_t)k * a.stride, a.g.V4h, a.g.Ls, h, s, o);
+      }
     }
   }
 }
@@ -423,7 +433,8 @@ __global__ void __launch_bounds__(64) block_cholesky_kernel(const double* __rest
 // Launchers
 // ---------------------------------------------------------------------------
 static int lanes_of(const dwf_context* c) { return c->nsb * c->g.Ls; }
-static int group_of(int lanes) { return (lanes + 63) / 64 * 64; }
+// workgroup of a per-block kernel: one lane per 5D site of the block, at most 512
+static int group_of(int lanes) { return std::min(512, (lanes + 63) / 64 * 64); }
 
 hipError_t launch_chiral_split(dwf_context* c, int prec, const char* in, char* out, int nvec) {
   const long long n = c->g.V4h * c->g.Ls;
@@ -455,11 +466,21 @@ static BlockArgs block_args(const dwf_context* c, int prec, const char* basis, i
   return a;
 }
 
-template <int P, int RT>
+template <int P, int RT, int PP>
 static void dot_t(const dwf_context* c, const BlockArgs& a) {
   const int lanes = group_of(lanes_of(c));
   const size_t lds = (size_t)(lanes / 64) * 2 * RT * KG * sizeof(double);
-  hipLaunchKernelGGL((block_dot_kernel<P, RT>), dim3(a.nb, (a.nrhs + RT - 1) / RT), dim3(lanes), lds, c->stream, a);
+  hipLaunchKernelGGL((block_dot_kernel<P, RT, PP>), dim3(a.nb, (a.nrhs + RT - 1) / RT), dim3(lanes), lds, c->stream,
+                     a);
+}
+
+// blocks of up to 512 5D sites: one site and two rhs per lane; up to 1024: two sites and one rhs
+template <int P>
+static void dot_p(const dwf_context* c, const BlockArgs& a) {
+  if (lanes_of(c) <= 512)
+    dot_t<P, 2, 1>(c, a);
+  else
+    dot_t<P, 1, 2>(c, a);
 }
 
 hipError_t launch_block_dot(dwf_context* c, int prec, const char* basis, int nvec, const char* v, int nrhs,
@@ -471,9 +492,9 @@ hipError_t launch_block_dot(dwf_context* c, int prec, const char* basis, int nve
   a.coef = coef;
   a.per_block = per_block ? 1 : 0;
   switch (prec) {
-    case DWF_F64: dot_t<DWF_F64, 2>(c, a); break;
-    case DWF_F32: dot_t<DWF_F32, 2>(c, a); break;
-    default: dot_t<DWF_F16S, 2>(c, a); break;
+    case DWF_F64: dot_p<DWF_F64>(c, a); break;
+    case DWF_F32: dot_p<DWF_F32>(c, a); break;
+    default: dot_p<DWF_F16S>(c, a); break;
   }
   return hipGetLastError();
 }

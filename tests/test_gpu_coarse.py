@@ -196,3 +196,36 @@ def test_block_orthonormalize_max_nvec():
     Q = unpack(op, buf, 64, EVEN)
     Qo, _ = C.block_orthonormalize(list(V), dims, block)
     assert max(relmax(Q[k], Qo[k]) for k in range(64)) < 1e-10
+
+
+@pytest.mark.parametrize("both,block", [(False, (4, 4, 4, 2)), (True, (4, 2, 4, 2))])
+def test_blocks_of_1024_5d_sites(both, block):
+    """Ls = 16 with 64 sites per block (even sites of 4x4x4x2, or all sites of the
+    Algorithm A block 4x2x4x2): 1024 5D sites, two per lane of the per-block kernels."""
+    import torch
+
+    dims, Ls = (8, 4, 8, 4), 16
+    parity = 2 if both else EVEN
+    op, _ = make_operator(dims, Ls, prec=F64, max_nrhs=8, max_cg_rhs=2)
+    nb = op.set_blocks(block, both=both)
+    assert nb == C.nblocks(dims, block)
+    raw = synth.gaussian_fermion_batch(dims, Ls, 3, 50)
+    if not both:
+        raw = np.stack([L.on_parity(f, L.EVEN) for f in raw])
+    split = unpack(op, op.chiral_split(pack(op, raw, parity), 3), 6, parity)
+    basis = pack(op, split, parity)
+    op.block_orthonormalize(basis, 6)
+    Q = unpack(op, basis, 6, parity)
+    Qo, _ = C.block_orthonormalize(list(split), dims, block)
+    for k in range(6):
+        assert relmax(Q[k], Qo[k]) < 1e-12
+    W = synth.gaussian_fermion_batch(dims, Ls, 3, 51)
+    if not both:
+        W = np.stack([L.on_parity(f, L.EVEN) for f in W])
+    c = coarse_host(op.restrict(basis, 6, pack(op, W, parity), 3))
+    for r in range(3):
+        assert relmax(c[r], C.restrict(list(Q), W[r], dims, block)) < 1e-13
+    cc = np.random.default_rng(52).standard_normal((2, nb, 6)) + 0.5j
+    got = unpack(op, op.prolong(basis, 6, torch.from_numpy(cc).cuda(), 2), 2, parity)
+    for r in range(2):
+        assert relmax(got[r], C.prolong(list(Q), cc[r], dims, block)) < 1e-14
