@@ -50,7 +50,7 @@ WORKLOADS = {
     # Algorithm B at the HDCR tables' light mass: setup filter (m, lo, hi), smoother (lo, hi, order);
     # Algorithm A (4x2x4x2 blocks, 20 + 20 chiral vectors) as a second leg
     "hdcr": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.001, eps=0.2, tol=1e-10, block=(2, 2, 2, 2), nraw=16,
-                 filter=(300, 0.05, 70.0), smoother=(0.5, 70.0, 12), coarse_tol=0.02, nkrylov=8,
+                 filter=(300, 0.05, 70.0), smoother=(0.5, 70.0, 16), coarse_tol=0.02, nkrylov=8,
                  algorithm_a=dict(block=(4, 2, 4, 2), nraw=20)),
 }
 
@@ -787,7 +787,7 @@ def run_hdcr(args):
     series from one Gaussian gives block-wise dependent vectors on these smooth links, whose
     light space has about a dozen modes), chirality split, block orthonormalisation and the
     little Dirac operator; then
-    pGCR(H_DW) with the V(1,1) preconditioner (Chebyshev smoother [0.5, 70] of order 12, CGNR
+    pGCR(H_DW) with the V(1,1) preconditioner (Chebyshev smoother [0.5, 70] of order 16, CGNR
     coarse solve to 0.02) to 1e-10, against the red-black CG solve of the same system.  The
     coarse matvec, which dominates the solve, is timed separately against its bytes."""
     import torch
