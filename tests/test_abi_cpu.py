@@ -93,3 +93,32 @@ def test_calls_on_null_handle_fail_cleanly(lib):
     assert "null handle" in dwf.last_error()
     assert lib.dwf_set_progress(None, dwf.PROGRESS_FN(), None, 0) == dwf.DWF_EINVAL
     assert lib.dwf_destroy(None) == dwf.DWF_OK
+
+
+def test_two_level_calls_on_null_handles_fail_cleanly(lib):
+    """The coarse-space and HDCR entry points reject null handles and report why,
+    before any device work."""
+    import paper_2103_05034_amd as dwf
+
+    blk = (ctypes.c_int * 4)(2, 2, 2, 2)
+    assert lib.dwf_set_blocks_ex(None, blk, dwf.DWF_BOTH, None) == dwf.DWF_EINVAL
+    assert lib.dwf_hdw(None, None, None, 1) == dwf.DWF_EINVAL
+    assert lib.dwf_hdcr_workspace_bytes(None, 8, 8) == 0
+    prm = dwf.HDCRParams(12, 0.5, 60.0, 0.02, 100, 8, dwf.DWF_F64)
+    out = ctypes.c_void_p()
+    assert lib.dwf_hdcr_create(None, 8, ctypes.byref(prm), None, 0, ctypes.byref(out)) == dwf.DWF_EINVAL
+    assert out.value is None
+    for call in (
+        lambda: lib.dwf_hdcr_set_basis(None, None),
+        lambda: lib.dwf_hdcr_filter(None, 4, 0.1, 60.0, None, 1),
+        lambda: lib.dwf_hdcr_series(None, 4, 0.1, 60.0, 2, 2, None, None),
+        lambda: lib.dwf_hdcr_coarse_apply(None, None, None),
+        lambda: lib.dwf_hdcr_coarse_solve(None, None, None, 1e-6, 10, None),
+        lambda: lib.dwf_hdcr_smoother(None, None, None),
+        lambda: lib.dwf_hdcr_vcycle(None, None, None, None),
+        lambda: lib.dwf_hdcr_solve(None, None, None, 1e-10, 10, None, None, None),
+    ):
+        assert call() == dwf.DWF_EINVAL
+        assert "null HDCR handle" in dwf.last_error()
+    assert lib.dwf_hdcr_coarse_data(None) is None
+    assert lib.dwf_hdcr_destroy(None) == dwf.DWF_OK
