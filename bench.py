@@ -197,11 +197,14 @@ def run_rb_solve(args):
     if args.tile:
         op.set_tile(args.tile, args.depth)
         tile = (args.tile, args.depth)
+        if args.order < 0:  # pick the traversal order by timing M_pc^dag M_pc in the given tile
+            args.order = _pick_order(op)
+    elif args.order < 0:  # tile, depth and order together, timed on the solver itself
+        spb, depth, args.order = _pick_shape_by_cg(op, dims, Ls)
+        tile = (spb, depth)
     else:
         spb, depth, _ = op.autotune(1, 10)
         tile = (spb, depth)
-    if args.order < 0:  # pick the traversal order by timing M_pc^dag M_pc in the chosen tile
-        args.order = _pick_order(op)
     log(f"hop launch shape: {tile[0]} sites per workgroup, pipeline depth {tile[1]}, order {args.order}")
     eta = op.pack(eta_nat, dwf.DWF_BOTH)
     del eta_nat
@@ -303,6 +306,41 @@ def run_rb_solve(args):
     }
     op.close()
     return out
+
+
+def _pick_shape_by_cg(op, dims, Ls, iters=60):
+    """Sites per workgroup, load-pipeline depth and traversal order of the hop kernels that
+    make 60 FP64 CG iterations (the timed solve's own mix of passes) fastest, best of two
+    timings per shape; orders a lattice does not admit are skipped."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    b = op.pack(torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=9)[None]).cuda(), dwf.DWF_EVEN)
+    x = op.new_field(1)
+    best = None
+    for mode in (0, 1, 2):
+        try:
+            op.set_order(mode)
+        except dwf.DWFError:
+            continue
+        for spb in (4, 8, 16):
+            for depth in (2, 3):
+                op.set_tile(spb, depth, 1)
+                op.cg(b, x, 1, tol=1e-30, maxiter=10, allow_noconv=True)
+                t = None
+                for _ in range(2):
+                    x.zero_()
+                    tk, _ = _timed(lambda: op.cg(b, x, 1, tol=1e-30, maxiter=iters, allow_noconv=True))
+                    t = tk if t is None else min(t, tk)
+                if best is None or t < best[0]:
+                    best = (t, spb, depth, mode)
+    _, spb, depth, mode = best
+    op.set_order(mode)
+    op.set_tile(spb, depth, 1)
+    log(f"launch shape by CG timing: {spb} sites, depth {depth}, order {mode} ({best[0] / iters * 1e3:.3f} ms per iteration)")
+    return spb, depth, mode
 
 
 def _pick_order(op, reps=20):
