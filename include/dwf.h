@@ -267,7 +267,9 @@ int dwf_prolong(dwf_handle h, const void* basis, int nvec, const void* coarse, i
 
 /* out = H_DW in = Gamma_5 D_DW in, (Gamma_5 v)_s = gamma_5 v_{Ls-1-s} (Spectrum
  * of domain wall fermions section), for nrhs packed "both" fields.  Needs a
- * DWF_F64 handle with max_cg_rhs >= 1. */
+ * DWF_F64 handle with max_cg_rhs >= 1: D_DW in goes through the handle's FP64
+ * CG work fields, so it must not overlap a dwf_cg / dwf_solve_* call on the
+ * same handle (both are ordered on the handle's stream). */
 int dwf_hdw(dwf_handle h, const void* in, void* out, int nrhs);
 
 /* Parameters of Algorithms A / B (their table): the smoother
