@@ -207,3 +207,38 @@ def test_mixed_workload_fp32_field_solve_sampled():
     Ax = oracle_at_sites(lambda u, p: L.mpcdagmpc(u, L.on_parity(p, EVEN), 1.8, mf), U, X, dims, sites, 4)
     bs = gpu_at_sites(psi, sites)
     assert rel(Ax, bs) < 1e-7
+
+
+def test_rb_workload_every_bench_launch_shape():
+    """16^3 x 32, Ls = 16, FP64: the launch shapes bench.py chooses from (4 / 8 / 16 sites per
+    workgroup, pipeline depth 2 / 3, traversal orders 0 / 1 / 2) give bit-identical
+    M_pc^dag M_pc (a site's arithmetic does not depend on the tile or the order), and the
+    shape the bench usually picks (8 sites, depth 3, order 1) matches the oracle at a
+    sampled site."""
+    import torch
+
+    dims, Ls, mf = (16, 16, 16, 32), 16, 0.01
+    op, U = make_operator(dims, Ls, eps=0.2, seed=0, prec=F64, max_nrhs=1, max_cg_rhs=0, mf=mf)
+    psi = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=11), EVEN)
+    v = pack(op, psi[None], EVEN)
+    ref = None
+    for order in (0, 1, 2):
+        op.set_order(order)
+        for spb in (4, 8, 16):
+            for depth in (2, 3):
+                op.set_tile(spb, depth, 1)
+                w = op.new_field(1)
+                op.mpcdagmpc(v, w, 1)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = w.clone()
+                else:
+                    assert torch.equal(w, ref), (order, spb, depth)
+    op.set_order(1)
+    op.set_tile(8, 3, 1)
+    w = op.new_field(1)
+    op.mpcdagmpc(v, w, 1)
+    sites = sample_sites(dims, 1, seed=12, parity=EVEN)
+    got = gpu_at_sites(unpack(op, w, 1, EVEN)[0], sites)
+    exp = oracle_at_sites(lambda u, p: L.mpcdagmpc(u, L.on_parity(p, EVEN), 1.8, mf), U, psi, dims, sites, 4)
+    assert rel(got, exp) < 1e-13
