@@ -243,7 +243,15 @@ hop_kernel(HopArgs a) {
         if (idx < total) {
           const int dk = idx / spb;
           const int h2 = site_h[idx - dk * spb];
-          if (h2 >= 0) t[u] = lg[(size_t)dk * V4h + h2];
+          if (h2 >= 0) {
+            if constexpr (PREC == DWF_F64) {  // each site's links are read by its own workgroup only
+              typedef double dv2 __attribute__((ext_vector_type(2)));
+              const dv2 q = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(lg + (size_t)dk * V4h + h2));
+              t[u] = V{q.x, q.y};
+            } else {  // 8-byte links: plain loads (non-temporal ones were slower)
+              t[u] = lg[(size_t)dk * V4h + h2];
+            }
+          }
         }
       }
 #pragma unroll
