@@ -177,17 +177,23 @@ int dwf_solve_unprec(dwf_handle h, const void* eta, void* psi, double tol, int m
                      double* true_rel_resid);
 
 /* SYNCHRONOUS.  Power method for lambda_max of M_pc^dag M_pc from the start
- * vector v (handle precision, one rhs, overwritten with the last iterate). */
+ * vector v (handle precision, one rhs, overwritten with the last iterate).
+ * The handle keeps the estimate (a Rayleigh quotient, so never above the true
+ * lambda_max) until its links or Schur form change; the three calls below
+ * then return the warning DWF_WLAMBDA, with their results computed, when
+ * their upper bound lies below it. */
 int dwf_power(dwf_handle h, void* v, int iters, double rtol, double* lambda_max, int* iters_done);
 
 /* In place: vecs <- T_order(x(A)) vecs, x(A) = 2 (A - lo) / (hi - lo) - 1,
  * A = M_pc^dag M_pc, for nvecs right-hand sides at once (handle precision),
- * no normalisation (Chebyshev smoothers / Deflation basis setup sections). */
+ * no normalisation (Chebyshev smoothers / Deflation basis setup sections).
+ * DWF_WLAMBDA if hi is below dwf_power's lambda_max (see there). */
 int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* vecs, int nvecs);
 
 /* The recursive series of the setup: v0 = T_m(x_[lam_lo, lam_max](A)) eta,
  * then out_series[k] = T_{k delta}(2 A / lam_max - 1) v0 for k = 0..nvec-1
- * (one rhs; out_series holds nvec packed fields).  eta is not modified. */
+ * (one rhs; out_series holds nvec packed fields).  eta is not modified.
+ * DWF_WLAMBDA if lam_max is below dwf_power's lambda_max. */
 int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int delta, int nvec,
                          const void* eta, void* out_series);
 
@@ -198,7 +204,8 @@ int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int
  * theta_k = pi (k + 1/2) / order.  A polynomial approximation of
  * (M_pc^dag M_pc)^{-1} M_pc^dag = M_pc^{-1} on [lo, hi]; order applications
  * of A plus one of M_pc^dag.  in, out: nrhs packed even fields (handle
- * precision), distinct.  Requires order >= 1 and 0 < lo < hi. */
+ * precision), distinct.  Requires order >= 1 and 0 < lo < hi.  DWF_WLAMBDA if
+ * hi is below dwf_power's lambda_max. */
 int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const void* in_e, void* out_e,
                            int nrhs);
 

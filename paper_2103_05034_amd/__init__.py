@@ -335,19 +335,28 @@ class Operator:
         _check(self.lib.dwf_power(self.h, _ptr(v), iters, rtol, ctypes.byref(lam), ctypes.byref(done)))
         return lam.value, done.value
 
+    @staticmethod
+    def _warn_lambda(code):
+        """DWF_WLAMBDA (the filter's top is below the measured lambda_max) becomes a Python warning."""
+        if _check(code, allow=(DWF_WLAMBDA,)) == DWF_WLAMBDA:
+            import warnings
+
+            warnings.warn(last_error(), RuntimeWarning, stacklevel=3)
+
     def chebyshev_filter(self, vecs, nvecs, order, lo, hi):
         self._sync_stream()
-        _check(self.lib.dwf_chebyshev_filter(self.h, order, lo, hi, _ptr(vecs), nvecs))
+        self._warn_lambda(self.lib.dwf_chebyshev_filter(self.h, order, lo, hi, _ptr(vecs), nvecs))
         return vecs
 
     def chebyshev_series(self, eta, out_series, m, lam_lo, lam_max, delta, nvec):
         self._sync_stream()
-        _check(self.lib.dwf_chebyshev_series(self.h, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out_series)))
+        self._warn_lambda(
+            self.lib.dwf_chebyshev_series(self.h, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out_series)))
         return out_series
 
     def chebyshev_smoother(self, inp, out, order, lo, hi, nrhs=1):
         self._sync_stream()
-        _check(self.lib.dwf_chebyshev_smoother(self.h, order, lo, hi, _ptr(inp), _ptr(out), nrhs))
+        self._warn_lambda(self.lib.dwf_chebyshev_smoother(self.h, order, lo, hi, _ptr(inp), _ptr(out), nrhs))
         return out
 
     def gram_schmidt(self, vecs, nvecs):

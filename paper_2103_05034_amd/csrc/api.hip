@@ -356,6 +356,7 @@ int dwf_update_links(dwf_handle h, const void* U) {
   if (int r = check_h(h)) return r;
   if (!U) return fail(DWF_EINVAL, "U is NULL");
   HIP_TRY(launch_pack_links(h, U));
+  h->lam_max = 0;  // the operator changed
   return DWF_OK;
 }
 
@@ -750,6 +751,16 @@ int dwf_power(dwf_handle h, void* v, int iters, double rtol, double* lambda_max,
   if (int rc = sync(h)) return rc;
   if (lambda_max) *lambda_max = lam;
   if (iters_done) *iters_done = k;
+  h->lam_max = lam;
+  return DWF_OK;
+}
+
+// DWF_WLAMBDA (a warning; the result is computed) when a filter's upper bound lies
+// below the lambda_max that dwf_power measured on this operator: the polynomial then
+// grows without bound on the modes above it instead of staying within [-1, 1].
+static int warn_lambda(dwf_handle h, double hi, const char* who) {
+  if (h->lam_max > 0 && hi < h->lam_max)
+    return fail(DWF_WLAMBDA, "%s: upper bound %g is below the measured lambda_max %g", who, hi, h->lam_max);
   return DWF_OK;
 }
 
@@ -782,7 +793,7 @@ int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* ve
     const int n = nvecs - r0 < h->max_nrhs ? nvecs - r0 : h->max_nrhs;
     if (int rc = cheb_chunk(h, order, lo, hi, reinterpret_cast<char*>(vecs) + r0 * fb, h->cheb_a, n)) return rc;
   }
-  return DWF_OK;
+  return warn_lambda(h, hi, "dwf_chebyshev_filter");
 }
 
 int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int delta, int nvec, const void* eta,
@@ -796,7 +807,7 @@ int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int
   char* S = reinterpret_cast<char*>(out_series);
   HIP_TRY(blas_copy(h, P, reinterpret_cast<const char*>(eta), P, S, 1));
   if (int rc = cheb_chunk(h, m, lam_lo, lam_max, S, h->cheb_a, 1)) return rc;
-  if (nvec == 1) return DWF_OK;
+  if (nvec == 1) return warn_lambda(h, lam_max, "dwf_chebyshev_series");
   // second recurrence over [0, lam_max]: x(A) = 2A/lam_max - 1
   char* prev = h->cheb_a;
   char* cur = h->cheb_a + fb;
@@ -814,7 +825,7 @@ int dwf_chebyshev_series(dwf_handle h, int m, double lam_lo, double lam_max, int
     prev = cur;
     cur = t;
   }
-  return DWF_OK;
+  return warn_lambda(h, lam_max, "dwf_chebyshev_series");
 }
 
 // Chebyshev smoother of the normal system: out = [c_0/2 + sum_{j=1}^N c_j T_j(x(A))] M_pc^dag in,
@@ -863,7 +874,7 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
     // out = x(A) b_1 - b_2 + c_0 w / 2 (written over w)
     HIP_TRY(cheb_step(h, P, B1, W, B1, B2, 2.0 / wdt, -(hi + lo) / wdt, -1.0, h->t_buf, h->u_buf, n, W, 0.5 * c[0]));
   }
-  return DWF_OK;
+  return warn_lambda(h, hi, "dwf_chebyshev_smoother");
 }
 
 int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host) {
@@ -1118,6 +1129,7 @@ int dwf_prolong(dwf_handle h, const void* basis, int nvec, const void* coarse, i
 int dwf_set_schur_form(dwf_handle h, int form) {
   if (int r = check_h(h)) return r;
   if (form != 1 && form != 2) return fail(DWF_EINVAL, "dwf_set_schur_form: form must be 1 or 2");
+  if (form != h->schur_form) h->lam_max = 0;  // another operator
   h->schur_form = form;
   return DWF_OK;
 }

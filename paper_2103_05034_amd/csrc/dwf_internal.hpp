@@ -361,6 +361,7 @@ struct dwf_context {
   int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
   int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
   int schur_form;  // 1: M_ee - M_eo M_oo^{-1} M_oe; 2: 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe
+  double lam_max;  // lambda_max of M_pc^dag M_pc last measured by dwf_power (0: none since the operator changed)
   // coarse-space blocks: extents, count, sites per block and their indices [nb][nsb] (even sites
   // for even-parity fields; all sites, odd ones as h + V4h, for fields of both parities), and the
   // neighbouring block in each of the 8 hop directions [nb][8]

@@ -242,3 +242,24 @@ def test_rb_workload_every_bench_launch_shape():
     got = gpu_at_sites(unpack(op, w, 1, EVEN)[0], sites)
     exp = oracle_at_sites(lambda u, p: L.mpcdagmpc(u, L.on_parity(p, EVEN), 1.8, mf), U, psi, dims, sites, 4)
     assert rel(got, exp) < 1e-13
+
+
+def test_rb_workload_gauge_covariance():
+    """16^3 x 32, Ls = 16, FP64: with U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag and psi -> g psi,
+    M_pc^dag M_pc[U^g] (g psi) = g (M_pc^dag M_pc[U] psi) over the whole lattice."""
+    dims, Ls = (16, 16, 16, 32), 16
+    U = synth.gauge_links(dims, eps=0.2, seed=0)
+    g = synth.gauge_transform(dims, seed=13)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        Ug[..., mu, :, :] = g @ U[..., mu, :, :] @ L.dagger(L.shift(g, mu, +1))
+    gpsi = lambda f: f @ np.swapaxes(g, -1, -2)  # noqa: E731  colour rotation per site
+    psi = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=14), EVEN)
+    outs = []
+    for links, field in ((U, psi), (Ug, gpsi(psi))):
+        op, _ = make_operator(dims, Ls, prec=F64, max_nrhs=1, max_cg_rhs=0, U=links)
+        w = op.new_field(1)
+        op.mpcdagmpc(pack(op, field[None], EVEN), w, 1)
+        outs.append(unpack(op, w, 1, EVEN)[0])
+        op.close()
+    assert rel(outs[1], gpsi(outs[0])) < 1e-13

@@ -12,7 +12,7 @@ import pytest
 
 import synth
 from oracle import krylov, lattice as L
-from tests.gpu_util import M5, MF, make_operator, pack, rel, rel_per_rhs, unpack
+from tests.gpu_util import M5, MF, dev_tensor, make_operator, pack, rel, rel_per_rhs, unpack
 
 pytestmark = pytest.mark.gpu
 
@@ -235,3 +235,35 @@ def test_mixed_cg_near_physical_mass(dims, Ls, prec, slack):
     code, it, res = op.cg(b, x, 1, tol=1e-10, maxiter=int(slack * it64[0]) + 50)
     assert code == 0 and res[0] < 1.5e-10
     assert it[0] <= slack * it64[0]
+
+
+def test_filter_warns_when_its_top_is_below_the_measured_lambda_max():
+    """After dwf_power, a filter, series or smoother whose upper bound lies below the
+    measured lambda_max still computes its result (the oracle's, for that bound) but
+    returns DWF_WLAMBDA; a bound above it, or a changed operator, gives no warning."""
+    import warnings
+
+    import paper_2103_05034_amd as dwf
+
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, prec=F64, max_nrhs=2)
+    v = pack(op, even_fields(dims, Ls, 1, seed=70), EVEN)
+    lam, _ = op.power(v, iters=200, rtol=1e-10)
+    A = lambda w: L.mpcdagmpc(U, w, M5, MF)  # noqa: E731
+    x = even_fields(dims, Ls, 1, seed=71)
+    low = 0.5 * lam
+    buf = pack(op, x, EVEN)
+    with pytest.warns(RuntimeWarning, match="below the measured lambda_max"):
+        op.chebyshev_filter(buf, 1, 6, 0.1, low)
+    want, _ = krylov.chebyshev_filter(A, x[0], 6, 0.1, low)
+    assert rel(unpack(op, buf, 1, EVEN)[0], want) < 1e-12
+    out = op.new_field(1)
+    with pytest.warns(RuntimeWarning):
+        op.chebyshev_smoother(pack(op, x, EVEN), out, 4, 0.1, low)
+    code = op.lib.dwf_chebyshev_filter(op.h, 3, 0.1, low, dwf._ptr(pack(op, x, EVEN)), 1)
+    assert code == dwf.DWF_WLAMBDA
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        op.chebyshev_filter(pack(op, x, EVEN), 1, 3, 0.1, 1.01 * lam)
+        op.update_links(dev_tensor(U))  # the operator may have changed: the estimate is dropped
+        op.chebyshev_filter(pack(op, x, EVEN), 1, 3, 0.1, low)
