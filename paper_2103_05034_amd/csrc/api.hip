@@ -194,12 +194,10 @@ hipError_t mdagm_pap(dwf_context* c, int prec, const char* p, char* q, char* t, 
 // One FP64 CG operator step without writing A p: u = M_pc p with p.Ap = |u|^2
 // into S_PAP, alpha from it, then the last pass of M_pc^dag u updates
 // r -= alpha A p in place and leaves |r|^2 in S_RR.
-hipError_t cg_step_f64(dwf_context* c, const char* p, char* r, char* t, char* u, int n) {
+hipError_t cg_step_f64(dwf_context* c, const char* p, char* r, char* t, char* u, int n, double tol2) {
   hipError_t e = mpc_chunk(c, DWF_F64, p, u, t, n, 0, c->hop_partials);
   if (e != hipSuccess) return e;
-  e = reduce_partials(c, c->hop_partials, hop_blocks(c), n, S_PAP);
-  if (e != hipSuccess) return e;
-  e = scal_alpha(c, n);
+  e = reduce_partials_step(c, c->hop_partials, hop_blocks(c), n, S_PAP, 1, tol2);  // p.Ap, alpha
   if (e != hipSuccess) return e;
   HopArgs a{};
   a.in = u;
@@ -216,7 +214,7 @@ hipError_t cg_step_f64(dwf_context* c, const char* p, char* r, char* t, char* u,
   b.scal = c->scalars;
   e = launch_hop(c, DWF_F64, b, DWF_EVEN, 1, EPI_CGR, n);
   if (e != hipSuccess) return e;
-  return reduce_partials(c, c->hop_partials, hop_blocks(c), n, S_RR);
+  return reduce_partials_step(c, c->hop_partials, hop_blocks(c), n, S_RR, 2, tol2);  // |r|^2, beta, convergence
 }
 
 hipError_t mdagm_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, char* u, int n) {
@@ -538,15 +536,18 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
       }
     }
     if (h->schur_form == 1) {
-      HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs));  // alpha, r -= alpha A p, |r|^2
+      // alpha, r -= alpha A p, |r|^2, beta and the convergence step; then x += alpha p,
+      // p = r + beta p (the convergence step changes neither alpha nor beta)
+      HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs, tol2));
+      HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, nrhs));
     } else {
       HIP_TRY(mdagm_pap(h, DWF_F64, p, q, h->t64, h->u64, nrhs));
       HIP_TRY(scal_alpha(h, nrhs));
       HIP_TRY(cg_update_r(h, DWF_F64, r, DWF_F64, q, nrhs));
+      HIP_TRY(scal_beta(h, nrhs));
+      HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, nrhs));
+      HIP_TRY(scal_converge(h, nrhs, tol2, true));
     }
-    HIP_TRY(scal_beta(h, nrhs));
-    HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F64, r, DWF_F64, p, nrhs));
-    HIP_TRY(scal_converge(h, nrhs, tol2, true));
   }
   // true residual at exit
   HIP_TRY(true_residual(h, b, x, q, nrhs, S_TRUE));

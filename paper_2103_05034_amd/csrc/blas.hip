@@ -74,10 +74,7 @@ __global__ void finalize_kernel(const double* __restrict__ partials, double* __r
 // out[rhs * ostride] = sum_k partials[rhs * count + k].  Each thread keeps
 // eight independent sums (k = tid + j*BS mod 8*BS), so eight loads are in
 // flight instead of one dependent chain; the order is fixed by count alone.
-__global__ void sum_partials_kernel(const double* __restrict__ partials, int count, double* __restrict__ out,
-                                    int ostride) {
-  const int rhs = blockIdx.x;
-  const double* p = partials + (size_t)rhs * count;
+__device__ __forceinline__ double partial_total(const double* __restrict__ p, int count) {  // valid on thread 0
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int k = threadIdx.x;
   for (; k + 7 * BS < count; k += 8 * BS) {
@@ -87,6 +84,13 @@ __global__ void sum_partials_kernel(const double* __restrict__ partials, int cou
   for (int j = 0; k < count; k += BS, ++j) acc[j] += p[k];
   double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])), b = 0;
   block_reduce2(a, b);
+  return a;
+}
+
+__global__ void sum_partials_kernel(const double* __restrict__ partials, int count, double* __restrict__ out,
+                                    int ostride) {
+  const int rhs = blockIdx.x;
+  const double a = partial_total(partials + (size_t)rhs * count, count);
   if (threadIdx.x == 0) out[(size_t)rhs * ostride] = a;
 }
 
@@ -259,10 +263,9 @@ __global__ void cg_p_kernel(VecGeom g, const char* __restrict__ r, char* __restr
 }
 
 // scalar bookkeeping: one thread per rhs
-__global__ void scal_alpha_kernel(double* scal, int nrhs) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  double* s = scal + r * NSCAL;
+// Per-rhs CG bookkeeping on the scalar slots s = scal + rhs * NSCAL.
+// alpha = |r|^2 / p.Ap (0 once the rhs has stopped; a breakdown stops it with the flag set)
+__device__ void alpha_step(double* s) {
   s[S_RR_OLD] = s[S_RR];
   if (s[S_ACTIVE] == 0.0) {
     s[S_ALPHA] = 0.0;
@@ -279,10 +282,8 @@ __global__ void scal_alpha_kernel(double* scal, int nrhs) {
   s[S_ALPHA] = a;
 }
 
-__global__ void scal_beta_kernel(double* scal, int nrhs) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  double* s = scal + r * NSCAL;
+// beta = |r_new|^2 / |r_old|^2
+__device__ void beta_step(double* s) {
   if (s[S_ACTIVE] == 0.0) {
     s[S_BETA] = 0.0;
     return;
@@ -297,15 +298,8 @@ __global__ void scal_beta_kernel(double* scal, int nrhs) {
   s[S_BETA] = b;
 }
 
-__global__ void scal_set_kernel(double* scal, int nrhs, int slot, double v) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < nrhs) scal[r * NSCAL + slot] = v;
-}
-
-__global__ void scal_converge_kernel(double* scal, int nrhs, double tol2, int count, int allow_stop) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nrhs) return;
-  double* s = scal + r * NSCAL;
+// count the iteration, flag non-finite norms, stop once |r|^2 <= tol2 |b|^2 (if allowed)
+__device__ void converge_step(double* s, double tol2, int count, int allow_stop) {
   if (s[S_ACTIVE] == 0.0) return;
   if (count) s[S_ITERS] += 1.0;
   const double rr = s[S_RR], bb = s[S_BB];
@@ -315,6 +309,45 @@ __global__ void scal_converge_kernel(double* scal, int nrhs, double tol2, int co
     return;
   }
   if (allow_stop && rr <= tol2 * bb) s[S_ACTIVE] = 0.0;
+}
+
+__global__ void scal_alpha_kernel(double* scal, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) alpha_step(scal + r * NSCAL);
+}
+
+__global__ void scal_beta_kernel(double* scal, int nrhs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) beta_step(scal + r * NSCAL);
+}
+
+// The reduction of per-workgroup partials into slot, then on the same thread the
+// CG step that needs it: mode 1 alpha (slot = S_PAP), mode 2 beta and the
+// convergence step (slot = S_RR).  One launch instead of two or three.
+__global__ void sum_partials_step_kernel(const double* __restrict__ partials, int count, double* __restrict__ scal,
+                                         int slot, int mode, double tol2) {
+  const int rhs = blockIdx.x;
+  const double a = partial_total(partials + (size_t)rhs * count, count);
+  if (threadIdx.x == 0) {
+    double* s = scal + (size_t)rhs * NSCAL;
+    s[slot] = a;
+    if (mode == 1) {
+      alpha_step(s);
+    } else {
+      beta_step(s);
+      converge_step(s, tol2, 1, 1);
+    }
+  }
+}
+
+__global__ void scal_set_kernel(double* scal, int nrhs, int slot, double v) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) scal[r * NSCAL + slot] = v;
+}
+
+__global__ void scal_converge_kernel(double* scal, int nrhs, double tol2, int count, int allow_stop) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < nrhs) converge_step(scal + r * NSCAL, tol2, count, allow_stop);
 }
 
 __global__ void scal_copy_kernel(double* scal, int nrhs, int dst, int src) {
@@ -384,6 +417,13 @@ static void dot_la(dwf_context* ctx, int pb, VecGeom g, const char* a, size_t sa
 hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot) {
   hipLaunchKernelGGL(sum_partials_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, partials, count, ctx->scalars + slot,
                      NSCAL);
+  return hipGetLastError();
+}
+
+hipError_t reduce_partials_step(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
+                                double tol2) {
+  hipLaunchKernelGGL(sum_partials_step_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, partials, count, ctx->scalars,
+                     slot, mode, tol2);
   return hipGetLastError();
 }
 

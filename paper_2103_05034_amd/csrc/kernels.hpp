@@ -57,6 +57,10 @@ enum Slot {
 
 // out[rhs * NSCAL + slot] = sum_k partials[rhs * count + k] (fixed order)
 hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot);
+// the same, then on the same thread mode 1: alpha (slot S_PAP); mode 2: beta and the
+// convergence step with tol2 (slot S_RR) -- scal_alpha / scal_beta + scal_converge fused
+hipError_t reduce_partials_step(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
+                                double tol2);
 // result[rhs] = <a, b> (complex, FP64 accumulation) into scalars[rhs*NSCAL + slot (+1 imag)]
 hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot,
                     bool imag);
