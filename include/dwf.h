@@ -60,7 +60,8 @@ enum dwf_parity { DWF_EVEN = 0, DWF_ODD = 1, DWF_BOTH = 2 };
 
 /* ---- set-up -------------------------------------------------------------- */
 
-/* Bytes of device workspace a handle needs (host only, no GPU call).  prec is
+/* Library plumbing (no passage of the paper defines this call).
+ * Bytes of device workspace a handle needs (host only, no GPU call).  prec is
  * the storage precision of the handle's fields; max_nrhs is the number of
  * right-hand sides the operator temporaries hold at once (operator and filter
  * calls with more are processed in chunks of max_nrhs); max_cg_rhs bounds the
@@ -68,12 +69,14 @@ enum dwf_parity { DWF_EVEN = 0, DWF_ODD = 1, DWF_BOTH = 2 };
  * workspace).  Returns 0 on invalid arguments. */
 size_t dwf_workspace_bytes(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs);
 
-/* Bytes of one packed half field of nrhs right-hand sides at precision prec
+/* Library plumbing (no passage of the paper defines this call).
+ * Bytes of one packed half field of nrhs right-hand sides at precision prec
  * (host only). */
 size_t dwf_field_bytes(const int dims[4], int Ls, int prec, int nrhs);
 
-/* Create a handle: validates the arguments, carves the caller's workspace
- * (device memory of at least dwf_workspace_bytes bytes, kept alive by the
+/* Create a handle for the operators of the Chiral Fermion Actions section
+ * (M5 and mf as in the D_DW matrix there): validates the arguments, carves
+ * the caller's workspace (device memory of at least dwf_workspace_bytes bytes, kept alive by the
  * caller until dwf_destroy, 256-byte aligned), packs the links U (natural
  * layout, device) into it and builds the neighbour tables, on `stream` (a
  * hipStream_t; NULL is the null stream).  M5 is the domain-wall height
@@ -83,47 +86,63 @@ int dwf_create(dwf_handle* h, const void* U, const int dims[4], int Ls, double M
                int prec, int max_nrhs, int max_cg_rhs, void* workspace, size_t ws_bytes,
                void* stream);
 
-/* Re-pack new links (same lattice), e.g. after an HMC update. */
+/* Re-pack new links (same lattice), e.g. after an HMC update of the
+ * Conclusions section's sampling. */
 int dwf_update_links(dwf_handle h, const void* U);
 
-/* Change the stream later calls are queued on. */
+/* Library plumbing (no passage of the paper defines this call).
+ * Change the stream later calls are queued on. */
 int dwf_set_stream(dwf_handle h, void* stream);
 
-/* Free the host-side handle; does not free the caller's workspace. */
+/* Library plumbing (no passage of the paper defines this call).
+ * Free the host-side handle; does not free the caller's workspace. */
 int dwf_destroy(dwf_handle h);
 
-/* Thread-local text of the last failure (never NULL). */
+/* Library plumbing (no passage of the paper defines this call).
+ * Thread-local text of the last failure (never NULL). */
 const char* dwf_last_error(void);
 
 /* Natural complex128 <-> packed (handle precision).  parity selects which
- * sites are moved; unpack writes only the sites of that parity. */
+ * sites are moved (the even / odd checkerboard of the red-black
+ * preconditioning, Conventional Krylov Solvers section); unpack writes only
+ * the sites of that parity. */
 int dwf_pack(dwf_handle h, const void* natural, void* packed, int nrhs, int parity);
 int dwf_unpack(dwf_handle h, const void* packed, void* natural, int nrhs, int parity);
 
 /* ---- operators (handle precision, packed layout) -------------------------- */
 
 /* out = D_hop in (dagger = 0) or D_hop^dag in (dagger = 1) on every slice s,
- * from the other parity into out_parity (the D_hop equation). */
+ * from the other parity into out_parity (Chiral Fermion Actions section, the
+ * D_hop equation). */
 int dwf_dhop(dwf_handle h, const void* in, void* out, int out_parity, int nrhs, int dagger);
 
-/* out = M5D in or M5D^dag in, and the exact inverses (site-local, one parity). */
+/* out = M5D in or M5D^dag in, and the exact inverses (site-local, one
+ * parity): the D_DW matrix of the Chiral Fermion Actions section without its
+ * D_hop part, i.e. the diagonal Schur blocks M_ee = M_oo. */
 int dwf_m5d(dwf_handle h, const void* in, void* out, int nrhs, int dagger);
 int dwf_m5d_inv(dwf_handle h, const void* in, void* out, int nrhs, int dagger);
 
-/* Full D_DW (or D_DW^dag) on both parities (packed "both" layout). */
+/* Full D_DW (or D_DW^dag) on both parities (packed "both" layout), the
+ * matrix of the Chiral Fermion Actions section. */
 int dwf_ddw(dwf_handle h, const void* in, void* out, int nrhs, int dagger);
 
-/* out_e = M_pc in_e (dagger = 0) or M_pc^dag in_e (dagger = 1): two passes,
+/* out_e = M_pc in_e (dagger = 0) or M_pc^dag in_e (dagger = 1), the Schur
+ * form of the Algorithms section (Algorithm G's table) used by the red-black
+ * CGNR of the Conventional Krylov Solvers section: two passes,
  * t_o = M5D^{-1} D_hop^{oe} in_e then out_e = M5D in_e - D_hop^{eo} t_o / 4. */
 int dwf_mpc(dwf_handle h, const void* in_e, void* out_e, int nrhs, int dagger);
 
-/* out_e = M_pc^dag M_pc in_e: four passes. */
+/* out_e = M_pc^dag M_pc in_e, the normal operator of the CGNR of the
+ * Spectrum of domain wall fermions section: four passes. */
 int dwf_mpcdagmpc(dwf_handle h, const void* in_e, void* out_e, int nrhs);
 
 /* ---- solver, filter, orthonormalisation ----------------------------------- */
 
 /* SYNCHRONOUS.  Solve M_pc^dag M_pc x = b for nrhs right-hand sides by CG
- * (Hestenes-Stiefel).  b and x are FP64 packed even fields whatever the
+ * (Hestenes-Stiefel): the CGNR on the normal operator of the Spectrum of
+ * domain wall fermions section, the red-black CGNR of the Conventional
+ * Krylov Solvers section; the low-precision handles give the mixed-precision
+ * variant that the Results section mentions without specifying it.  b and x are FP64 packed even fields whatever the
  * handle precision; x holds the initial guess on entry.  With a DWF_F64
  * handle every step is FP64; with DWF_F32 / DWF_F16S the iteration runs on
  * low-precision fields with FP64 dot products and FP64 reliable updates
@@ -138,7 +157,8 @@ int dwf_mpcdagmpc(dwf_handle h, const void* in_e, void* out_e, int nrhs);
 int dwf_cg(dwf_handle h, const void* b, void* x, int nrhs, double tol, int maxiter, int* iters,
            double* true_rel_resid);
 
-/* Progress of the synchronous solvers (dwf_cg, dwf_solve_rb): fn is called on
+/* Library plumbing (no passage of the paper defines this call).
+ * Progress of the synchronous solvers (dwf_cg, dwf_solve_rb): fn is called on
  * the calling thread after iteration `iteration` with the recursive
  * ||r|| / ||b|| of each of the nrhs right-hand sides (a host array valid for
  * the call only), at least `every` iterations apart (rounded up to the
@@ -151,15 +171,16 @@ typedef int (*dwf_progress_fn)(void* user, int iteration, int nrhs, const double
 int dwf_set_progress(dwf_handle h, dwf_progress_fn fn, void* user, int every);
 
 /* SYNCHRONOUS.  Red-black solve of D_DW psi = eta (FP64, packed "both"
- * layout, nrhs = 1): eta' = eta_e - M_eo M5D^{-1} eta_o, CG on
+ * layout, nrhs = 1), the prec-CGNR of the Conventional Krylov Solvers section
+ * with the Schur complement of the Two level preconditioner section: eta' = eta_e - M_eo M5D^{-1} eta_o, CG on
  * M_pc^dag M_pc psi_e = M_pc^dag eta', psi_o = M5D^{-1}(eta_o - M_oe psi_e).
  * psi's even half is the initial guess. */
 int dwf_solve_rb(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters,
                  double* true_rel_resid);
 
 /* Red-black operator used by dwf_mpc, dwf_mpcdagmpc, dwf_cg, dwf_solve_rb and
- * dwf_power (Results, Krylov table: the two Schur forms of the preconditioned
- * operator): form 1 (default) M_pc = M_ee - M_eo M_oo^{-1} M_oe; form 2
+ * dwf_power (Conventional Krylov Solvers section, the Krylov table: the two Schur
+ * forms of the preconditioned operator): form 1 (default) M_pc = M_ee - M_eo M_oo^{-1} M_oe; form 2
  * M_pc = 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe, whose red-black solve takes the
  * right-hand side M_ee^{-1} eta'.  The filters, the smoother and the force
  * are defined on form 1 and return DWF_EINVAL under form 2.  The adjoint
@@ -167,8 +188,8 @@ int dwf_solve_rb(dwf_handle h, const void* eta, void* psi, double tol, int maxit
 int dwf_set_schur_form(dwf_handle h, int form);
 
 /* SYNCHRONOUS.  Unpreconditioned solve of D_DW psi = eta by CG on
- * D_DW^dag D_DW psi = D_DW^dag eta over both parities (Results, Krylov table,
- * the CGNR row), FP64 packed "both" fields, psi holding the initial guess.
+ * D_DW^dag D_DW psi = D_DW^dag eta over both parities (Conventional Krylov
+ * Solvers section, the Krylov table's CGNR row), FP64 packed "both" fields, psi holding the initial guess.
  * Needs a DWF_F64 handle with max_cg_rhs >= 2.  iters and true_rel_resid
  * (host, may be NULL) receive the iterations and ||b - A psi|| / ||b|| of the
  * normal equations.  Returns DWF_ENOCONV after maxiter or when stopped by the
@@ -176,8 +197,9 @@ int dwf_set_schur_form(dwf_handle h, int form);
 int dwf_solve_unprec(dwf_handle h, const void* eta, void* psi, double tol, int maxiter, int* iters,
                      double* true_rel_resid);
 
-/* SYNCHRONOUS.  Power method for lambda_max of M_pc^dag M_pc from the start
- * vector v (handle precision, one rhs, overwritten with the last iterate).
+/* SYNCHRONOUS.  Power method for lambda_max of M_pc^dag M_pc (Deflation
+ * basis setup section: the upper end of the filter interval comes from the
+ * power method) from the start vector v (handle precision, one rhs, overwritten with the last iterate).
  * The handle keeps the estimate (a Rayleigh quotient, so never above the true
  * lambda_max) until its links or Schur form change; the three calls below
  * then return the warning DWF_WLAMBDA, with their results computed, when
@@ -190,7 +212,7 @@ int dwf_power(dwf_handle h, void* v, int iters, double rtol, double* lambda_max,
  * DWF_WLAMBDA if hi is below dwf_power's lambda_max (see there). */
 int dwf_chebyshev_filter(dwf_handle h, int order, double lo, double hi, void* vecs, int nvecs);
 
-/* The recursive series of the setup: v0 = T_m(x_[lam_lo, lam_max](A)) eta,
+/* The recursive series of the setup (Deflation basis setup section): v0 = T_m(x_[lam_lo, lam_max](A)) eta,
  * then out_series[k] = T_{k delta}(2 A / lam_max - 1) v0 for k = 0..nvec-1
  * (one rhs; out_series holds nvec packed fields).  eta is not modified.
  * DWF_WLAMBDA if lam_max is below dwf_power's lambda_max. */
@@ -210,7 +232,9 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
                            int nrhs);
 
 /* SYNCHRONOUS.  In place Q R = V for nvecs packed even fields (handle
- * precision) by classical Gram-Schmidt applied twice with FP64 dot products;
+ * precision), the orthonormal basis that the projector P_S of the Two level
+ * preconditioner section assumes, by classical Gram-Schmidt applied twice
+ * with FP64 dot products;
  * R (nvecs x nvecs complex128, row-major, upper triangular, positive real
  * diagonal) is written to host memory R_host if non-NULL. */
 int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
@@ -229,7 +253,8 @@ int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
  * handle's precision and need dwf_set_blocks first. */
 int dwf_set_blocks(dwf_handle h, const int block[4], int* nblocks);
 
-/* As dwf_set_blocks, with parity = DWF_EVEN (the same) or DWF_BOTH: then the
+/* Blocks of the Two level preconditioner section as dwf_set_blocks, with
+ * parity = DWF_EVEN (the same) or DWF_BOTH: then the
  * coarse-space calls below take fields of both parities in the packed
  * "both" layout (for n fields: the n even halves, then the n odd halves),
  * a block holds all bx*by*bz*bt of its sites (sites per block x Ls <= 1024),
@@ -244,13 +269,14 @@ int dwf_set_blocks_ex(dwf_handle h, const int block[4], int parity, int* nblocks
  * in: nvec fields, out: 2 nvec fields; they must not overlap. */
 int dwf_chiral_split(dwf_handle h, const void* in, void* out, int nvec);
 
-/* Device scratch (bytes) that dwf_block_orthonormalize needs for nvec
- * vectors with the current blocks; 0 if blocks are not set or nvec is
+/* Device scratch (bytes) that dwf_block_orthonormalize (Two level
+ * preconditioner section) needs for nvec vectors with the current blocks; 0 if blocks are not set or nvec is
  * outside [1, 64]. */
 size_t dwf_block_scratch_bytes(dwf_handle h, int nvec);
 
 /* SYNCHRONOUS.  In place: inside every block, orthonormalise
- * phi_0^b .. phi_{nvec-1}^b in index order (Q^b R^b = Phi^b, R^b upper
+ * phi_0^b .. phi_{nvec-1}^b in index order (the orthonormal blocked basis of
+ * the Two level preconditioner section) (Q^b R^b = Phi^b, R^b upper
  * triangular with a positive real diagonal), by two rounds of Cholesky QR
  * with FP64 Gram matrices.  scratch: caller-owned device memory of at least
  * dwf_block_scratch_bytes(h, nvec) bytes.  1 <= nvec <= 64.  Returns
@@ -264,7 +290,8 @@ int dwf_block_orthonormalize(dwf_handle h, void* basis, int nvec, void* scratch,
  * order in FP64. */
 int dwf_restrict(dwf_handle h, const void* basis, int nvec, const void* v, int nrhs, void* coarse);
 
-/* Prolongation (the prolongator |phi_k^b>): v_r = sum_{b,k} coarse[r][b][k]
+/* Prolongation (the prolongator |phi_k^b> of the Two level preconditioner
+ * section): v_r = sum_{b,k} coarse[r][b][k]
  * phi_k^b for nrhs coarse vectors laid out as dwf_restrict writes them; FP64
  * accumulation, stored in the handle's precision.  v must not alias the
  * basis. */
@@ -299,14 +326,15 @@ typedef struct {
 
 typedef struct dwf_hdcr_s* dwf_hdcr;
 
-/* Device workspace (bytes) of an HDCR solver with nvec basis vectors and
- * nkrylov outer directions under the handle's current DWF_BOTH blocks: the
+/* Device workspace (bytes) of an HDCR solver (Algorithms section, Algorithms
+ * A / B) with nvec basis vectors and nkrylov outer directions under the handle's current DWF_BOTH blocks: the
  * stencil of the little Dirac operator (nblocks x 9 x nvec^2 complex128),
  * coarse vectors, and 11 + 2 nkrylov FP64 fields of both parities.  0 if
  * blocks are not set with DWF_BOTH or an argument is out of range. */
 size_t dwf_hdcr_workspace_bytes(dwf_handle h, int nvec, int nkrylov);
 
-/* Create a solver on a DWF_F64 handle whose blocks were set with
+/* Create (and destroy) an HDCR solver of the Algorithms section
+ * (Algorithms A / B) on a DWF_F64 handle whose blocks were set with
  * dwf_set_blocks_ex(..., DWF_BOTH, ...); 1 <= nvec <= 64, 1 <= nkrylov <= 64,
  * smoother_order >= 1, 0 < smoother_lo < smoother_hi, coarse_tol > 0.  The
  * caller owns ws (>= dwf_hdcr_workspace_bytes) and keeps it, and the handle,
@@ -338,17 +366,20 @@ int dwf_hdcr_series(dwf_hdcr hd, int m, double lam_lo, double lam_max, int delta
  * the caller and must stay unchanged while the solver uses it. */
 int dwf_hdcr_set_basis(dwf_hdcr hd, const void* basis);
 
-/* Device pointer to the little Dirac operator, a 9-point stencil over the
+/* Device pointer to the little Dirac operator (Two level preconditioner
+ * section), a 9-point stencil over the
  * block grid: complex128 (complex64 with coarse_prec = DWF_F32) [nblocks][9][nvec][nvec], entry (j, k) of stencil
  * point d at (d * nvec + k) * nvec + j.  Point d < 8 couples block b to the
  * block that hop direction d leads to (d = 2 mu + 0 forward / 1 backward,
  * mu = x, y, z, t), point 8 to b itself.  NULL for a null solver. */
 const void* dwf_hdcr_coarse_data(dwf_hdcr hd);
 
-/* y = A x for one coarse vector (complex128 [nblocks][nvec], device). */
+/* y = A x for one coarse vector (complex128 [nblocks][nvec], device), A the
+ * little Dirac operator of the Two level preconditioner section. */
 int dwf_hdcr_coarse_apply(dwf_hdcr hd, const void* x, void* y);
 
-/* SYNCHRONOUS.  c = A^{-1} d by CG on A^dag A c = A^dag d from c = 0 (A is
+/* SYNCHRONOUS.  c = A^{-1} d (the coarse solve inside Q of the Two level
+ * preconditioner section) by CG on A^dag A c = A^dag d from c = 0 (A is
  * Hermitian), stopped when the normal equations' relative residual is
  * <= tol or after maxiter iterations; *iters (host, may be NULL) receives
  * the count.  d and c are coarse vectors (device); the solver's coarse
@@ -382,8 +413,10 @@ int dwf_hdcr_solve(dwf_hdcr hd, const void* eta, void* psi, double tol, int maxi
 
 /* ---- HMC force ------------------------------------------------------------ */
 
-/* Link gradient of S = phi^dag (M_pc^dag M_pc)^{-1} phi given X = A^{-1} phi
- * and Y = M_pc X (FP64 packed even fields, one rhs):
+/* Link gradient of S = phi^dag (M_pc^dag M_pc)^{-1} phi, the pseudofermion
+ * estimate of the two-flavour determinant det(M^dag M) whose HMC evolution
+ * the Conclusions section motivates, given X = A^{-1} phi and Y = M_pc X
+ * (FP64 packed even fields, one rhs):
  *   G_mu(x) = -sum_s sum_spin [ a(x,s) ((1-g_mu) b(x+mu,s))^dag + ((1+g_mu) b(x,s)) a(x+mu,s)^dag ],
  * a = (Y even, M5D^{-dag} M_eo^dag Y odd), b = (X even, M5D^{-1} M_oe X odd),
  * written as grad_U in the natural link layout (complex128), with the
@@ -392,14 +425,16 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U);
 
 /* ---- introspection -------------------------------------------------------- */
 
-/* Launch shape of the hopping kernels: 4D sites per workgroup (0 = default,
+/* Library plumbing (no passage of the paper defines this call).
+ * Launch shape of the hopping kernels: 4D sites per workgroup (0 = default,
  * sites_per_block * Ls <= 256), the depth (1..3; 0 keeps the current one)
  * of the neighbour-load pipeline, i.e. how many directions' spinor loads a
  * wave keeps in flight, and the right-hand sides one workgroup loops over
  * with its links staged once in LDS (1..64; 0 keeps the current one). */
 int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_per_block);
 
-/* SYNCHRONOUS.  Traversal order of the half-lattice sites in the hop kernels:
+/* Library plumbing (no passage of the paper defines this call).
+ * SYNCHRONOUS.  Traversal order of the half-lattice sites in the hop kernels:
  * 0 = lexicographic (x fastest, t slowest); 1 = the (x,y,z) box split into
  * 2x2x2 sub-boxes, one per XCD, each streamed with t slowest (needs X, Y, Z
  * divisible by 4); 2 = eight slabs of consecutive t, one per XCD, each
@@ -407,12 +442,14 @@ int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_
  * do not depend on the order. */
 int dwf_set_order(dwf_handle h, int mode);
 
-/* Cap the resident hop workgroups per compute unit (0 = no cap) by reserving
+/* Library plumbing (no passage of the paper defines this call).
+ * Cap the resident hop workgroups per compute unit (0 = no cap) by reserving
  * LDS: fewer sites in flight per XCD keep the stencil's neighbour reuse
  * window inside that XCD's L2.  Results do not depend on it. */
 int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu);
 
-/* SYNCHRONOUS.  Times M_pc^dag M_pc on nrhs right-hand sides (<= max_nrhs)
+/* Library plumbing (no passage of the paper defines this call).
+ * SYNCHRONOUS.  Times M_pc^dag M_pc on nrhs right-hand sides (<= max_nrhs)
  * for each candidate launch shape -- workgroups of 256, 128 and 64 lanes,
  * load-pipeline depth 1..3, 1/2/4/8 rhs per workgroup (<= nrhs) -- over
  * `reps` applications each, keeps the fastest in the handle and reports it
@@ -420,7 +457,8 @@ int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu);
 int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb,
                  double* best_ms);
 
-/* Average duration (ms) of the hopping-term kernels since the last reset, as
+/* Library plumbing (no passage of the paper defines this call).
+ * Average duration (ms) of the hopping-term kernels since the last reset, as
  * measured by HIP events on the handle's stream when timing is enabled. */
 int dwf_enable_timing(dwf_handle h, int enable);
 int dwf_kernel_time(dwf_handle h, double* ms_total, long long* launches);

@@ -122,3 +122,77 @@ def test_two_level_calls_on_null_handles_fail_cleanly(lib):
         assert "null HDCR handle" in dwf.last_error()
     assert lib.dwf_hdcr_coarse_data(None) is None
     assert lib.dwf_hdcr_destroy(None) == dwf.DWF_OK
+
+
+# Section titles of the paper (as printed, or shortened where the header uses
+# the short form): every declaration's comment names the passage it follows.
+SECTIONS = (
+    "Chiral Fermion Actions",
+    "Spectrum of domain wall fermions",
+    "Two level preconditioner",
+    "Chebyshev smoothers",
+    "Composite V(1,1)",
+    "Deflation basis setup",
+    "Algorithms section",
+    "Algorithms A / B",
+    "Conventional Krylov Solvers",
+    "Results section",
+    "Setup costs",
+    "Conclusions",
+)
+PLUMBING = "Library plumbing (no passage of the paper defines this call)"
+
+
+def declaration_comments():
+    """{function name: the comment block right above its declaration}; consecutive
+    declarations under one comment share it."""
+    text = open(HEADER).read()
+    out = {}
+    last = None
+    pos = 0
+    for m in re.finditer(r"/\*.*?\*/|\b(?:int|size_t|const\s+\w+\s*\*|const\s+char\s*\*)\s+(dwf_[a-z0-9_]+)\s*\(", text,
+                         flags=re.S):
+        if m.group(0).startswith("/*"):
+            # the comment serves the declarations that follow it
+            last = m.group(0)
+            pos = m.end()
+            continue
+        between = text[pos:m.start()]
+        if last is not None and between.strip() and not re.fullmatch(r"(?:\s*[^;{}]*\);\s*)*", between, flags=re.S):
+            last = None
+        out[m.group(1)] = last
+        pos = m.end()
+    return out
+
+
+def _flat(comment):
+    """The comment's text on one line, without the comment markers and line stars."""
+    body = comment[2:-2]
+    return " ".join(" ".join(line.strip().lstrip("*").split()) for line in body.splitlines()).strip()
+
+
+def test_every_declaration_cites_its_passage_or_says_it_is_plumbing():
+    comments = declaration_comments()
+    names = header_functions()
+    assert sorted(comments) == names
+    for name in names:
+        c = comments[name]
+        assert c is not None, f"{name} has no comment"
+        flat = _flat(c)
+        assert PLUMBING in flat or any(s in flat for s in SECTIONS), f"{name} cites no section"
+
+
+def test_method_calls_cite_a_section():
+    """The calls that compute a step of the method cite the paper, not just plumbing."""
+    comments = declaration_comments()
+    method = [
+        "dwf_create", "dwf_dhop", "dwf_m5d", "dwf_m5d_inv", "dwf_ddw", "dwf_mpc", "dwf_mpcdagmpc", "dwf_cg",
+        "dwf_solve_rb", "dwf_power", "dwf_chebyshev_filter", "dwf_chebyshev_series", "dwf_chebyshev_smoother",
+        "dwf_gram_schmidt", "dwf_force", "dwf_pack", "dwf_unpack", "dwf_set_schur_form", "dwf_solve_unprec",
+        "dwf_set_blocks", "dwf_chiral_split", "dwf_block_orthonormalize", "dwf_restrict", "dwf_prolong", "dwf_hdw",
+        "dwf_hdcr_filter", "dwf_hdcr_series", "dwf_hdcr_set_basis", "dwf_hdcr_coarse_solve", "dwf_hdcr_smoother",
+        "dwf_hdcr_vcycle", "dwf_hdcr_solve",
+    ]
+    for name in method:
+        flat = _flat(comments[name])
+        assert any(s in flat for s in SECTIONS), f"{name} cites no section"
