@@ -239,6 +239,18 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
  * diagonal) is written to host memory R_host if non-NULL. */
 int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
 
+/* <a_r, b_r> = sum over the 5D sites, spins and colours of conj(a_r) b_r for
+ * nrhs packed one-parity fields of precision prec (either parity; each
+ * operand is nrhs consecutive fields): the inner products of the CG of the
+ * Spectrum of domain wall fermions section, and the pseudofermion action
+ * S = phi^dag X of the Conclusions section's HMC.  Accumulated in FP64 and
+ * reduced in a fixed order, so repeated calls are bitwise identical.
+ * result: device array of 2 nrhs doubles (re, im per rhs), written
+ * asynchronously on the handle's stream.  The reduction goes through the
+ * handle's workspace, so calls on one handle must stay ordered on its
+ * stream. */
+int dwf_dot(dwf_handle h, int prec, const void* a, const void* b, int nrhs, double* result);
+
 /* ---- coarse-space transfer ------------------------------------------------ */
 
 /* Blocks of the two-level method (Two level preconditioner section: the

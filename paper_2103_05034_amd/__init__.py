@@ -92,6 +92,7 @@ _PROTOS = {
     "dwf_chebyshev_series": (_i, [_vp, _i, _d, _d, _i, _i, _vp, _vp]),
     "dwf_chebyshev_smoother": (_i, [_vp, _i, _d, _d, _vp, _vp, _i]),
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
+    "dwf_dot": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_set_schur_form": (_i, [_vp, _i]),
     "dwf_solve_unprec": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p]),
@@ -186,6 +187,29 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr() if hasattr(t, "data_ptr") else int(t))
 
 
+def _tensor_ptr(t, device, what, nbytes=None, dtype=None, shape=None):
+    """Device pointer of tensor t after checking what the C call will assume of it:
+    a torch tensor on the operator's device, contiguous, of the given dtype and
+    shape, and holding at least nbytes bytes.  Raises DWFError(DWF_EINVAL) otherwise,
+    before anything reaches the library (a kernel would read or write past a short
+    buffer)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise DWFError(DWF_EINVAL, f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.device != device:
+        raise DWFError(DWF_EINVAL, f"{what}: tensor on {t.device}, the operator's device is {device}")
+    if not t.is_contiguous():
+        raise DWFError(DWF_EINVAL, f"{what}: tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise DWFError(DWF_EINVAL, f"{what}: dtype {t.dtype}, expected {dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise DWFError(DWF_EINVAL, f"{what}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if nbytes is not None and t.numel() * t.element_size() < nbytes:
+        raise DWFError(DWF_EINVAL, f"{what}: {t.numel() * t.element_size()} bytes, at least {nbytes} needed")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _stream():
     import torch
 
@@ -199,6 +223,10 @@ class Operator:
     (X, Y, Z, T).  ``prec`` selects the storage precision of the handle's
     packed fields; ``max_nrhs`` the batch held by the operator temporaries;
     ``max_cg_rhs`` the number of simultaneous CG right-hand sides.
+
+    Every method checks its tensors (device, contiguity, dtype and shape of
+    natural fields and links, byte size of packed fields) before calling the
+    library, and raises :class:`DWFError` if one does not fit.
     """
 
     def __init__(self, U, dims, Ls, M5, mf, prec=DWF_F64, max_nrhs=1, max_cg_rhs=1):
@@ -209,24 +237,27 @@ class Operator:
         self.dims = tuple(int(d) for d in dims)
         self.Ls, self.M5, self.mf, self.prec = int(Ls), float(M5), float(mf), int(prec)
         self.max_nrhs, self.max_cg_rhs = int(max_nrhs), int(max_cg_rhs)
+        if not isinstance(U, torch.Tensor) or not U.is_cuda:
+            raise DWFError(DWF_EINVAL, "U must be a complex128 tensor on a HIP device")
         self.device = U.device
+        X, Y, Z, T = self.dims
+        self.V4 = X * Y * Z * T
+        self.V4h = self.V4 // 2
+        self.U = U.contiguous()
+        u_ptr = self._links(self.U)
         nbytes = lib.dwf_workspace_bytes(_dims(self.dims), self.Ls, self.prec, self.max_nrhs, self.max_cg_rhs)
         if nbytes == 0:
             raise DWFError(DWF_EINVAL, last_error())
         # 256-byte alignment: torch's caching allocator returns >= 512-byte aligned blocks
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=U.device)
-        self.U = U.contiguous()
         h = ctypes.c_void_p()
         _check(
             lib.dwf_create(
-                ctypes.byref(h), _ptr(self.U), _dims(self.dims), self.Ls, self.M5, self.mf, self.prec,
+                ctypes.byref(h), u_ptr, _dims(self.dims), self.Ls, self.M5, self.mf, self.prec,
                 self.max_nrhs, self.max_cg_rhs, _ptr(self.workspace), nbytes, _stream(),
             )
         )
         self.h = h
-        X, Y, Z, T = self.dims
-        self.V4 = X * Y * Z * T
-        self.V4h = self.V4 // 2
 
     # -- memory helpers -------------------------------------------------------
     def field_bytes(self, nrhs=1, prec=None):
@@ -243,75 +274,134 @@ class Operator:
         X, Y, Z, T = self.dims
         return (nrhs, self.Ls, T, Z, Y, X, 4, 3)
 
+    def link_shape(self):
+        X, Y, Z, T = self.dims
+        return (T, Z, Y, X, 4, 3, 3)
+
     def _sync_stream(self):
         self.lib.dwf_set_stream(self.h, _stream())
 
+    # -- argument checks (no library call) -------------------------------------
+    def _f(self, t, nrhs=1, prec=None, both=False, what="field"):
+        """Pointer of a packed field of nrhs right-hand sides (both parities if both)."""
+        if int(nrhs) < 1:
+            raise DWFError(DWF_EINVAL, f"{what}: nrhs must be >= 1")
+        need = self.field_bytes(nrhs, prec) * (2 if both else 1)
+        return _tensor_ptr(t, self.device, what, nbytes=need)
+
+    def _natural(self, t, nrhs, what="natural field"):
+        import torch
+
+        return _tensor_ptr(t, self.device, what, dtype=torch.complex128, shape=self.natural_shape(nrhs))
+
+    def _links(self, t, what="U"):
+        import torch
+
+        return _tensor_ptr(t, self.device, what, dtype=torch.complex128, shape=self.link_shape())
+
+    def _coarse(self, t, shape, what="coarse vector"):
+        import torch
+
+        return _tensor_ptr(t, self.device, what, dtype=torch.complex128, shape=shape)
+
     # -- ABI calls ------------------------------------------------------------
     def update_links(self, U):
-        self.U = U.contiguous()
-        _check(self.lib.dwf_update_links(self.h, _ptr(self.U)))
+        U = U.contiguous() if hasattr(U, "contiguous") else U
+        ptr = self._links(U)
+        self.U = U
+        self._sync_stream()
+        _check(self.lib.dwf_update_links(self.h, ptr))
 
     def pack(self, natural, parity, out=None):
+        if getattr(natural, "dim", lambda: 0)() != 8:
+            raise DWFError(DWF_EINVAL, "natural field must be [nrhs][Ls][T][Z][Y][X][4][3]")
         nrhs = natural.shape[0]
+        natural = natural.contiguous()
+        src = self._natural(natural, nrhs)
         if out is None:
             out = self.new_field(nrhs, both=(parity == DWF_BOTH))
+        dst = self._f(out, nrhs, both=(parity == DWF_BOTH), what="packed output")
         self._sync_stream()
-        _check(self.lib.dwf_pack(self.h, _ptr(natural.contiguous()), _ptr(out), nrhs, parity))
+        _check(self.lib.dwf_pack(self.h, src, dst, nrhs, parity))
         return out
 
     def unpack(self, packed, nrhs, parity, out=None):
         import torch
 
+        src = self._f(packed, nrhs, both=(parity == DWF_BOTH), what="packed input")
         if out is None:
             out = torch.zeros(self.natural_shape(nrhs), dtype=torch.complex128, device=self.device)
+        dst = self._natural(out, nrhs, what="natural output")
         self._sync_stream()
-        _check(self.lib.dwf_unpack(self.h, _ptr(packed), _ptr(out), nrhs, parity))
+        _check(self.lib.dwf_unpack(self.h, src, dst, nrhs, parity))
         return out
 
     def dhop(self, inp, out, out_parity, nrhs=1, dagger=False):
+        a, b = self._f(inp, nrhs, what="in"), self._f(out, nrhs, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_dhop(self.h, _ptr(inp), _ptr(out), out_parity, nrhs, int(dagger)))
+        _check(self.lib.dwf_dhop(self.h, a, b, out_parity, nrhs, int(dagger)))
         return out
 
     def m5d(self, inp, out, nrhs=1, dagger=False):
+        a, b = self._f(inp, nrhs, what="in"), self._f(out, nrhs, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_m5d(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        _check(self.lib.dwf_m5d(self.h, a, b, nrhs, int(dagger)))
         return out
 
     def m5d_inv(self, inp, out, nrhs=1, dagger=False):
+        a, b = self._f(inp, nrhs, what="in"), self._f(out, nrhs, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_m5d_inv(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        _check(self.lib.dwf_m5d_inv(self.h, a, b, nrhs, int(dagger)))
         return out
 
     def ddw(self, inp, out, nrhs=1, dagger=False):
+        a, b = self._f(inp, nrhs, both=True, what="in"), self._f(out, nrhs, both=True, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_ddw(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        _check(self.lib.dwf_ddw(self.h, a, b, nrhs, int(dagger)))
         return out
 
     def mpc(self, inp, out, nrhs=1, dagger=False):
+        a, b = self._f(inp, nrhs, what="in"), self._f(out, nrhs, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_mpc(self.h, _ptr(inp), _ptr(out), nrhs, int(dagger)))
+        _check(self.lib.dwf_mpc(self.h, a, b, nrhs, int(dagger)))
         return out
 
     def mpcdagmpc(self, inp, out, nrhs=1):
+        a, b = self._f(inp, nrhs, what="in"), self._f(out, nrhs, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_mpcdagmpc(self.h, _ptr(inp), _ptr(out), nrhs))
+        _check(self.lib.dwf_mpcdagmpc(self.h, a, b, nrhs))
         return out
+
+    def dot(self, a, b, nrhs=1, prec=None, out=None):
+        """<a_r, b_r> for nrhs packed one-parity fields (FP64 sums in the library):
+        a complex128 device tensor [nrhs] viewing ``out`` (float64 [nrhs, 2])."""
+        import torch
+
+        p = self.prec if prec is None else int(prec)
+        pa, pb = self._f(a, nrhs, p, what="a"), self._f(b, nrhs, p, what="b")
+        if out is None:
+            out = torch.empty((nrhs, 2), dtype=torch.float64, device=self.device)
+        po = _tensor_ptr(out, self.device, "out", dtype=torch.float64, shape=(nrhs, 2))
+        self._sync_stream()
+        _check(self.lib.dwf_dot(self.h, p, pa, pb, nrhs, po))
+        return torch.view_as_complex(out)
 
     def cg(self, b, x, nrhs=1, tol=1e-10, maxiter=10000, allow_noconv=False):
         """Synchronous CG on M_pc^dag M_pc (b, x FP64 packed); returns (status, iters, true_rel_resid)."""
+        pb, px = self._f(b, nrhs, DWF_F64, what="b"), self._f(x, nrhs, DWF_F64, what="x")
         it = (ctypes.c_int * nrhs)()
         res = (ctypes.c_double * nrhs)()
         self._sync_stream()
-        code = self.lib.dwf_cg(self.h, _ptr(b), _ptr(x), nrhs, tol, maxiter, it, res)
+        code = self.lib.dwf_cg(self.h, pb, px, nrhs, tol, maxiter, it, res)
         _check(code, allow=(DWF_ENOCONV,) if allow_noconv else ())
         return code, list(it), list(res)
 
     def solve_rb(self, eta, psi, tol=1e-10, maxiter=10000):
+        pe, pp = self._f(eta, 1, DWF_F64, both=True, what="eta"), self._f(psi, 1, DWF_F64, both=True, what="psi")
         it = ctypes.c_int()
         res = ctypes.c_double()
         self._sync_stream()
-        code = self.lib.dwf_solve_rb(self.h, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
+        code = self.lib.dwf_solve_rb(self.h, pe, pp, tol, maxiter, ctypes.byref(it), ctypes.byref(res))
         _check(code)
         return it.value, res.value
 
@@ -321,18 +411,20 @@ class Operator:
 
     def solve_unprec(self, eta, psi, tol=1e-10, maxiter=100000):
         """CGNR on D_DW^dag D_DW over both parities; returns (iterations, true residual)."""
+        pe, pp = self._f(eta, 1, DWF_F64, both=True, what="eta"), self._f(psi, 1, DWF_F64, both=True, what="psi")
         it = ctypes.c_int()
         res = ctypes.c_double()
         self._sync_stream()
-        code = self.lib.dwf_solve_unprec(self.h, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res))
+        code = self.lib.dwf_solve_unprec(self.h, pe, pp, tol, maxiter, ctypes.byref(it), ctypes.byref(res))
         _check(code)
         return it.value, res.value
 
     def power(self, v, iters=100, rtol=1e-6):
+        pv = self._f(v, 1, what="v")
         lam = ctypes.c_double()
         done = ctypes.c_int()
         self._sync_stream()
-        _check(self.lib.dwf_power(self.h, _ptr(v), iters, rtol, ctypes.byref(lam), ctypes.byref(done)))
+        _check(self.lib.dwf_power(self.h, pv, iters, rtol, ctypes.byref(lam), ctypes.byref(done)))
         return lam.value, done.value
 
     @staticmethod
@@ -344,27 +436,30 @@ class Operator:
             warnings.warn(last_error(), RuntimeWarning, stacklevel=3)
 
     def chebyshev_filter(self, vecs, nvecs, order, lo, hi):
+        pv = self._f(vecs, nvecs, what="vecs")
         self._sync_stream()
-        self._warn_lambda(self.lib.dwf_chebyshev_filter(self.h, order, lo, hi, _ptr(vecs), nvecs))
+        self._warn_lambda(self.lib.dwf_chebyshev_filter(self.h, order, lo, hi, pv, nvecs))
         return vecs
 
     def chebyshev_series(self, eta, out_series, m, lam_lo, lam_max, delta, nvec):
+        pe, po = self._f(eta, 1, what="eta"), self._f(out_series, nvec, what="out_series")
         self._sync_stream()
-        self._warn_lambda(
-            self.lib.dwf_chebyshev_series(self.h, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out_series)))
+        self._warn_lambda(self.lib.dwf_chebyshev_series(self.h, m, lam_lo, lam_max, delta, nvec, pe, po))
         return out_series
 
     def chebyshev_smoother(self, inp, out, order, lo, hi, nrhs=1):
+        a, b = self._f(inp, nrhs, what="in"), self._f(out, nrhs, what="out")
         self._sync_stream()
-        self._warn_lambda(self.lib.dwf_chebyshev_smoother(self.h, order, lo, hi, _ptr(inp), _ptr(out), nrhs))
+        self._warn_lambda(self.lib.dwf_chebyshev_smoother(self.h, order, lo, hi, a, b, nrhs))
         return out
 
     def gram_schmidt(self, vecs, nvecs):
         import numpy as np
 
+        pv = self._f(vecs, nvecs, what="vecs")
         R = (ctypes.c_double * (2 * nvecs * nvecs))()
         self._sync_stream()
-        _check(self.lib.dwf_gram_schmidt(self.h, _ptr(vecs), nvecs, R))
+        _check(self.lib.dwf_gram_schmidt(self.h, pv, nvecs, R))
         r = np.frombuffer(R, dtype=np.float64).reshape(nvecs, nvecs, 2)
         return r[..., 0] + 1j * r[..., 1]
 
@@ -379,56 +474,73 @@ class Operator:
         self.coarse_both = bool(both)
         return nb.value
 
+    def _cf(self, t, n, what):
+        """A field of the coarse-space calls: n fields, both parities if the blocks cover both."""
+        return self._f(t, n, both=getattr(self, "coarse_both", False), what=what)
+
     def hdw(self, inp, out, nrhs=1):
         """out = H_DW inp = Gamma_5 D_DW inp (packed fields of both parities)."""
+        a, b = self._f(inp, nrhs, both=True, what="in"), self._f(out, nrhs, both=True, what="out")
         self._sync_stream()
-        _check(self.lib.dwf_hdw(self.h, _ptr(inp), _ptr(out), nrhs))
+        _check(self.lib.dwf_hdw(self.h, a, b, nrhs))
 
     def chiral_split(self, vecs, nvec, out=None):
         """out[2k], out[2k+1] = (1 +- Gamma_5) vecs[k] / 2."""
         if out is None:
             out = self.new_field(2 * nvec, both=getattr(self, "coarse_both", False))
+        a, b = self._cf(vecs, nvec, "vecs"), self._cf(out, 2 * nvec, "out")
         self._sync_stream()
-        _check(self.lib.dwf_chiral_split(self.h, _ptr(vecs), _ptr(out), nvec))
+        _check(self.lib.dwf_chiral_split(self.h, a, b, nvec))
         return out
 
     def block_orthonormalize(self, basis, nvec):
         import torch
 
+        pb = self._cf(basis, nvec, "basis")
         nbytes = self.lib.dwf_block_scratch_bytes(self.h, nvec)
         if nbytes == 0:
             raise DWFError(DWF_EINVAL, "set blocks first; nvec must be in [1, 64]")
         scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._sync_stream()
-        _check(self.lib.dwf_block_orthonormalize(self.h, _ptr(basis), nvec, _ptr(scratch), nbytes))
+        _check(self.lib.dwf_block_orthonormalize(self.h, pb, nvec, _ptr(scratch), nbytes))
         return basis
 
     def restrict(self, basis, nvec, v, nrhs=1, coarse=None):
         """coarse[r][b][k] = <phi_k^b, v_r> (complex128 device tensor [nrhs, nblocks, nvec])."""
         import torch
 
+        if not hasattr(self, "nblocks"):
+            raise DWFError(DWF_EINVAL, "set blocks first")
+        pb, pv = self._cf(basis, nvec, "basis"), self._cf(v, nrhs, "v")
         if coarse is None:
             coarse = torch.empty((nrhs, self.nblocks, nvec), dtype=torch.complex128, device=self.device)
+        pc = self._coarse(coarse, (nrhs, self.nblocks, nvec), "coarse")
         self._sync_stream()
-        _check(self.lib.dwf_restrict(self.h, _ptr(basis), nvec, _ptr(v), nrhs, _ptr(coarse)))
+        _check(self.lib.dwf_restrict(self.h, pb, nvec, pv, nrhs, pc))
         return coarse
 
     def prolong(self, basis, nvec, coarse, nrhs=1, out=None):
         """out_r = sum_{b,k} coarse[r][b][k] phi_k^b."""
+        if not hasattr(self, "nblocks"):
+            raise DWFError(DWF_EINVAL, "set blocks first")
         if out is None:
             out = self.new_field(nrhs, both=getattr(self, "coarse_both", False))
+        coarse = coarse.contiguous()
+        pb, po = self._cf(basis, nvec, "basis"), self._cf(out, nrhs, "out")
+        pc = self._coarse(coarse, (nrhs, self.nblocks, nvec), "coarse")
         self._sync_stream()
-        _check(self.lib.dwf_prolong(self.h, _ptr(basis), nvec, _ptr(coarse.contiguous()), nrhs, _ptr(out)))
+        _check(self.lib.dwf_prolong(self.h, pb, nvec, pc, nrhs, po))
         return out
 
     def force(self, X_e, Y_e, grad=None):
         import torch
 
+        px, py = self._f(X_e, 1, DWF_F64, what="X"), self._f(Y_e, 1, DWF_F64, what="Y")
         if grad is None:
-            X, Y, Z, T = self.dims
-            grad = torch.zeros((T, Z, Y, X, 4, 3, 3), dtype=torch.complex128, device=self.device)
+            grad = torch.zeros(self.link_shape(), dtype=torch.complex128, device=self.device)
+        pg = self._links(grad, what="grad")
         self._sync_stream()
-        _check(self.lib.dwf_force(self.h, _ptr(X_e), _ptr(Y_e), _ptr(grad)))
+        _check(self.lib.dwf_force(self.h, px, py, pg))
         return grad
 
     def set_tile(self, sites_per_block, pipeline_depth=0, rhs_per_block=0):
@@ -517,25 +629,34 @@ class HDCR:
 
         return torch.zeros((self.op.nblocks, self.nvec), dtype=torch.complex128, device=self.op.device)
 
+    def _cv(self, t, what):
+        return self.op._coarse(t, (self.op.nblocks, self.nvec), what)
+
+    def _both(self, t, n, what):
+        return self.op._f(t, n, DWF_F64, both=True, what=what)
+
     def filter(self, vecs, nvecs, order, lo, hi):
         """vecs <- T_order(x(D^dag D)) vecs for nvecs fields of both parities."""
+        pv = self._both(vecs, nvecs, "vecs")
         self.op._sync_stream()
-        _check(self.lib.dwf_hdcr_filter(self.hd, order, lo, hi, _ptr(vecs), nvecs))
+        _check(self.lib.dwf_hdcr_filter(self.hd, order, lo, hi, pv, nvecs))
 
     def series(self, eta, m, lam_lo, lam_max, delta, nvec, out=None):
         """The setup series from one field eta: out[0] = T_m(x_[lam_lo, lam_max](D^dag D)) eta,
         out[k] = T_{k delta}(2 D^dag D / lam_max - 1) out[0] (nvec fields of both parities)."""
         if out is None:
             out = self.op.new_field(nvec, both=True)
+        pe, po = self._both(eta, 1, "eta"), self._both(out, nvec, "out")
         self.op._sync_stream()
-        _check(self.lib.dwf_hdcr_series(self.hd, m, lam_lo, lam_max, delta, nvec, _ptr(eta), _ptr(out)))
+        _check(self.lib.dwf_hdcr_series(self.hd, m, lam_lo, lam_max, delta, nvec, pe, po))
         return out
 
     def set_basis(self, basis):
         """Build the little Dirac operator of H_DW on ``basis`` (kept referenced)."""
+        pb = self._both(basis, self.nvec, "basis")
         self.op._sync_stream()
         self.basis = basis
-        _check(self.lib.dwf_hdcr_set_basis(self.hd, _ptr(basis)))
+        _check(self.lib.dwf_hdcr_set_basis(self.hd, pb))
 
     def coarse_operator(self):
         """The stencil as a complex128 (complex64 with coarse_prec=DWF_F32) tensor
@@ -551,40 +672,45 @@ class HDCR:
     def coarse_apply(self, x, y=None):
         if y is None:
             y = self.coarse_vector()
+        px, py = self._cv(x, "x"), self._cv(y, "y")
         self.op._sync_stream()
-        _check(self.lib.dwf_hdcr_coarse_apply(self.hd, _ptr(x), _ptr(y)))
+        _check(self.lib.dwf_hdcr_coarse_apply(self.hd, px, py))
         return y
 
     def coarse_solve(self, d, c=None, tol=1e-10, maxiter=10000):
         if c is None:
             c = self.coarse_vector()
+        pd, pc = self._cv(d, "d"), self._cv(c, "c")
         it = ctypes.c_int()
         self.op._sync_stream()
-        _check(self.lib.dwf_hdcr_coarse_solve(self.hd, _ptr(d), _ptr(c), tol, maxiter, ctypes.byref(it)))
+        _check(self.lib.dwf_hdcr_coarse_solve(self.hd, pd, pc, tol, maxiter, ctypes.byref(it)))
         return c, it.value
 
     def smoother(self, r, out=None):
         if out is None:
             out = self.op.new_field(1, both=True)
+        pr, po = self._both(r, 1, "r"), self._both(out, 1, "out")
         self.op._sync_stream()
-        _check(self.lib.dwf_hdcr_smoother(self.hd, _ptr(r), _ptr(out)))
+        _check(self.lib.dwf_hdcr_smoother(self.hd, pr, po))
         return out
 
     def vcycle(self, r, x=None):
         if x is None:
             x = self.op.new_field(1, both=True)
+        pr, px = self._both(r, 1, "r"), self._both(x, 1, "x")
         ci = ctypes.c_int()
         self.op._sync_stream()
-        _check(self.lib.dwf_hdcr_vcycle(self.hd, _ptr(r), _ptr(x), ctypes.byref(ci)))
+        _check(self.lib.dwf_hdcr_vcycle(self.hd, pr, px, ctypes.byref(ci)))
         return x, ci.value
 
     def solve(self, eta, psi, tol=1e-10, maxiter=1000, allow_noconv=False):
         """D_DW psi = eta; returns (outer iterations, true relative residual, coarse iterations)."""
+        pe, pp = self._both(eta, 1, "eta"), self._both(psi, 1, "psi")
         it, ci = ctypes.c_int(), ctypes.c_int()
         res = ctypes.c_double()
         self.op._sync_stream()
         _check(
-            self.lib.dwf_hdcr_solve(self.hd, _ptr(eta), _ptr(psi), tol, maxiter, ctypes.byref(it), ctypes.byref(res),
+            self.lib.dwf_hdcr_solve(self.hd, pe, pp, tol, maxiter, ctypes.byref(it), ctypes.byref(res),
                                     ctypes.byref(ci)),
             allow=(DWF_ENOCONV,) if allow_noconv else (),
         )
@@ -600,3 +726,12 @@ class HDCR:
             self.close()
         except Exception:
             pass
+
+
+def __getattr__(name):
+    """PseudofermionAction lives in the autograd module, which imports torch."""
+    if name == "PseudofermionAction":
+        from .autograd import PseudofermionAction
+
+        return PseudofermionAction
+    raise AttributeError(name)

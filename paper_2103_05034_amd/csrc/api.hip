@@ -878,6 +878,21 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
   return warn_lambda(h, hi, "dwf_chebyshev_smoother");
 }
 
+int dwf_dot(dwf_handle h, int prec, const void* a, const void* b, int nrhs, double* result) {
+  if (int r = check_h(h)) return r;
+  if (!a || !b || !result) return fail(DWF_EINVAL, "dwf_dot: null pointer");
+  if (prec != DWF_F64 && prec != DWF_F32 && prec != DWF_F16S) return fail(DWF_EINVAL, "dwf_dot: unknown precision");
+  if (nrhs < 1 || nrhs > 65535) return fail(DWF_EINVAL, "dwf_dot: nrhs %d out of range", nrhs);
+  const size_t fb = fbytes(h, prec);
+  const int chunk = (int)h->partial_count;  // rhs whose partial sums the handle's scratch holds at once
+  for (int r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int n = std::min(chunk, nrhs - r0);
+    HIP_TRY(blas_dot_to(h, prec, reinterpret_cast<const char*>(a) + r0 * fb, reinterpret_cast<const char*>(b) + r0 * fb,
+                        n, h->partials, result + 2 * (size_t)r0));
+  }
+  return DWF_OK;
+}
+
 int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host) {
   if (int r = check_h(h)) return r;
   if (!vecs || nvecs < 1 || nvecs > GS_MAX) return fail(DWF_EINVAL, "dwf_gram_schmidt: nvecs must be in [1, %d]", GS_MAX);

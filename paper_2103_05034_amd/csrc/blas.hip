@@ -400,17 +400,19 @@ __global__ void scale_kernel(VecGeom g, char* __restrict__ v, const double* __re
 static unsigned grid_n(long long n) { return (unsigned)((n + BS - 1) / BS); }
 
 template <int PA, int PB>
-static void dot_l(dwf_context* ctx, VecGeom g, const char* a, size_t sa, const char* b, size_t sb, int nrhs) {
+static void dot_l(dwf_context* ctx, VecGeom g, const char* a, size_t sa, const char* b, size_t sb, int nrhs,
+                  double* partials) {
   hipLaunchKernelGGL((dot_kernel<PA, PB>), dim3(RED_BLOCKS, nrhs), dim3(BS), 0, ctx->stream, g, a, sa, b, sb,
-                     ctx->partials);
+                     partials);
 }
 template <int PA>
 static void dot_la(dwf_context* ctx, int pb, VecGeom g, const char* a, size_t sa, const char* b, size_t sb,
-                   int nrhs) {
+                   int nrhs, double* partials = nullptr) {
+  if (!partials) partials = ctx->partials;
   switch (pb) {
-    case DWF_F64: dot_l<PA, DWF_F64>(ctx, g, a, sa, b, sb, nrhs); break;
-    case DWF_F32: dot_l<PA, DWF_F32>(ctx, g, a, sa, b, sb, nrhs); break;
-    default: dot_l<PA, DWF_F16S>(ctx, g, a, sa, b, sb, nrhs); break;
+    case DWF_F64: dot_l<PA, DWF_F64>(ctx, g, a, sa, b, sb, nrhs, partials); break;
+    case DWF_F32: dot_l<PA, DWF_F32>(ctx, g, a, sa, b, sb, nrhs, partials); break;
+    default: dot_l<PA, DWF_F16S>(ctx, g, a, sa, b, sb, nrhs, partials); break;
   }
 }
 
@@ -433,6 +435,15 @@ hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char*
   DWF_DISPATCH1(pa, dot_la, ctx, pb, g, a, sa, b, sb, nrhs);
   hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, ctx->partials, ctx->scalars + slot,
                      NSCAL, imag ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t blas_dot_to(dwf_context* ctx, int prec, const char* a, const char* b, int nrhs, double* partials,
+                       double* result) {
+  VecGeom g = vgeom(ctx);
+  const size_t st = field_bytes_rhs(ctx, prec);
+  DWF_DISPATCH1(prec, dot_la, ctx, prec, g, a, st, b, st, nrhs, partials);
+  hipLaunchKernelGGL(finalize_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, partials, result, 2, 1);
   return hipGetLastError();
 }
 

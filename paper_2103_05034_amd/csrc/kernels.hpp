@@ -64,6 +64,10 @@ hipError_t reduce_partials_step(dwf_context* ctx, const double* partials, int co
 // result[rhs] = <a, b> (complex, FP64 accumulation) into scalars[rhs*NSCAL + slot (+1 imag)]
 hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot,
                     bool imag);
+// result[2 r], result[2 r + 1] = <a_r, b_r> (re, im) for nrhs fields of one precision, reduced
+// through `partials` (RED_BLOCKS * 2 doubles per rhs) in the fixed order of blas_dot
+hipError_t blas_dot_to(dwf_context* ctx, int prec, const char* a, const char* b, int nrhs, double* partials,
+                       double* result);
 // y <- alpha x + beta y with per-rhs or constant coefficients; any storage mix
 //  coef_mode 0: constants; 1: alpha = scalars[slot_a], beta = cb (device coefficients)
 hipError_t blas_axpby(dwf_context* ctx, int px, const char* x, int py, char* y, int nrhs, double ca,
