@@ -342,8 +342,14 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   hipError_t e = launch_pack_links(c, U);
   if (e == hipSuccess) e = launch_neighbours(c);
   if (e == hipSuccess) e = hipMemsetAsync(c->scalars, 0, (size_t)(c->partial_count * NSCAL) * sizeof(double), c->stream);
+  if (e == hipSuccess && max_cg_rhs > 0 && prec != DWF_F64) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&c->pin_scal), (size_t)2 * max_cg_rhs * NSCAL * sizeof(double),
+                      hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->pin_ev[0], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->pin_ev[1], hipEventDisableTiming);
+  }
   if (e != hipSuccess) {
-    delete c;
+    dwf_destroy(c);
     return fail(DWF_EHIP, "set-up launch failed: %s", hipGetErrorString(e));
   }
   *out = c;
@@ -366,6 +372,11 @@ int dwf_set_stream(dwf_handle h, void* stream) {
 
 int dwf_destroy(dwf_handle h) {
   if (!h) return DWF_OK;
+  if (h->pin_scal) {
+    (void)hipHostFree(h->pin_scal);
+    (void)hipEventDestroy(h->pin_ev[0]);
+    (void)hipEventDestroy(h->pin_ev[1]);
+  }
   for (auto& p : h->ev_pool) {
     (void)hipEventDestroy(p.a);
     (void)hipEventDestroy(p.b);
@@ -557,7 +568,170 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
   return finish_cg(h, nrhs, maxiter, iters, resid, sc, tr, stopped);
 }
 
-// Low-precision CG with FP64 reliable updates.
+// Low-precision CG with FP64 reliable updates on the first Schur form.  The
+// search direction p is stored at the handle's precision (FP32, or FP16 +
+// scale); the operator's intermediate fields t (odd) and u = M_pc p (even) and
+// the iterated residual are FP32, so the operator is applied in FP32 to
+// exactly the stored p; the solution accumulates in FP64 (an FP32 running sum
+// of alpha p loses the low modes' small corrections and costs iterations at
+// light mass).  One iteration is four hop launches: t = M5D^{-1} D_hop p;
+// u = M5D p - D_hop t / 4 with p.Ap = |u|^2 reduced into alpha;
+// t = M5D^{-dag} D_hop^dag u; r -= alpha (M5D^dag u - D_hop^dag t / 4) with
+// |r|^2 reduced into beta; then x += alpha p and p = r + beta p in one pass.
+// After each iteration the scalars are copied to pinned host memory, and the
+// host reads them one iteration later, while the next iteration runs.  A rhs
+// whose iterated |r| fell tenfold below its largest value since the last
+// reliable update, or below the tolerance, triggers a reliable update of all
+// rhs: r = b - A x in FP64, p += r - r_lo (which makes p the direction
+// r + beta p_old that the new residual implies), r_lo = r, and p loses p_old's
+// component along the new r (r^dag p = |r|^2, as CG's recursion assumes).  A
+// rhs retires only on its FP64 true residual.
+static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double tol, int maxiter, int* iters,
+                          double* resid) {
+  const int P = h->prec;
+  const double tol2 = tol * tol;
+  const double delta2 = 0.01;
+  char* r64 = h->r64;
+  char* t32 = h->t64;  // FP32 views of the FP64 temporaries, which are free between reliable updates
+  char* u32 = h->u64;
+  if (!h->pin_scal) return fail(DWF_EINVAL, "dwf_cg: handle has no pinned scalar buffer");
+  HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
+  HIP_TRY(blas_dot(h, DWF_F64, b, DWF_F64, b, nrhs, S_BB, false));
+  HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
+  HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
+  HIP_TRY(blas_copy(h, DWF_F64, r64, DWF_F32, h->lo_r, nrhs));
+  HIP_TRY(blas_copy(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+  HIP_TRY(scal_set(h, nrhs, S_ACTIVE, 1.0));
+  HIP_TRY(scal_set(h, nrhs, S_FLAG, 0.0));
+  HIP_TRY(scal_set(h, nrhs, S_ITERS, 0.0));
+  HIP_TRY(scal_converge(h, nrhs, tol2, false));
+  std::vector<double> sc;
+  if (int rc = read_scalars(h, nrhs, sc)) return rc;
+  // Stagnation: a rhs whose true |r| has not halved over `patience`
+  // consecutive update cycles (updates asked for by a tenfold fall of the
+  // iterated |r|) is stagnant; the solve stops once every active rhs is.
+  const int patience = 12;
+  std::vector<double> best(nrhs);
+  for (int rr = 0; rr < nrhs; ++rr) best[rr] = sc[(size_t)rr * NSCAL + S_RR];
+  std::vector<int> idle(nrhs, 0);
+  std::vector<char> cycle(nrhs, 0);
+  const int nb = hop_blocks(h);
+  const size_t slot_doubles = (size_t)nrhs * NSCAL;
+  bool stagnant = false, stopped = false;
+  int it = 0, last = 0;
+  auto any_active = [&](const double* snap) {
+    for (int rr = 0; rr < nrhs; ++rr)
+      if (snap[(size_t)rr * NSCAL + S_ACTIVE] != 0.0) return true;
+    return false;
+  };
+  // pinned slot holding the scalars after the latest queued iteration that the
+  // host has not read yet (-1: none)
+  int prev_slot = -1;
+  while (any_active(sc.data())) {
+    int new_slot = -1;
+    if (it < maxiter) {  // queue one iteration and the copy of its scalars
+      HopArgs a{};
+      a.in = h->lo_p;
+      a.out = t32;
+      a.alpha = 1.0;
+      HIP_TRY(launch_hop_ex(h, DWF_F32, P, DWF_F32, a, DWF_ODD, 0, EPI_M5INV, nrhs));
+      HopArgs m{};
+      m.in = t32;
+      m.x = h->lo_p;
+      m.out = u32;
+      m.alpha = -0.25;
+      m.partial = h->hop_partials;
+      HIP_TRY(launch_hop_ex(h, DWF_F32, DWF_F32, P, m, DWF_EVEN, 0, EPI_M5, nrhs));
+      HIP_TRY(reduce_partials_step(h, h->hop_partials, nb, nrhs, S_PAP, 1, tol2));  // p.Ap, alpha
+      HopArgs c{};
+      c.in = u32;
+      c.out = t32;
+      c.alpha = 1.0;
+      HIP_TRY(launch_hop(h, DWF_F32, c, DWF_ODD, 1, EPI_M5INV, nrhs));
+      HopArgs d{};
+      d.in = t32;
+      d.x = u32;
+      d.out = h->lo_r;
+      d.alpha = -0.25;
+      d.partial = h->hop_partials;
+      d.scal = h->scalars;
+      HIP_TRY(launch_hop(h, DWF_F32, d, DWF_EVEN, 1, EPI_CGR, nrhs));
+      HIP_TRY(reduce_partials_step(h, h->hop_partials, nb, nrhs, S_RR, 3, tol2));  // |r|^2, beta, max |r|^2
+      HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+      new_slot = prev_slot == 0 ? 1 : 0;
+      HIP_TRY(hipMemcpyAsync(h->pin_scal + new_slot * slot_doubles, h->scalars, slot_doubles * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
+      HIP_TRY(hipEventRecord(h->pin_ev[new_slot], h->stream));
+      ++it;
+    }
+    if (prev_slot < 0) {  // nothing to read yet (first iteration, or right after an update)
+      if (new_slot < 0) break;
+      prev_slot = new_slot;
+      continue;
+    }
+    // the scalars after the iteration before the one just queued (after the last one
+    // when nothing was queued), read while the queued iteration runs
+    HIP_TRY(hipEventSynchronize(h->pin_ev[prev_slot]));
+    const double* snap = h->pin_scal + prev_slot * slot_doubles;
+    if (!any_active(snap)) break;  // every rhs stopped on a breakdown
+    bool update = new_slot < 0;    // out of iterations: finish with an update
+    for (int rr = 0; rr < nrhs; ++rr) {
+      const double* s = snap + (size_t)rr * NSCAL;
+      cycle[rr] = 0;
+      if (s[S_ACTIVE] == 0.0) continue;
+      cycle[rr] = s[S_RR] < delta2 * s[S_RRMAX];
+      if (cycle[rr] || s[S_RR] < tol2 * s[S_BB] || !std::isfinite(s[S_RR])) update = true;
+    }
+    if (update) {
+      // after the iteration(s) already queued: the FP64 residual of the FP64 solution
+      HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
+      HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
+      HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
+      HIP_TRY(cg_reliable_p(h, r64, h->lo_r, P, h->lo_p, nrhs));
+      HIP_TRY(blas_dot(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs, S_TMP, true));
+      HIP_TRY(cg_orth_p(h, h->lo_r, P, h->lo_p, nrhs));
+      HIP_TRY(scal_converge(h, nrhs, tol2, false, 1));  // retire on the true residual
+      if (int rc = read_scalars(h, nrhs, sc)) return rc;
+      prev_slot = -1;  // a snapshot queued before the update is stale
+      if (new_slot < 0) break;
+      bool all_stuck = true;
+      for (int rr = 0; rr < nrhs; ++rr) {
+        const double* s = &sc[(size_t)rr * NSCAL];
+        if (s[S_ACTIVE] == 0.0) continue;
+        if (s[S_RR] < 0.25 * best[rr]) {
+          best[rr] = s[S_RR];
+          idle[rr] = 0;
+        } else if (cycle[rr]) {
+          ++idle[rr];
+        }
+        if (idle[rr] < patience) all_stuck = false;
+      }
+      if (any_active(sc.data()) && all_stuck) {
+        stagnant = true;
+        break;
+      }
+      continue;
+    }
+    if (report_progress(h, it - 1, nrhs, std::vector<double>(snap, snap + slot_doubles), last)) {
+      stopped = true;
+      break;
+    }
+    prev_slot = new_slot;
+  }
+  HIP_TRY(true_residual(h, b, x, r64, nrhs, S_TRUE));
+  if (int rc = read_scalars(h, nrhs, sc)) return rc;
+  std::vector<double> tr(nrhs);
+  for (int rr = 0; rr < nrhs; ++rr) tr[rr] = sc[(size_t)rr * NSCAL + S_TRUE];
+  const int rc = finish_cg(h, nrhs, maxiter, iters, resid, sc, tr, stopped);
+  if (rc == DWF_ENOCONV && stagnant)
+    return fail(DWF_ENOCONV,
+                "mixed-precision CG stagnated: the true residual stopped falling (the low-precision operator is "
+                "too coarse for this conditioning; use a higher handle precision)");
+  return rc;
+}
+
+// Low-precision CG with FP64 reliable updates on the second Schur form
+// (operator applied at the handle's precision throughout).
 static int cg_mixed(dwf_handle h, const char* b, char* x, int nrhs, double tol, int maxiter, int* iters,
                     double* resid) {
   const int P = h->prec;
@@ -673,6 +847,9 @@ int dwf_cg(dwf_handle h, const void* b, void* x, int nrhs, double tol, int maxit
   if (h->prec == DWF_F64)
     return cg_f64(h, reinterpret_cast<const char*>(b), reinterpret_cast<char*>(x), nrhs, tol, maxiter, iters,
                   true_rel_resid);
+  if (h->schur_form == 1)
+    return cg_mixed_fused(h, reinterpret_cast<const char*>(b), reinterpret_cast<char*>(x), nrhs, tol, maxiter, iters,
+                          true_rel_resid);
   return cg_mixed(h, reinterpret_cast<const char*>(b), reinterpret_cast<char*>(x), nrhs, tol, maxiter, iters,
                   true_rel_resid);
 }

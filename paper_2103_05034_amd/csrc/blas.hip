@@ -38,21 +38,10 @@ __device__ __forceinline__ void vstore(char* base, const VecGeom& g, long long i
   Store<P>::store(base, g.V4h, g.Ls, h, (int)(i - h * g.Ls), t);
 }
 
-// fixed-shape tree reduction of 2 doubles over a workgroup of BS threads
+// fixed-order sums of 2 doubles over a workgroup of BS threads, valid on thread 0
 __device__ __forceinline__ void block_reduce2(double& a, double& b) {
-  __shared__ double sa[BS], sb[BS];
-  sa[threadIdx.x] = a;
-  sb[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = BS / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  a = sa[0];
-  b = sb[0];
+  __shared__ double red[2 * (BS / 64)];
+  block_sum2(a, b, red);
 }
 
 // partials[(rhs * RED_BLOCKS + blk) * 2 + {0,1}] -> out[rhs * ostride + {0, 1}]
@@ -262,6 +251,46 @@ __global__ void cg_p_kernel(VecGeom g, const char* __restrict__ r, char* __restr
   vstore<PP>(p + rhs * sp, g, i, vr);
 }
 
+// p += r_true - r_iter ; r_iter = r_true.  After a reliable update replaced the
+// iterated residual by the true one, this turns p = r_iter + beta p_old into
+// r_true + beta p_old without keeping p_old.
+template <int PP>
+__global__ void cg_reliable_kernel(VecGeom g, const char* __restrict__ rt, char* __restrict__ ri, char* __restrict__ p,
+                                   size_t st, size_t si, size_t sp) {
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  cplx<double> vt[12], vi[12], vp[12];
+  vload<DWF_F64>(rt + rhs * st, g, i, vt);
+  vload<DWF_F32>(ri + rhs * si, g, i, vi);
+  vload<PP>(p + rhs * sp, g, i, vp);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) vp[c] = {vp[c].re + (vt[c].re - vi[c].re), vp[c].im + (vt[c].im - vi[c].im)};
+  vstore<PP>(p + rhs * sp, g, i, vp);
+  vstore<DWF_F32>(ri + rhs * si, g, i, vt);
+}
+
+// p <- p - (c - 1) r with c = r^dag p / |r|^2 taken from scal[S_TMP], scal[S_TMPI] and
+// scal[S_RR]: after a reliable update p = r + beta p_old, this removes p_old's
+// component along the new r (r^dag p = |r|^2 afterwards, as in exact CG).
+template <int PP>
+__global__ void cg_orth_kernel(VecGeom g, const char* __restrict__ r, char* __restrict__ p, size_t sr, size_t sp,
+                               const double* __restrict__ scal) {
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double* s = scal + rhs * NSCAL;
+  if (!(s[S_RR] > 0.0) || s[S_ACTIVE] == 0.0) return;
+  const cplx<double> f = {s[S_TMP] / s[S_RR] - 1.0, s[S_TMPI] / s[S_RR]};
+  cplx<double> vr[12], vp[12];
+  vload<DWF_F32>(r + rhs * sr, g, i, vr);
+  vload<PP>(p + rhs * sp, g, i, vp);
+#pragma unroll
+  for (int c = 0; c < 12; ++c)
+    vp[c] = {vp[c].re - (f.re * vr[c].re - f.im * vr[c].im), vp[c].im - (f.re * vr[c].im + f.im * vr[c].re)};
+  vstore<PP>(p + rhs * sp, g, i, vp);
+}
+
 // scalar bookkeeping: one thread per rhs
 // Per-rhs CG bookkeeping on the scalar slots s = scal + rhs * NSCAL.
 // alpha = |r|^2 / p.Ap (0 once the rhs has stopped; a breakdown stops it with the flag set)
@@ -335,7 +364,8 @@ __global__ void sum_partials_step_kernel(const double* __restrict__ partials, in
       alpha_step(s);
     } else {
       beta_step(s);
-      converge_step(s, tol2, 1, 1);
+      converge_step(s, tol2, 1, mode == 2);
+      if (mode == 3 && s[S_ACTIVE] != 0.0) s[S_RRMAX] = fmax(s[S_RRMAX], s[S_RR]);
     }
   }
 }
@@ -557,6 +587,37 @@ hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r
     xp_l<DWF_F32, DWF_F32, DWF_F32>(ctx, g, x, r, p, nrhs);
   else if (px == DWF_F32 && pr == DWF_F32 && pp == DWF_F16S)
     xp_l<DWF_F32, DWF_F32, DWF_F16S>(ctx, g, x, r, p, nrhs);
+  else if (px == DWF_F64 && pr == DWF_F32 && pp == DWF_F32)
+    xp_l<DWF_F64, DWF_F32, DWF_F32>(ctx, g, x, r, p, nrhs);
+  else if (px == DWF_F64 && pr == DWF_F32 && pp == DWF_F16S)
+    xp_l<DWF_F64, DWF_F32, DWF_F16S>(ctx, g, x, r, p, nrhs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t cg_reliable_p(dwf_context* ctx, const char* r_true, char* r_iter, int pp, char* p, int nrhs) {
+  VecGeom g = vgeom(ctx);
+  const dim3 grid(grid_n(g.n), nrhs);
+  const size_t st = field_bytes_rhs(ctx, DWF_F64), si = field_bytes_rhs(ctx, DWF_F32), sp = field_bytes_rhs(ctx, pp);
+  if (pp == DWF_F32)
+    hipLaunchKernelGGL((cg_reliable_kernel<DWF_F32>), grid, dim3(BS), 0, ctx->stream, g, r_true, r_iter, p, st, si, sp);
+  else if (pp == DWF_F16S)
+    hipLaunchKernelGGL((cg_reliable_kernel<DWF_F16S>), grid, dim3(BS), 0, ctx->stream, g, r_true, r_iter, p, st, si,
+                       sp);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t cg_orth_p(dwf_context* ctx, const char* r, int pp, char* p, int nrhs) {
+  VecGeom g = vgeom(ctx);
+  const dim3 grid(grid_n(g.n), nrhs);
+  const size_t sr = field_bytes_rhs(ctx, DWF_F32), sp = field_bytes_rhs(ctx, pp);
+  if (pp == DWF_F32)
+    hipLaunchKernelGGL((cg_orth_kernel<DWF_F32>), grid, dim3(BS), 0, ctx->stream, g, r, p, sr, sp, ctx->scalars);
+  else if (pp == DWF_F16S)
+    hipLaunchKernelGGL((cg_orth_kernel<DWF_F16S>), grid, dim3(BS), 0, ctx->stream, g, r, p, sr, sp, ctx->scalars);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -56,6 +56,54 @@ template <class R>
 __device__ __forceinline__ cplx<R> ctimesi(cplx<R> a) { return {-a.im, a.re}; }
 
 // ---------------------------------------------------------------------------
+// Deterministic workgroup sums built on wavefront shuffles.  A wave folds its
+// 64 lanes in a fixed butterfly (the last wave of a workgroup may hold fewer
+// lanes; only those that exist are added), then thread 0 adds the waves' sums
+// in wave order.  The order depends only on blockDim, so results are bitwise
+// reproducible.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_lanes_present() {
+  const int first = (int)(threadIdx.x & ~63u);
+  const int n = (int)blockDim.x - first;
+  return n < 64 ? n : 64;
+}
+
+// sum of v over the calling wave's lanes, valid in its lane 0
+__device__ __forceinline__ double wave_sum(double v) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int present = wave_lanes_present();
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off, 64);
+    if (lane + off < present) v += o;
+  }
+  return v;
+}
+
+// sums of a and b over the workgroup, valid on thread 0; red holds 2 * (blockDim / 64) doubles
+// (LDS).  Contains one barrier, which every thread of the workgroup must reach.
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = (int)(threadIdx.x >> 6);
+  const int nw = (int)((blockDim.x + 63) >> 6);
+  if ((threadIdx.x & 63u) == 0) {
+    red[w] = a;
+    red[nw + w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = red[0], tb = red[nw];
+    for (int k = 1; k < nw; ++k) {
+      ta += red[k];
+      tb += red[nw + k];
+    }
+    a = ta;
+    b = tb;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Field storage.  A packed half field of one right-hand side holds the 12
 // spin-colour components (c = 3 spin + colour) of every (site h, slice s),
 // grouped so that one lane moves 16 bytes per load:
@@ -283,7 +331,7 @@ enum Epilogue {
   EPI_M5INV = 1,  // out = M5D^{-1} [alpha * Dhop(in) + beta * x]  (x optional)
   EPI_M5 = 2,     // out = M5D x + alpha * Dhop(in)
   EPI_CHEB = 3,   // out = ca * (M5D x + alpha * Dhop(in)) + cb * y + cc * z (+ cw * w)
-  EPI_CGR = 4,    // q = M5D x + alpha * Dhop(in) kept in registers; out -= alpha_cg * q  (CG residual, FP64)
+  EPI_CGR = 4,    // q = M5D x + alpha * Dhop(in) kept in registers; out -= alpha_cg * q  (CG residual, FP64/FP32)
 };
 
 struct HopArgs {
@@ -295,7 +343,9 @@ struct HopArgs {
   const char* w;      // EPI_CHEB optional fourth term (may alias out)
   const void* links;  // packed links of out parity: [dir][9][V4h] complex
   const int* nbr;     // neighbour table of out parity: [dir][V4h]
-  size_t stride;      // bytes per rhs of every field argument
+  size_t stride;      // bytes per rhs of out, y, z and w
+  size_t in_stride;   // bytes per rhs of in
+  size_t x_stride;    // bytes per rhs of x
   long long V4h;
   int Ls;
   int spb;            // sites per workgroup
@@ -374,6 +424,10 @@ struct dwf_context {
   dwf_progress_fn progress_fn;
   void* progress_user;
   int progress_every;
+  // low-precision CG: pinned host copies of the scalars (two slots of max_cg_rhs * 16 doubles)
+  // and an event per slot, so the host reads an iteration's scalars while the next one runs
+  double* pin_scal;
+  hipEvent_t pin_ev[2];
   // timing of hopping kernels
   bool timing;
   std::vector<dwf::EventPair> ev_pool;

@@ -240,21 +240,11 @@ __global__ void __launch_bounds__(64) coarse_matvec_kernel(const T* __restrict__
   y[(size_t)b * n + j] = make_double2(re, im);
 }
 
-// Fixed-order sum over the workgroup (tree in LDS).
+// Fixed-order sums over the workgroup (wavefront shuffles, then the waves in
+// order), valid on thread 0.
 __device__ __forceinline__ void tree2(double& a, double& b) {
-  __shared__ double ra[CB], rb[CB];
-  ra[threadIdx.x] = a;
-  rb[threadIdx.x] = b;
-  __syncthreads();
-  for (int o = CB / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      ra[threadIdx.x] += ra[threadIdx.x + o];
-      rb[threadIdx.x] += rb[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
-  a = ra[0];
-  b = rb[0];
+  __shared__ double red[2 * (CB / 64)];
+  block_sum2(a, b, red);
 }
 
 // part[blk] (re) and part[CRED + blk] (im) of sum conj(x) y over n complex values

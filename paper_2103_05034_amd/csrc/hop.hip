@@ -171,15 +171,11 @@ __device__ __forceinline__ void m5inv_columns(cplx<R>* buf, int spb, int Ls, lon
   }
 }
 
-// sum over the workgroup of v (FP64), written by thread 0; scratch holds blockDim doubles
+// sum over the workgroup of v (FP64), valid on thread 0; scratch holds 8 doubles
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
-  scratch[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w && (int)threadIdx.x + w < (int)blockDim.x) scratch[threadIdx.x] += scratch[threadIdx.x + w];
-    __syncthreads();
-  }
-  return scratch[0];
+  double unused = 0;
+  block_sum2(v, unused, scratch);
+  return v;
 }
 
 // MULTI: the workgroup loops over rpb right-hand sides (links staged once);
@@ -195,10 +191,17 @@ struct HopOccupancy {
   static constexpr int waves = (PREC == DWF_F64 || MULTI) ? 1 : 3;
 };
 
-template <int PREC, bool DAG, int EPI, int DEPTH, bool MULTI>
+// PREC is the storage of the output (and of y, z, w), PIN that of the
+// neighbour input and PX that of the site-local operand x; all three share the
+// arithmetic type.  The mixed forms (FP16 + scale in, FP32 out, or FP16 + scale
+// x) let the low-precision CG keep its search direction in FP16 + scale while
+// the operator's intermediate fields stay FP32.
+template <int PREC, int PIN, int PX, bool DAG, int EPI, int DEPTH, bool MULTI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HopOccupancy<PREC, MULTI>::waves)))
 hop_kernel(HopArgs a) {
   using R = typename Store<PREC>::real;
+  static_assert(sizeof(typename Store<PIN>::real) == sizeof(R) && sizeof(typename Store<PX>::real) == sizeof(R),
+                "one arithmetic type per launch");
   using V = typename LinkT<R>::vec;
   extern __shared__ char smem_raw[];
   const int Ls = a.Ls;
@@ -267,14 +270,15 @@ hop_kernel(HopArgs a) {
     const int rhs = blockIdx.y * nrr + rr;
     if (rhs >= a.nrhs) break;  // uniform across the workgroup
     const size_t off = (size_t)rhs * a.stride;
-    const char* in = a.in + off;
+    const char* in = a.in + (size_t)rhs * a.in_stride;
+    const char* xb = a.x ? a.x + (size_t)rhs * a.x_stride : nullptr;
     cplx<R> buf[DEPTH][12];
-    if (valid) hop_prologue<PREC, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
+    if (valid) hop_prologue<PIN, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
     __syncthreads();  // links staged (first rhs); scratch free (later rhs)
     cplx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-    if (valid) hop_pipeline<PREC, DAG, 0, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+    if (valid) hop_pipeline<PIN, DAG, 0, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
 
     char* out = a.out + off;
     cplx<R> v[12];
@@ -282,9 +286,9 @@ hop_kernel(HopArgs a) {
 #pragma unroll
       for (int c = 0; c < 12; ++c) v[c] = cscale(alpha, acc[c]);
       const bool x_after = EPI == EPI_M5INV && a.x_after;
-      if (a.x != nullptr && valid && !x_after) {
+      if (xb != nullptr && valid && !x_after) {
         cplx<R> xv[12];
-        Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
+        Store<PX>::load(xb, V4h, Ls, h, s, xv);
         const R beta = (R)a.beta;
 #pragma unroll
         for (int c = 0; c < 12; ++c) v[c] = {v[c].re + beta * xv[c].re, v[c].im + beta * xv[c].im};
@@ -302,9 +306,9 @@ hop_kernel(HopArgs a) {
         if (valid) {
 #pragma unroll
           for (int c = 0; c < 12; ++c) v[c] = col[(size_t)(sl * 12 + c) * LP + s];
-          if (x_after && a.x != nullptr) {  // second Schur form: x + M5D^{-1}(alpha Dhop in)
+          if (x_after && xb != nullptr) {  // second Schur form: x + M5D^{-1}(alpha Dhop in)
             cplx<R> xv[12];
-            Store<PREC>::load(a.x + off, V4h, Ls, h, s, xv);
+            Store<PX>::load(xb, V4h, Ls, h, s, xv);
             const R beta = (R)a.beta;
 #pragma unroll
             for (int c = 0; c < 12; ++c) v[c] = {v[c].re + beta * xv[c].re, v[c].im + beta * xv[c].im};
@@ -319,7 +323,7 @@ hop_kernel(HopArgs a) {
       const int nl = spb * Ls;
       cplx<R> xs[12];
       if (valid) {
-        Store<PREC>::load_nt(a.x + off, V4h, Ls, h, s, xs);
+        Store<PX>::load_nt(xb, V4h, Ls, h, s, xs);
 #pragma unroll
         for (int c = 0; c < 12; ++c) xl[c * nl + tid] = xs[c];
       }
@@ -488,46 +492,62 @@ void fill_shape(const dwf_context* ctx, HopArgs& a) {
   a.corner = -ctx->mf / (1.0 + ctx->mf * std::pow(d, -(double)Ls));
 }
 
-template <int PREC, bool DAG, int EPI, int DEPTH>
+template <int PREC, int PIN, int PX, bool DAG, int EPI, int DEPTH>
 static hipError_t launch_hop_t(const HopArgs& a, int nrhs, hipStream_t st) {
   dim3 grid(a.nb8 * 8, (nrhs + a.rpb - 1) / a.rpb);
   dim3 block(a.spb * a.Ls);
   const size_t lds = std::max(hop_lds(PREC, a.spb, a.Ls, EPI, a.partial != nullptr), (size_t)a.lds_floor);
   if (a.rpb > 1)
-    hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH, true>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((hop_kernel<PREC, PIN, PX, DAG, EPI, DEPTH, true>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((hop_kernel<PREC, DAG, EPI, DEPTH, false>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((hop_kernel<PREC, PIN, PX, DAG, EPI, DEPTH, false>), grid, block, lds, st, a);
   return hipGetLastError();
 }
 
-template <int PREC, bool DAG, int EPI>
+template <int PREC, int PIN, int PX, bool DAG, int EPI>
 static hipError_t launch_hop_d(const HopArgs& a, int depth, int nrhs, hipStream_t st) {
   switch (depth) {
-    case 1: return launch_hop_t<PREC, DAG, EPI, 1>(a, nrhs, st);
-    case 3: return launch_hop_t<PREC, DAG, EPI, 3>(a, nrhs, st);
-    default: return launch_hop_t<PREC, DAG, EPI, 2>(a, nrhs, st);
+    case 1: return launch_hop_t<PREC, PIN, PX, DAG, EPI, 1>(a, nrhs, st);
+    case 3: return launch_hop_t<PREC, PIN, PX, DAG, EPI, 3>(a, nrhs, st);
+    default: return launch_hop_t<PREC, PIN, PX, DAG, EPI, 2>(a, nrhs, st);
   }
 }
 
 template <int PREC>
 static hipError_t launch_hop_p(const HopArgs& a, int dag, int epi, int depth, int nrhs, hipStream_t st) {
   switch (epi * 2 + (dag ? 1 : 0)) {
-    case EPI_LIN * 2 + 0: return launch_hop_d<PREC, false, EPI_LIN>(a, depth, nrhs, st);
-    case EPI_LIN * 2 + 1: return launch_hop_d<PREC, true, EPI_LIN>(a, depth, nrhs, st);
-    case EPI_M5INV * 2 + 0: return launch_hop_d<PREC, false, EPI_M5INV>(a, depth, nrhs, st);
-    case EPI_M5INV * 2 + 1: return launch_hop_d<PREC, true, EPI_M5INV>(a, depth, nrhs, st);
-    case EPI_M5 * 2 + 0: return launch_hop_d<PREC, false, EPI_M5>(a, depth, nrhs, st);
-    case EPI_M5 * 2 + 1: return launch_hop_d<PREC, true, EPI_M5>(a, depth, nrhs, st);
-    case EPI_CHEB * 2 + 0: return launch_hop_d<PREC, false, EPI_CHEB>(a, depth, nrhs, st);
-    case EPI_CHEB * 2 + 1: return launch_hop_d<PREC, true, EPI_CHEB>(a, depth, nrhs, st);
+    case EPI_LIN * 2 + 0: return launch_hop_d<PREC, PREC, PREC, false, EPI_LIN>(a, depth, nrhs, st);
+    case EPI_LIN * 2 + 1: return launch_hop_d<PREC, PREC, PREC, true, EPI_LIN>(a, depth, nrhs, st);
+    case EPI_M5INV * 2 + 0: return launch_hop_d<PREC, PREC, PREC, false, EPI_M5INV>(a, depth, nrhs, st);
+    case EPI_M5INV * 2 + 1: return launch_hop_d<PREC, PREC, PREC, true, EPI_M5INV>(a, depth, nrhs, st);
+    case EPI_M5 * 2 + 0: return launch_hop_d<PREC, PREC, PREC, false, EPI_M5>(a, depth, nrhs, st);
+    case EPI_M5 * 2 + 1: return launch_hop_d<PREC, PREC, PREC, true, EPI_M5>(a, depth, nrhs, st);
+    case EPI_CHEB * 2 + 0: return launch_hop_d<PREC, PREC, PREC, false, EPI_CHEB>(a, depth, nrhs, st);
+    case EPI_CHEB * 2 + 1: return launch_hop_d<PREC, PREC, PREC, true, EPI_CHEB>(a, depth, nrhs, st);
     case EPI_CGR * 2 + 1:
-      if constexpr (PREC == DWF_F64) return launch_hop_d<PREC, true, EPI_CGR>(a, depth, nrhs, st);
+      if constexpr (PREC != DWF_F16S) return launch_hop_d<PREC, PREC, PREC, true, EPI_CGR>(a, depth, nrhs, st);
       break;
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int dag, int epi, int nrhs) {
+// The two mixed-storage forms: FP16 + scale neighbour input with FP32 output
+// (t = M5D^{-1} D_hop p, no x), and FP32 neighbour input with an FP16 + scale
+// site-local operand (u = M5D p - D_hop t / 4).
+static hipError_t launch_hop_mixed(const HopArgs& a, int pin, int px, int dag, int epi, int depth, int nrhs,
+                                   hipStream_t st) {
+  if (pin == DWF_F16S && epi == EPI_M5INV && a.x == nullptr)
+    return dag ? launch_hop_d<DWF_F32, DWF_F16S, DWF_F32, true, EPI_M5INV>(a, depth, nrhs, st)
+               : launch_hop_d<DWF_F32, DWF_F16S, DWF_F32, false, EPI_M5INV>(a, depth, nrhs, st);
+  if (pin == DWF_F32 && px == DWF_F16S && epi == EPI_M5)
+    return dag ? launch_hop_d<DWF_F32, DWF_F32, DWF_F16S, true, EPI_M5>(a, depth, nrhs, st)
+               : launch_hop_d<DWF_F32, DWF_F32, DWF_F16S, false, EPI_M5>(a, depth, nrhs, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_hop_ex(dwf_context* ctx, int prec, int pin, int px, HopArgs a, int out_parity, int dag, int epi,
+                         int nrhs) {
+  if (prec != DWF_F64 && ctx->links32 == nullptr) return hipErrorInvalidValue;  // FP64 handles hold no FP32 links
   fill_shape(ctx, a);
   const long long V4h = ctx->g.V4h;
   a.nbr = ctx->nbr + (size_t)out_parity * 8 * V4h;
@@ -537,20 +557,30 @@ hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int
   else
     a.links = reinterpret_cast<const float2*>(ctx->links32) + link_elems;
   a.stride = field_bytes_rhs(ctx, prec);
+  a.in_stride = field_bytes_rhs(ctx, pin);
+  a.x_stride = field_bytes_rhs(ctx, px);
   a.order = ctx->order_mode ? ctx->order + (size_t)out_parity * V4h : nullptr;
   a.lds_floor = ctx->lds_floor;
   a.nrhs = nrhs;
   a.rpb = std::max(1, std::min(ctx->rpb, nrhs));
-  const int depth = ctx->depth[prec];
+  const int depth = ctx->depth[pin];
   timing_begin(ctx);
   hipError_t e;
-  switch (prec) {
-    case DWF_F64: e = launch_hop_p<DWF_F64>(a, dag, epi, depth, nrhs, ctx->stream); break;
-    case DWF_F32: e = launch_hop_p<DWF_F32>(a, dag, epi, depth, nrhs, ctx->stream); break;
-    default: e = launch_hop_p<DWF_F16S>(a, dag, epi, depth, nrhs, ctx->stream); break;
+  if (pin != prec || px != prec) {
+    e = (prec == DWF_F32) ? launch_hop_mixed(a, pin, px, dag, epi, depth, nrhs, ctx->stream) : hipErrorInvalidValue;
+  } else {
+    switch (prec) {
+      case DWF_F64: e = launch_hop_p<DWF_F64>(a, dag, epi, depth, nrhs, ctx->stream); break;
+      case DWF_F32: e = launch_hop_p<DWF_F32>(a, dag, epi, depth, nrhs, ctx->stream); break;
+      default: e = launch_hop_p<DWF_F16S>(a, dag, epi, depth, nrhs, ctx->stream); break;
+    }
   }
   timing_end(ctx);
   return e;
+}
+
+hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int dag, int epi, int nrhs) {
+  return launch_hop_ex(ctx, prec, prec, prec, a, out_parity, dag, epi, nrhs);
 }
 
 int hop_blocks(const dwf_context* ctx) {

@@ -27,6 +27,11 @@ void timing_end(dwf_context* ctx);
 // hop.hip
 void fill_shape(const dwf_context* ctx, HopArgs& a);
 hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int dag, int epi, int nrhs);
+// the same with the neighbour input stored at pin and the operand x at px (output at prec); the
+// mixed forms offered are FP16S in -> FP32 out (EPI_M5INV, no x) and FP32 in + FP16S x -> FP32
+// out (EPI_M5)
+hipError_t launch_hop_ex(dwf_context* ctx, int prec, int pin, int px, HopArgs a, int out_parity, int dag, int epi,
+                         int nrhs);
 int hop_blocks(const dwf_context* ctx);  // workgroups per rhs of a hop launch
 hipError_t launch_site5(dwf_context* ctx, int prec, const char* in, char* out, int dag, int inv, int nrhs);
 
@@ -47,7 +52,7 @@ enum Slot {
   S_BETA = 4,
   S_BB = 5,
   S_ACTIVE = 6,  // 1 while the rhs iterates, 0 once converged
-  S_RRMAX = 7,   // unused
+  S_RRMAX = 7,   // largest |r|^2 since the last reliable update (low-precision CG)
   S_TMP = 8,     // scratch dot result (re)
   S_TMPI = 9,    // scratch dot result (im)
   S_TRUE = 10,   // true |r|^2
@@ -58,7 +63,9 @@ enum Slot {
 // out[rhs * NSCAL + slot] = sum_k partials[rhs * count + k] (fixed order)
 hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot);
 // the same, then on the same thread mode 1: alpha (slot S_PAP); mode 2: beta and the
-// convergence step with tol2 (slot S_RR) -- scal_alpha / scal_beta + scal_converge fused
+// convergence step with tol2 (slot S_RR) -- scal_alpha / scal_beta + scal_converge fused;
+// mode 3: beta, the iteration count and S_RRMAX = max(S_RRMAX, |r|^2), without retiring a rhs
+// (the low-precision CG retires one only on its FP64 true residual)
 hipError_t reduce_partials_step(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
                                 double tol2);
 // result[rhs] = <a, b> (complex, FP64 accumulation) into scalars[rhs*NSCAL + slot (+1 imag)]
@@ -84,6 +91,11 @@ hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p,
 // r -= alpha q with |r|^2 -> S_RR ; then x += alpha p and p = r + beta p in one pass (old p)
 hipError_t cg_update_r(dwf_context* ctx, int pr, char* r, int pq, const char* q, int nrhs);
 hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r, int pp, char* p, int nrhs);
+// reliable update of the low-precision CG: p += r_true - r_iter, then r_iter = r_true (r_true FP64,
+// r_iter FP32, p at pp)
+hipError_t cg_reliable_p(dwf_context* ctx, const char* r_true, char* r_iter, int pp, char* p, int nrhs);
+// p -= (r^dag p / |r|^2 - 1) r per active rhs (r FP32; the dot in scalars S_TMP, S_TMPI)
+hipError_t cg_orth_p(dwf_context* ctx, const char* r, int pp, char* p, int nrhs);
 // scalar bookkeeping kernels
 hipError_t scal_alpha(dwf_context* ctx, int nrhs);  // alpha = rr / pAp  (0 if inactive)
 hipError_t scal_beta(dwf_context* ctx, int nrhs);   // beta = rr_new / rr_old

@@ -184,10 +184,13 @@ def test_force_workload_c4():
         op_m.close()
 
 
-def test_mixed_workload_fp32_field_solve_sampled():
-    """24^3 x 48, Ls = 24, mf = 0.00078: the mixed workload's solve (FP32 fields, FP64
-    reliable updates) reaches the FP64 true residual, and the oracle's M_pc^dag M_pc
-    applied to the GPU solution on patches around sampled sites reproduces b there."""
+@pytest.mark.parametrize("prec", [F32, F16S])
+def test_mixed_workload_field_solve_sampled(prec):
+    """24^3 x 48, Ls = 24, mf = 0.00078: the mixed workload's solve with the search direction
+    stored in FP32 or in FP16 + per-site scale (FP32 operator intermediates, FP64 reliable
+    updates) reaches an FP64 true residual of 1e-10: measured by the solver, by the FP64
+    operator of the library over the whole lattice, and by the oracle's M_pc^dag M_pc applied
+    to the GPU solution on patches around sampled sites, which reproduces b there."""
     import torch
 
     dims, Ls, mf = (24, 24, 24, 48), 24, 0.00078
@@ -195,18 +198,25 @@ def test_mixed_workload_fp32_field_solve_sampled():
     psi = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=5), EVEN)
     op64, _ = make_operator(dims, Ls, prec=F64, mf=mf, U=U, max_nrhs=1, max_cg_rhs=0)
     b = pack(op64, psi[None], EVEN)
-    op32, _ = make_operator(dims, Ls, prec=F32, mf=mf, U=U, max_nrhs=1, max_cg_rhs=1)
-    x = op32.new_field(1, prec=F64)
-    code, iters, res = op32.cg(b, x, 1, tol=1e-10, maxiter=5000)
+    opl, _ = make_operator(dims, Ls, prec=prec, mf=mf, U=U, max_nrhs=1, max_cg_rhs=1)
+    x = opl.new_field(1, prec=F64)
+    code, iters, res = opl.cg(b, x, 1, tol=1e-10, maxiter=5000)
+    print(f"prec {prec}: {iters[0]} iterations, true residual {res[0]:.3e}", flush=True)
     assert code == 0 and res[0] < 1.5e-10
-    op32.close()
-    del op32
+    opl.close()
+    del opl
     torch.cuda.empty_cache()
+    Ax = op64.new_field(1)
+    op64.mpcdagmpc(x, Ax, 1)
+    torch.cuda.synchronize()
+    cv = lambda t_: t_.view(torch.complex128)  # noqa: E731
+    whole = (torch.linalg.vector_norm(cv(b) - cv(Ax)) / torch.linalg.vector_norm(cv(b))).item()
+    assert whole < 1.5e-10
     X = unpack(op64, x, 1, EVEN)[0]
     sites = sample_sites(dims, 2, seed=11, parity=EVEN)
-    Ax = oracle_at_sites(lambda u, p: L.mpcdagmpc(u, L.on_parity(p, EVEN), 1.8, mf), U, X, dims, sites, 4)
+    Axs = oracle_at_sites(lambda u, p: L.mpcdagmpc(u, L.on_parity(p, EVEN), 1.8, mf), U, X, dims, sites, 4)
     bs = gpu_at_sites(psi, sites)
-    assert rel(Ax, bs) < 1e-7
+    assert rel(Axs, bs) < 1e-7
 
 
 def test_rb_workload_every_bench_launch_shape():
