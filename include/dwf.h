@@ -251,6 +251,24 @@ int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host);
  * stream. */
 int dwf_dot(dwf_handle h, int prec, const void* a, const void* b, int nrhs, double* result);
 
+#define DWF_DOT_NOALLOC_MAX_RHS 64
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the inner
+ * products of dwf_dot with no handle, no workspace and no allocation.  dims,
+ * Ls and prec describe the packed fields as for dwf_field_bytes; a and b are
+ * nrhs consecutive one-parity fields each; result is a device array of
+ * 2 nrhs doubles (re, im per rhs), written asynchronously on `stream`
+ * (a hipStream_t; NULL = the default stream).  The values are bitwise those
+ * of dwf_dot.  The partial sums go to a fixed device array of
+ * DWF_DOT_NOALLOC_MAX_RHS * 2048 doubles (1 MiB) that each GPU holds from the
+ * first call on it until the process ends; nrhs above DWF_DOT_NOALLOC_MAX_RHS
+ * is rejected with DWF_EINVAL.  All calls on one GPU share that array, so
+ * calls that overlap in time on one GPU (different streams, or threads)
+ * race; calls ordered on one stream do not.  Returns DWF_OK, DWF_EINVAL or
+ * DWF_EHIP. */
+int dwf_dot_noalloc(const int dims[4], int Ls, int prec, const void* a, const void* b, int nrhs, double* result,
+                    void* stream);
+
 /* ---- coarse-space transfer ------------------------------------------------ */
 
 /* Blocks of the two-level method (Two level preconditioner section: the

@@ -30,6 +30,7 @@ LIB_PATH = os.path.join(PKG, "libdwf.so")
 DWF_OK, DWF_EINVAL, DWF_ENOMEM, DWF_EHIP, DWF_ENOCONV, DWF_EBREAKDOWN, DWF_WLAMBDA = 0, -1, -2, -3, -4, -5, 1
 DWF_F64, DWF_F32, DWF_F16S = 0, 1, 2
 DWF_EVEN, DWF_ODD, DWF_BOTH = 0, 1, 2
+DWF_DOT_NOALLOC_MAX_RHS = 64  # as in include/dwf.h
 
 _STATUS = {
     DWF_EINVAL: "DWF_EINVAL",
@@ -93,6 +94,7 @@ _PROTOS = {
     "dwf_chebyshev_smoother": (_i, [_vp, _i, _d, _d, _vp, _vp, _i]),
     "dwf_gram_schmidt": (_i, [_vp, _vp, _i, _c_dbl_p]),
     "dwf_dot": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
+    "dwf_dot_noalloc": (_i, [_c_int_p, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_set_schur_form": (_i, [_vp, _i]),
     "dwf_solve_unprec": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p]),
@@ -165,6 +167,26 @@ def dwf_workspace_bytes(dims, Ls, prec, max_nrhs, max_cg_rhs):
 
 def dwf_field_bytes(dims, Ls, prec, nrhs):
     return load_library().dwf_field_bytes(_dims(dims), Ls, prec, nrhs)
+
+
+def dwf_dot_noalloc(dims, Ls, prec, a, b, nrhs, result, stream=None):
+    """The allocation-free inner products (include/dwf.h): a and b packed one-parity fields
+    (torch tensors on one HIP device), result a float64 tensor of 2 nrhs values on that device,
+    stream a hipStream_t (default: torch's current stream).  The tensors are checked here; the
+    lattice, precision and nrhs are checked by the library, whose status code is returned."""
+    import torch
+
+    dev = a.device if isinstance(a, torch.Tensor) else None
+    if dev is None or dev.type != "cuda":
+        raise DWFError(DWF_EINVAL, "dwf_dot_noalloc: a must be a tensor on a HIP device")
+    need = dwf_field_bytes(dims, Ls, prec, nrhs) if 0 < nrhs <= DWF_DOT_NOALLOC_MAX_RHS else 0
+    pa = _tensor_ptr(a, dev, "a", nbytes=need or None)
+    pb = _tensor_ptr(b, dev, "b", nbytes=need or None)
+    pr = _tensor_ptr(result, dev, "result", dtype=torch.float64,
+                     nbytes=16 * nrhs if 0 < nrhs <= DWF_DOT_NOALLOC_MAX_RHS else None)
+    if stream is None:
+        stream = _stream()
+    return load_library().dwf_dot_noalloc(_dims(dims), int(Ls), int(prec), pa, pb, int(nrhs), pr, stream)
 
 
 def _thin(name):
