@@ -76,10 +76,10 @@ def hop_bytes_per_site(prec, Ls, nrhs=1):
 # M_pc p (pass 1: 2 S, pass 2 with p.Ap partials: 3 S), then M_pc^dag u with the residual update
 # fused into its second pass (reads t, u, r and writes r: 4 S); each pass also reads 8 L / Ls of links
 CG_ITERATION_HOPS = (
-    ("void dwf::hop_kernel<0, false, 1,", 2),
-    ("void dwf::hop_kernel<0, false, 2,", 3),
-    ("void dwf::hop_kernel<0, true, 1,", 2),
-    ("void dwf::hop_kernel<0, true, 4,", 4),
+    ("void dwf::hop_kernel<0, 0, 0, false, 1,", 2),
+    ("void dwf::hop_kernel<0, 0, 0, false, 2,", 3),
+    ("void dwf::hop_kernel<0, 0, 0, true, 1,", 2),
+    ("void dwf::hop_kernel<0, 0, 0, true, 4,", 4),
 )
 
 
@@ -171,6 +171,7 @@ def cpu_baseline_rb(cfg):
         "value": V5 / dt,
         "unit": "5D site-updates/s",
         "cores": 1,
+        "host_cores": len(os.sched_getaffinity(0)),
         "kind": "oracle",
         "sample": f"one M_pc application (= {V5} site-updates by the paper's counting) of the FP64 NumPy oracle "
         f"on the {X}x{Y}x{Z}x{T}, Ls={Ls} lattice, BLAS limited to 1 thread; {dt:.1f} s",
@@ -379,22 +380,20 @@ def _timed(fn):
 
 
 def _fill_gaussian(op, buf, nvec, dims, Ls, seed, chunk=4):
-    """Pack nvec complex Gaussian even fields into buf, a few at a time."""
+    """Pack nvec complex Gaussian even fields into buf, a few at a time, drawn on the device
+    (seeded per chunk, so handles of any precision receive the same fields)."""
     import torch
 
     import paper_2103_05034_amd as dwf
     import synth
 
     fb = op.field_bytes(1)
-    rng_fields = synth.gaussian_fermion_batch(dims, Ls, nvec, seed) if nvec * Ls * np.prod(dims) * 192 < 2**31 else None
     for k0 in range(0, nvec, chunk):
         n = min(chunk, nvec - k0)
-        if rng_fields is not None:
-            nat = rng_fields[k0 : k0 + n]
-        else:
-            nat = synth.gaussian_fermion_batch(dims, Ls, n, seed * 1000 + k0)
-        op.pack(torch.from_numpy(nat).to("cuda"), dwf.DWF_EVEN, out=buf[k0 * fb : (k0 + n) * fb])
+        nat = synth.gaussian_fermion_device(dims, Ls, n, seed * 1000 + k0)
+        op.pack(nat, dwf.DWF_EVEN, out=buf[k0 * fb : (k0 + n) * fb])
         torch.cuda.synchronize()
+        del nat
 
 
 def _setup_time(op, vecs, pristine, nvec, order, lo, hi, steps):
@@ -408,7 +407,41 @@ def _setup_time(op, vecs, pristine, nvec, order, lo, hi, steps):
     return total, R
 
 
-def run_batched(args):
+def _roofline(bytes_per_launch, hop_ms, hop_n, kernel):
+    avg = hop_ms / max(hop_n, 1)
+    achieved = bytes_per_launch / (avg * 1e-3) / 1e9 if hop_n else 0.0
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": PEAK_HBM_GBS,
+        "unit": "GB/s",
+        "frac": achieved / PEAK_HBM_GBS,
+        "traffic": None,
+        "kernel": kernel,
+        "bytes_per_launch": bytes_per_launch,
+        "avg_launch_ms": avg,
+        "launches": hop_n,
+    }
+
+
+def cheb_step_bytes(prec, Ls, nrhs):
+    """Algorithmic bytes per even 5D site and rhs of one Chebyshev step of M_pc^dag M_pc: four hop
+    passes reading and writing 2 S, 3 S, 2 S and 5 S (the last also reads T_k and T_{k-1}),
+    each with 8 L / (Ls nrhs) of links."""
+    S, Lb = SPINOR_BYTES[prec], LINK_BYTES[prec]
+    return 12 * S + 4 * 8.0 * Lb / (Ls * nrhs)
+
+
+def mixed_cg_pass_bytes(Ls, prec_p):
+    """Algorithmic bytes per even 5D site and rhs of the four hop passes of one low-precision CG
+    iteration: p stored at prec_p (FP16 + scale or FP32), t, u and r in FP32, FP32 links.
+    pass 1 reads p, writes t; pass 2 reads t and p, writes u; pass 3 reads u, writes t; pass 4
+    reads t and u, reads and writes r; each reads 8 L / Ls of links."""
+    Sp, S32, link = SPINOR_BYTES[prec_p], SPINOR_BYTES[1], 8.0 * LINK_BYTES[1] / Ls
+    return (Sp + S32 + link, 2 * S32 + Sp + link, 2 * S32 + link, 4 * S32 + link)
+
+
+def leg_batched(args, steps=3, warmup=1):
     """40 complex64 subspace vectors through the order-32 filter in one multi-rhs launch per pass,
     then FP64-accumulated Gram-Schmidt; compared with the same work in FP64 one vector at a time."""
     import torch
@@ -429,20 +462,19 @@ def run_batched(args):
     vecs = op.new_field(nvec)
     _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
     pristine = vecs.clone()
-    _setup_time(op, vecs, pristine, nvec, order, lo, hi, args.warmup)
+    _setup_time(op, vecs, pristine, nvec, order, lo, hi, warmup)
     op.enable_timing(True)
-    t_b, R_b = _setup_time(op, vecs, pristine, nvec, order, lo, hi, args.steps)
+    t_b, R_b = _setup_time(op, vecs, pristine, nvec, order, lo, hi, steps)
     hop_ms, hop_n = op.kernel_time()
     op.enable_timing(False)
     q_b = vecs[: op.field_bytes(2)].clone()
-    S, Lb = SPINOR_BYTES[1], LINK_BYTES[1]
-    # per filter step: 4 launches; pass bytes per site and rhs: 2S, 3S, 2S, 5S (last reads T_k, T_{k-1}) + links
-    link = 8.0 * Lb / (Ls * nvec)
-    step_bytes = V5h * nvec * (12 * S + 4 * link)
-    achieved = step_bytes / 4 / (hop_ms / max(hop_n, 1) * 1e-3) / 1e9
+    # one filter step = 4 launches over nvec rhs
+    per_launch = V5h * nvec * cheb_step_bytes(dwf.DWF_F32, Ls, nvec) / 4
+    roof = _roofline(per_launch, hop_ms, hop_n, "hop_kernel, FP32, 40 rhs per launch (filter passes)")
+    op.close()
     del op, vecs, pristine
     torch.cuda.empty_cache()
-    log(f"batched: {args.steps} setups in {t_b:.3f} s")
+    log(f"batched: {steps} setups in {t_b:.3f} s")
 
     # FP64, one vector at a time
     op64 = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=0)
@@ -450,28 +482,27 @@ def run_batched(args):
     v64 = op64.new_field(nvec)
     _fill_gaussian(op64, v64, nvec, dims, Ls, seed=2)
     p64 = v64.clone()
-    _setup_time(op64, v64, p64, nvec, order, lo, hi, 1 if args.warmup else 0)
-    t_64, R_64 = _setup_time(op64, v64, p64, nvec, order, lo, hi, max(1, args.steps // 2))
-    t_64 /= max(1, args.steps // 2)
+    _setup_time(op64, v64, p64, nvec, order, lo, hi, 1 if warmup else 0)
+    n64 = max(1, steps // 2)
+    t_64, R_64 = _setup_time(op64, v64, p64, nvec, order, lo, hi, n64)
+    t_64 /= n64
     # agreement of the orthonormalised vectors (FP32 storage vs FP64)
     a = op64.unpack(v64[: op64.field_bytes(2)], 2, dwf.DWF_EVEN)
     op32 = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F32, max_nrhs=2, max_cg_rhs=0)
     b = op32.unpack(q_b, 2, dwf.DWF_EVEN)
     agree = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(a))
-    per_step = t_b / args.steps
+    op64.close()
+    op32.close()
+    del op64, op32, v64, p64, a, b
+    torch.cuda.empty_cache()
+    per_step = t_b / steps
     return {
-        "metric": METRIC,
         "value": nvec / per_step,
         "unit": "Chebyshev setup vecs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": per_step * 1e3,
         "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
+        "ms_per_step": per_step * 1e3,
+        "steps": steps,
         "dtype": "f32",
-        "data": "synthetic",
         "config": {
             "workload": "40 complex64 vectors, order-32 Chebyshev filter [0.05,60] of M_pc^dag M_pc in one "
             "multi-rhs launch per pass + FP64-accumulated Gram-Schmidt, 16^3x32 Ls=16",
@@ -480,28 +511,24 @@ def run_batched(args):
             "speedup_vs_fp64_unbatched": t_64 / per_step,
             "fp32_vs_fp64_rel_diff_first_two_vectors": agree,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": PEAK_HBM_GBS,
-            "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
-            "kernel": "hop_kernel, FP32, 40 rhs per launch",
-            "avg_launch_ms": hop_ms / max(hop_n, 1),
-            "launches": hop_n,
-        },
+        "roofline": roof,
     }
 
 
-def run_mixed(args):
+def run_batched(args):
+    leg = leg_batched(args, max(args.steps, 1), args.warmup)
+    return {"metric": METRIC, "n_gpus": 1, "warmup": args.warmup, "scaling": "weak", "vs_baseline": None,
+            "data": "synthetic", **leg}
+
+
+def leg_mixed(args):
     """Chebyshev setup of 24 vectors + 2 CG solves to 1e-10 at near-physical mass.
 
-    Mixed: the setup runs on FP16 + per-site-scale fields (FP32 arithmetic, batched, FP64
-    Gram-Schmidt); the solves run on FP32 fields with FP64 reliable updates, both rhs batched.
-    Plain: the same work in FP64, one vector / rhs at a time.  A CG whose inner fields are also
-    FP16 is attempted with a bounded iteration count and reported: at this conditioning the FP16
-    rounding of the operator's intermediate fields exceeds the residual it has to resolve."""
+    Mixed: the setup runs on FP16 + per-site-scale fields (FP32 arithmetic, 24 vectors batched,
+    FP64 Gram-Schmidt); the two solves run batched with the search direction in FP16 + scale,
+    FP32 operator intermediates and residual, FP64 solution and reliable updates.  Plain: the
+    same work in FP64, one vector / rhs at a time.  The same solves with an FP32 search
+    direction are reported beside them."""
     import torch
 
     import paper_2103_05034_amd as dwf
@@ -510,6 +537,9 @@ def run_mixed(args):
     cfg = WORKLOADS["mixed"]
     dims, Ls, nvec = cfg["dims"], cfg["Ls"], cfg["nvec"]
     order, lo, hi = cfg["order"], cfg["lo"], cfg["hi"]
+    X, Y, Z, T = dims
+    V5h = X * Y * Z * T * Ls // 2
+    log("mixed: building the 24^3x48 links")
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
 
     def make(prec, nb, ncg):
@@ -517,9 +547,9 @@ def run_mixed(args):
 
     # two Gaussian sources, FP64 packed
     src = make(dwf.DWF_F64, 1, 0)
-    b64 = torch.zeros(2 * src.field_bytes(1, dwf.DWF_F64), dtype=torch.uint8, device="cuda")
-    _fill_gaussian(src, b64, 2, dims, Ls, seed=5, chunk=1)
     fb = src.field_bytes(1, dwf.DWF_F64)
+    b64 = torch.zeros(2 * fb, dtype=torch.uint8, device="cuda")
+    _fill_gaussian(src, b64, 2, dims, Ls, seed=5, chunk=1)
     src.close()
     del src
 
@@ -530,14 +560,20 @@ def run_mixed(args):
         _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
         pristine = vecs.clone()
         log(f"setup prec={prec}: Chebyshev filter of {nvec} vectors (tile {spb}x{depth})")
+        op.enable_timing(True)
         t, _ = _setup_time(op, vecs, pristine, nvec, order, lo, hi, 1)
+        hop_ms, hop_n = op.kernel_time()
+        op.enable_timing(False)
         log(f"setup prec={prec}: {t:.3f} s")
+        per_launch = V5h * nb * cheb_step_bytes(prec, Ls, nb) / 4
+        roof = _roofline(per_launch, hop_ms, hop_n, f"hop_kernel, {['FP64', 'FP32', 'FP16+scale'][prec]}, "
+                         f"{nb} rhs per launch (filter passes)")
         op.close()
         del op, vecs, pristine
         torch.cuda.empty_cache()
-        return t, [spb, depth]
+        return t, [spb, depth], roof
 
-    def solve(prec, batched, maxiter=100000, tag=""):
+    def solve(prec, batched, tag):
         op = make(prec, 2 if batched else 1, 2 if batched else 1)
         op.autotune(2 if batched else 1, 2)
         x64 = torch.zeros_like(b64)
@@ -548,67 +584,59 @@ def run_mixed(args):
             chunks = [(0, 2)] if batched else [(0, 1), (1, 2)]
             for k0, k1 in chunks:
                 code, it, r = op.cg(b64[k0 * fb : k1 * fb], x64[k0 * fb : k1 * fb], k1 - k0, tol=1e-10,
-                                    maxiter=maxiter, allow_noconv=True)
+                                    maxiter=20000, allow_noconv=True)
                 codes.append(code)
                 iters.extend(it)
                 res.extend(r)
 
+        op.enable_timing(True)
         t, _ = _timed(run)
+        hop_ms, hop_n = op.kernel_time()
+        op.enable_timing(False)
         log(f"{tag}: {t:.3f} s, iterations {iters}, residuals {res}, status {codes}")
         op.close()
         del op, x64
         torch.cuda.empty_cache()
-        return t, iters, res, codes
+        return {"solve_s": t, "cg_iterations": iters, "true_rel_residual": res, "converged": not any(codes),
+                "hop_ms": hop_ms, "hop_launches": hop_n}
 
-    t_set_mixed, tile_mixed = setup(dwf.DWF_F16S, nvec)
-    t_sol_mixed, it_mixed, res_mixed, codes_mixed = solve(dwf.DWF_F32, True, tag="FP32-field CG")
-    t_set_plain, tile_plain = setup(dwf.DWF_F64, 1)
-    t_sol_plain, it_plain, res_plain, codes_plain = solve(dwf.DWF_F64, False, tag="FP64 CG")
-    cap = 2 * max(it_plain)
-    t_f16, it_f16, res_f16, codes_f16 = solve(dwf.DWF_F16S, True, maxiter=cap, tag="FP16-field CG")
-    if any(codes_mixed) or any(codes_plain):
-        raise SystemExit(f"a solve did not converge: mixed {codes_mixed}, plain {codes_plain}")
-    total_mixed = t_set_mixed + t_sol_mixed
-    total_plain = t_set_plain + t_sol_plain
+    t_set_mixed, tile_mixed, roof_setup = setup(dwf.DWF_F16S, nvec)
+    f16 = solve(dwf.DWF_F16S, True, "FP16-field CG")
+    f32 = solve(dwf.DWF_F32, True, "FP32-field CG")
+    t_set_plain, tile_plain, _ = setup(dwf.DWF_F64, 1)
+    f64 = solve(dwf.DWF_F64, False, "FP64 CG")
+    if not (f16["converged"] and f32["converged"] and f64["converged"]):
+        raise SystemExit(f"a solve did not converge: FP16 {f16}, FP32 {f32}, FP64 {f64}")
+    # the FP16-field solve's hop launches: the mean of the four passes over 2 rhs
+    per_launch = 2 * V5h * sum(mixed_cg_pass_bytes(Ls, dwf.DWF_F16S)) / 4
+    roof = _roofline(per_launch, f16.pop("hop_ms"), f16.pop("hop_launches"),
+                     "hop_kernel of the FP16-field CG (2 rhs; p FP16+scale, t/u/r FP32; mean of the four passes)")
+    for d in (f32, f64):
+        d.pop("hop_ms"), d.pop("hop_launches")
+    total_mixed = t_set_mixed + f16["solve_s"]
+    total_plain = t_set_plain + f64["solve_s"]
     return {
-        "metric": METRIC,
         "value": total_plain / total_mixed,
         "unit": "x (plain FP64 time / mixed time), setup of 24 vectors + 2 CG solves to 1e-10",
-        "n_gpus": 1,
-        "steps": 1,
-        "warmup": 0,
-        "ms_per_step": total_mixed * 1e3,
         "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "setup: f16+scale storage, f32 arithmetic; solves: f32 fields, f64 reliable updates",
-        "data": "synthetic",
+        "ms_per_step": total_mixed * 1e3,
+        "steps": 1,
+        "dtype": "f16+scale storage, f32 arithmetic, f64 reliable updates and solution",
         "config": {
             "workload": "24^3x48 Ls=24 M5=1.8 mf=0.00078 links exp(0.15iH): Chebyshev setup of 24 vectors "
             "(order 32 [0.05,60]) + FP64 Gram-Schmidt + 2 CG solves to 1e-10",
-            "mixed": {
-                "setup_s": t_set_mixed,
-                "setup_tile": tile_mixed,
-                "solve_s": t_sol_mixed,
-                "cg_iterations": it_mixed,
-                "true_rel_residual": res_mixed,
-            },
-            "plain_f64": {
-                "setup_s": t_set_plain,
-                "setup_tile": tile_plain,
-                "solve_s": t_sol_plain,
-                "cg_iterations": it_plain,
-                "true_rel_residual": res_plain,
-            },
-            "fp16_field_cg_attempt": {
-                "maxiter": cap,
-                "solve_s": t_f16,
-                "cg_iterations": it_f16,
-                "true_rel_residual": res_f16,
-                "converged": not any(codes_f16),
-            },
+            "mixed": {"setup_s": t_set_mixed, "setup_tile": tile_mixed, "setup_roofline": roof_setup, **f16},
+            "plain_f64": {"setup_s": t_set_plain, "setup_tile": tile_plain, **f64},
+            "fp32_field_solves": {**f32, "x_plain_over_mixed": total_plain / (t_set_mixed + f32["solve_s"])},
         },
+        "roofline": roof,
     }
+
+
+def run_mixed(args):
+    leg = leg_mixed(args)
+    return {"metric": METRIC, "n_gpus": 1, "warmup": 0, "scaling": "weak", "vs_baseline": None,
+            "data": "synthetic", **leg}
 
 
 def run_force(args):
@@ -998,6 +1026,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rb_solve", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="default workload only: skip the batched and mixed legs")
     ap.add_argument("--tile", type=int, default=0, help="sites per workgroup of the hop kernels (0 = autotune)")
     ap.add_argument("--depth", type=int, default=0, help="neighbour-load pipeline depth with --tile (0 = keep)")
     ap.add_argument("--order", type=int, default=-1,
@@ -1038,6 +1067,13 @@ def main():
         if not args.no_cpu_baseline:
             log("timing the oracle (cpu baseline)")
             out["cpu_baseline"] = cpu_baseline_rb(WORKLOADS["rb_solve"])
+        if not args.no_legs:
+            # the metric's other parts, each on its own workload with its own roofline
+            out["legs"] = {}
+            log("leg: batched Chebyshev setup (16^3x32, Ls 16, 40 FP32 vectors)")
+            out["legs"]["batched"] = leg_batched(args)
+            log("leg: FP64 vs mixed setup + 2 solves (24^3x48, Ls 24, mf 0.00078)")
+            out["legs"]["mixed"] = leg_mixed(args)
     print(json.dumps(out), flush=True)
 
 

@@ -28,6 +28,7 @@ __all__ = [
     "unit_links",
     "gaussian_fermion",
     "gaussian_fermion_batch",
+    "gaussian_fermion_device",
     "random_link_sites",
 ]
 
@@ -95,6 +96,20 @@ def gaussian_fermion_batch(dims, Ls: int, nrhs: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     g = rng.standard_normal((nrhs, Ls, T, Z, Y, X, 4, 3, 2))
     return g[..., 0] + 1j * g[..., 1]
+
+
+def gaussian_fermion_device(dims, Ls: int, nrhs: int, seed: int, device="cuda"):
+    """``nrhs`` complex Gaussian fields ``[nrhs][Ls][T][Z][Y][X][4][3]`` (complex128, Re, Im
+    ~ N(0,1)) drawn on a torch device from a generator seeded with ``seed``.  For lattices
+    whose host-side draw would take minutes; a different stream of numbers from
+    ``gaussian_fermion_batch`` with the same seed."""
+    import torch
+
+    X, Y, Z, T = (int(d) for d in dims)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    g = torch.randn((nrhs, Ls, T, Z, Y, X, 4, 3, 2), dtype=torch.float64, device=device, generator=gen)
+    return torch.view_as_complex(g)
 
 
 def random_link_sites(dims, count: int, seed: int):
