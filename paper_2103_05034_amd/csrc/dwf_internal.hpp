@@ -109,11 +109,9 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
 // grouped so that one lane moves 16 bytes per load:
 //   FP64 : [V4h][12][Ls]      complex128            (1 component per 16 B)
 //   FP32 : [V4h][6][Ls][2]    complex64, c = 2j + k (2 components per 16 B)
-//   FP16S: [V4h][12][Ls]      half pairs (4 B), then [V4h][Ls] FP32 scales
+//   FP16S: [V4h][3][Ls][8]    halves (4 components per 16 B), then [V4h][Ls] FP32 scales
 // In each case s runs fastest across lanes, so a wave's load is contiguous.
 // ---------------------------------------------------------------------------
-typedef _Float16 half2v __attribute__((ext_vector_type(2)));
-
 template <int PREC>
 struct Store;
 
@@ -121,6 +119,16 @@ template <>
 struct Store<DWF_F64> {
   using real = double;
   static constexpr size_t bytes_per_spinor = 192;
+  struct Raw {
+    cplx<double> v[12];
+  };
+  __device__ static void load_raw(const char* base, size_t V4h, int Ls, size_t h, int s, Raw& r) {
+    load(base, V4h, Ls, h, s, r.v);
+  }
+  __device__ static void unpack(const Raw& r, cplx<double> v[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = r.v[c];
+  }
   __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<double> v[12]) {
     const double2* p = reinterpret_cast<const double2*>(base) + h * 12 * Ls + s;
 #pragma unroll
@@ -163,6 +171,16 @@ template <>
 struct Store<DWF_F32> {
   using real = float;
   static constexpr size_t bytes_per_spinor = 96;
+  struct Raw {
+    cplx<float> v[12];
+  };
+  __device__ static void load_raw(const char* base, size_t V4h, int Ls, size_t h, int s, Raw& r) {
+    load(base, V4h, Ls, h, s, r.v);
+  }
+  __device__ static void unpack(const Raw& r, cplx<float> v[12]) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = r.v[c];
+  }
   __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
     const float4* p = reinterpret_cast<const float4*>(base) + h * 6 * Ls + s;
 #pragma unroll
@@ -203,21 +221,36 @@ struct Store<DWF_F32> {
 };
 
 // FP16 values v * (1 / scale) (round to nearest even) plus one FP32 scale =
-// max |v| per (site, s).  Data [V4h][12][Ls] half pairs (4 bytes per lane and
-// component: wider groups made the compiler hoist every direction's loads and
-// halve the occupancy); the scale array follows the half data of the same rhs.
+// max |v| per (site, s).  Data [V4h][3][Ls] groups of 8 halves (16 bytes per
+// lane and load: components 4j .. 4j+3 as re, im pairs), then the scale array
+// [V4h][Ls] of the same rhs.
+typedef _Float16 half8v __attribute__((ext_vector_type(8)));
+
 template <>
 struct Store<DWF_F16S> {
   using real = float;
   static constexpr size_t bytes_per_spinor = 52;
-  __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
-    const half2v* p = reinterpret_cast<const half2v*>(base) + h * 12 * Ls + s;
-    const float scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
+  // the stored form of one spinor, as loaded: 3 x 16 bytes and the scale
+  struct Raw {
+    half8v q[3];
+    float scale;
+  };
+  __device__ static void load_raw(const char* base, size_t V4h, int Ls, size_t h, int s, Raw& r) {
+    const half8v* p = reinterpret_cast<const half8v*>(base) + h * 3 * Ls + s;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      half2v t = p[(size_t)c * Ls];
-      v[c] = {(float)t.x * scale, (float)t.y * scale};
-    }
+    for (int j = 0; j < 3; ++j) r.q[j] = p[(size_t)j * Ls];
+    r.scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
+  }
+  __device__ static void unpack(const Raw& r, cplx<float> v[12]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[4 * j + k] = {(float)r.q[j][2 * k] * r.scale, (float)r.q[j][2 * k + 1] * r.scale};
+  }
+  __device__ static void load(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
+    Raw r;
+    load_raw(base, V4h, Ls, h, s, r);
+    unpack(r, v);
   }
   __device__ static void load_nt(const char* base, size_t V4h, int Ls, size_t h, int s, cplx<float> v[12]) {
     load(base, V4h, Ls, h, s, v);  // plain loads: the scale array makes it two streams per spinor
@@ -226,15 +259,18 @@ struct Store<DWF_F16S> {
     float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 12; ++c) m = fmaxf(m, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
-    half2v* p = reinterpret_cast<half2v*>(base) + h * 12 * Ls + s;
+    half8v* p = reinterpret_cast<half8v*>(base) + h * 3 * Ls + s;
     reinterpret_cast<float*>(base + V4h * Ls * 48)[h * Ls + s] = m;
     const float r = 1.f / ((m > 0.f) ? m : 1.f);  // one correctly rounded division per spinor
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-      half2v t;
-      t.x = (_Float16)(v[c].re * r);
-      t.y = (_Float16)(v[c].im * r);
-      p[(size_t)c * Ls] = t;
+    for (int j = 0; j < 3; ++j) {
+      half8v t;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        t[2 * k] = (_Float16)(v[4 * j + k].re * r);
+        t[2 * k + 1] = (_Float16)(v[4 * j + k].im * r);
+      }
+      p[(size_t)j * Ls] = t;
     }
   }
 };

@@ -69,24 +69,34 @@ __device__ __forceinline__ void hop_compute(const cplx<R> psi[12], const cplx<R>
 __host__ __device__ constexpr int dir_at(int k) { return k; }
 
 // compute the direction of step K from its buffer slot, then refill the slot
-// with the neighbour of step K + DEPTH
+// with the neighbour of step K + DEPTH.  The slots hold spinors as stored
+// (FP16 + scale stays packed until its direction is computed).
 template <int PREC, bool DAG, int K, int DEPTH>
 __device__ __forceinline__ void hop_pipeline(const char* in, long long V4h, int Ls, int s, const int nh[8],
                                              const cplx<typename Store<PREC>::real>* __restrict__ ll, int spb,
-                                             int sl, cplx<typename Store<PREC>::real> (&buf)[DEPTH][12],
+                                             int sl, typename Store<PREC>::Raw (&buf)[DEPTH],
                                              cplx<typename Store<PREC>::real> acc[12]) {
   if constexpr (K < 8) {
-    hop_compute<typename Store<PREC>::real, DAG, dir_at(K)>(buf[K % DEPTH], ll, spb, sl, acc);
-    if constexpr (K + DEPTH < 8) Store<PREC>::load(in, V4h, Ls, nh[dir_at(K + DEPTH)], s, buf[K % DEPTH]);
+    cplx<typename Store<PREC>::real> psi[12];
+    Store<PREC>::unpack(buf[K % DEPTH], psi);
+    if constexpr (PREC == DWF_F16S) {
+      // the packed slot is refilled before the arithmetic (it is small next to psi)
+      if constexpr (K + DEPTH < 8) Store<PREC>::load_raw(in, V4h, Ls, nh[dir_at(K + DEPTH)], s, buf[K % DEPTH]);
+      hop_compute<typename Store<PREC>::real, DAG, dir_at(K)>(psi, ll, spb, sl, acc);
+    } else {
+      // psi is the slot itself: refill it once its direction is computed
+      hop_compute<typename Store<PREC>::real, DAG, dir_at(K)>(psi, ll, spb, sl, acc);
+      if constexpr (K + DEPTH < 8) Store<PREC>::load_raw(in, V4h, Ls, nh[dir_at(K + DEPTH)], s, buf[K % DEPTH]);
+    }
     hop_pipeline<PREC, DAG, K + 1, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
   }
 }
 
 template <int PREC, int J, int DEPTH>
 __device__ __forceinline__ void hop_prologue(const char* in, long long V4h, int Ls, int s, const int nh[8],
-                                             cplx<typename Store<PREC>::real> (&buf)[DEPTH][12]) {
+                                             typename Store<PREC>::Raw (&buf)[DEPTH]) {
   if constexpr (J < DEPTH) {
-    Store<PREC>::load(in, V4h, Ls, nh[dir_at(J)], s, buf[J]);
+    Store<PREC>::load_raw(in, V4h, Ls, nh[dir_at(J)], s, buf[J]);
     hop_prologue<PREC, J + 1, DEPTH>(in, V4h, Ls, s, nh, buf);
   }
 }
@@ -127,13 +137,10 @@ __device__ __forceinline__ void load_half(const char* base, long long V4h, int L
       v[2 * j + 1] = {t.z, t.w};
     }
   } else {
-    const half2v* p = reinterpret_cast<const half2v*>(base) + (h * 12 + c0) * Ls + s;
-    const float scale = reinterpret_cast<const float*>(base + V4h * Ls * 48)[h * Ls + s];
+    cplx<R> full[12];
+    Store<PREC>::load(base, V4h, Ls, h, s, full);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      half2v t = p[(size_t)c * Ls];
-      v[c] = {(R)t.x * scale, (R)t.y * scale};
-    }
+    for (int c = 0; c < 6; ++c) v[c] = full[c0 + c];
   }
 }
 
@@ -272,7 +279,7 @@ hop_kernel(HopArgs a) {
     const size_t off = (size_t)rhs * a.stride;
     const char* in = a.in + (size_t)rhs * a.in_stride;
     const char* xb = a.x ? a.x + (size_t)rhs * a.x_stride : nullptr;
-    cplx<R> buf[DEPTH][12];
+    typename Store<PIN>::Raw buf[DEPTH];
     if (valid) hop_prologue<PIN, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
     __syncthreads();  // links staged (first rhs); scratch free (later rhs)
     cplx<R> acc[12];
