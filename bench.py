@@ -44,6 +44,9 @@ WORKLOADS = {
     "mixed": dict(dims=(24, 24, 24, 48), Ls=24, M5=1.8, mf=0.00078, eps=0.15, nvec=24, order=32, lo=0.05, hi=60.0),
     "force": dict(dims=(8, 8, 8, 16), Ls=12, M5=1.8, mf=0.01, eps=0.2),
     "copy": dict(bytes=4 << 30),
+    # M_pc^dag M_pc alone on the 16^3x32 (Ls 16, links exp(0.2iH)) or 24^3x48 (Ls 24, exp(0.15iH)) lattice
+    "operator": dict(lattices={"16x16x16x32": ((16, 16, 16, 32), 16, 0.2), "24x24x24x48": ((24, 24, 24, 48), 24, 0.15)},
+                     M5=1.8, mf=0.01),
     "krylov": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, tol=1e-10),
     # Algorithm A: 4x2x4x2 blocks, 40 basis vectors; Algorithm B: 2^4 blocks, 32 (both chirality-split)
     "coarse": dict(dims=(16, 16, 16, 32), Ls=16, M5=1.8, mf=0.01, eps=0.2, algos={"A": ((4, 2, 4, 2), 20), "B": ((2, 2, 2, 2), 16)}),
@@ -639,8 +642,16 @@ def run_mixed(args):
             "data": "synthetic", **leg}
 
 
+def force_bytes(V4, Ls):
+    """Algorithmic bytes of one force-kernel launch (both parities): a and b read once on each
+    parity (4 FP64 half fields) and the gradient written, 4 links x 9 complex128 per 4D site."""
+    return 4 * (V4 // 2) * Ls * SPINOR_BYTES[0] + V4 * 4 * 9 * 16
+
+
 def run_force(args):
-    """dS/dU of S = phi^dag (M_pc^dag M_pc)^-1 phi on 8^3 x 16, Ls = 12, FP64: CG, M_pc, force kernel."""
+    """dS/dU of S = phi^dag (M_pc^dag M_pc)^-1 phi on 8^3 x 16, Ls = 12, FP64: CG, M_pc, force kernel;
+    and the force kernel alone on the 16^3 x 32, Ls = 16 lattice, where its launch fills the chip,
+    timed with HIP events against its algorithmic bytes."""
     import torch
 
     import paper_2103_05034_amd as dwf
@@ -664,9 +675,38 @@ def run_force(args):
     for _ in range(args.warmup):
         step()
     t, (G, it, res) = _timed(lambda: [step() for _ in range(args.steps)][-1])
-    # force kernel alone
+    op.close()
+    del op, U, phi, X, Y, G
+    torch.cuda.empty_cache()
+
+    # the force kernel on the 16^3 x 32, Ls = 16 lattice: dwf_force = two hop passes (Z, W) + the
+    # force kernel; the hop passes are timed by the library's HIP events and subtracted
+    c2 = WORKLOADS["rb_solve"]
+    d2, L2 = c2["dims"], c2["Ls"]
+    V4 = int(np.prod(d2))
+    U2 = torch.from_numpy(synth.gauge_links(d2, c2["eps"], seed=0)).to("cuda")
+    op2 = dwf.Operator(U2, d2, L2, c2["M5"], c2["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=1)
+    op2.autotune(1, 3)
+    X2, Y2 = op2.new_field(1), op2.new_field(1)
+    _fill_gaussian(op2, X2, 1, d2, L2, seed=31)
+    _fill_gaussian(op2, Y2, 1, d2, L2, seed=32)
+    G2 = op2.force(X2, Y2)
+    reps = 20
     torch.cuda.synchronize()
-    tk, _ = _timed(lambda: [op.force(X, Y, G) for _ in range(20)])
+    op2.enable_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        op2.force(X2, Y2, G2)
+    e1.record()
+    torch.cuda.synchronize()
+    hop_ms, hop_n = op2.kernel_time()
+    op2.enable_timing(False)
+    total_ms = e0.elapsed_time(e1)
+    kernel_ms = (total_ms - hop_ms) / reps
+    nbytes = force_bytes(V4, L2)
+    achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+    op2.close()
     return {
         "metric": METRIC,
         "value": args.steps / t,
@@ -684,8 +724,77 @@ def run_force(args):
             "workload": "pseudofermion force dS/dU, 8^3x16 Ls=12 mf=0.01, FP64",
             "cg_iterations": it,
             "true_rel_residual": res,
-            "force_kernel_ms": tk / 20 * 1e3,
+            "force_kernel_16x16x16x32_Ls16": {
+                "dwf_force_ms": total_ms / reps,
+                "hop_passes_ms": hop_ms / reps,
+                "force_kernel_ms": kernel_ms,
+            },
         },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": None,
+            "kernel": "force_kernel, 16^3x32 Ls=16 (both parities; bytes: a, b on both parities + the gradient)",
+            "bytes_per_launch": nbytes,
+            "avg_launch_ms": kernel_ms,
+            "launches": reps,
+        },
+    }
+
+
+def run_operator(args):
+    """M_pc^dag M_pc applications (args.steps of them, after args.warmup) on one lattice at one
+    storage precision and rhs count, in the autotuned launch shape: the kernel-level view of the
+    hop kernels for profiles, with a roofline from HIP events and the per-site bytes of a
+    M_pc^dag M_pc (10 S + 32 L / (Ls nrhs) per even 5D site and rhs)."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+    import synth
+
+    cfg = WORKLOADS["operator"]
+    dims, Ls, eps = cfg["lattices"][args.lattice]
+    prec = {"f64": dwf.DWF_F64, "f32": dwf.DWF_F32, "f16s": dwf.DWF_F16S}[args.prec]
+    nrhs = args.nrhs
+    X, Y, Z, T = dims
+    V5h = X * Y * Z * T * Ls // 2
+    U = torch.from_numpy(synth.gauge_links(dims, eps, seed=0)).to("cuda")
+    op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=prec, max_nrhs=nrhs, max_cg_rhs=0)
+    if args.order >= 0:
+        op.set_order(args.order)
+    spb, depth, _ = op.autotune(nrhs, 3)
+    v = op.new_field(nrhs)
+    _fill_gaussian(op, v, nrhs, dims, Ls, seed=2)
+    w = op.new_field(nrhs)
+    for _ in range(args.warmup):
+        op.mpcdagmpc(v, w, nrhs)
+    torch.cuda.synchronize()
+    op.enable_timing(True)
+    t, _ = _timed(lambda: [op.mpcdagmpc(v, w, nrhs) for _ in range(args.steps)])
+    hop_ms, hop_n = op.kernel_time()
+    op.enable_timing(False)
+    S, Lb = SPINOR_BYTES[prec], LINK_BYTES[prec]
+    per_app = V5h * nrhs * (10 * S + 32.0 * Lb / (Ls * nrhs))
+    op.close()
+    return {
+        "metric": METRIC,
+        "value": 2 * V5h * 2 * nrhs * args.steps / t,
+        "unit": "5D site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"M_pc^dag M_pc, {args.lattice} Ls={Ls}, {args.prec}, {nrhs} rhs per launch",
+                   "tile": {"sites_per_block": spb, "pipeline_depth": depth}},
+        "roofline": _roofline(per_app / 4, hop_ms, hop_n, f"hop_kernel, {args.prec}, {nrhs} rhs (mean of the 4 passes)"),
     }
 
 
@@ -1016,6 +1125,7 @@ def run_hdcr(args):
 
 
 RUNNERS = {"batched": run_batched, "mixed": run_mixed, "force": run_force, "copy": run_copy, "coarse": run_coarse,
+           "operator": run_operator,
            "krylov": run_krylov, "hdcr": run_hdcr}
 
 
@@ -1027,6 +1137,10 @@ def main():
     ap.add_argument("--workload", default="rb_solve", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true", help="default workload only: skip the batched and mixed legs")
+    ap.add_argument("--lattice", default="16x16x16x32", choices=sorted(WORKLOADS["operator"]["lattices"]),
+                    help="--workload operator: lattice")
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32", "f16s"], help="--workload operator: storage")
+    ap.add_argument("--nrhs", type=int, default=1, help="--workload operator: rhs per launch")
     ap.add_argument("--tile", type=int, default=0, help="sites per workgroup of the hop kernels (0 = autotune)")
     ap.add_argument("--depth", type=int, default=0, help="neighbour-load pipeline depth with --tile (0 = keep)")
     ap.add_argument("--order", type=int, default=-1,

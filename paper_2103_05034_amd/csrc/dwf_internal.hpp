@@ -397,6 +397,7 @@ struct HopArgs {
   int rpb;            // right-hand sides per workgroup (looped, sharing the LDS links)
   const double* scal; // EPI_CGR: per-rhs solver scalars, alpha_cg = scal[rhs * NSCAL + S_ALPHA]
   int x_after;        // EPI_M5INV: add beta * x after the inverse instead of before
+  float one;          // 1.0, passed at run time (keeps the FP16 projection FMAs as mixed-precision FMAs)
 };
 
 // ---------------------------------------------------------------------------

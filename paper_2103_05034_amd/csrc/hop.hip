@@ -63,41 +63,111 @@ __device__ __forceinline__ void hop_compute(const cplx<R> psi[12], const cplx<R>
   reconstruct<MU, SIGMA>(chi, acc);
 }
 
+// The same direction for an FP16 + scale neighbour, without unpacking it:
+// the projection reads the halves directly (each real is one mixed-precision
+// FMA, f16 * (+-1) + f16 in FP32; `one` is 1.0 passed at run time so that the
+// FMA is not folded into an add of two conversions), the link multiply runs on
+// the unscaled half spinor, and the site's scale enters the reconstruction's
+// FMAs.  48 fewer vector instructions per direction than unpack + project.
+template <int MU, int SIGMA>
+__device__ __forceinline__ void project_f16(const typename Store<DWF_F16S>::Raw& r, float one, cplx<float> h[6]) {
+  const float sg = SIGMA > 0 ? one : -one;
+  auto re = [&](int c) { return r.q[c / 4][2 * (c % 4)]; };
+  auto im = [&](int c) { return r.q[c / 4][2 * (c % 4) + 1]; };
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int u0 = a, u1 = 3 + a, l0 = 6 + a, l1 = 9 + a;
+    if (MU == 0) {  // u0 + sg i l1, u1 + sg i l0
+      h[a] = {fmaf((float)im(l1), -sg, (float)re(u0)), fmaf((float)re(l1), sg, (float)im(u0))};
+      h[3 + a] = {fmaf((float)im(l0), -sg, (float)re(u1)), fmaf((float)re(l0), sg, (float)im(u1))};
+    } else if (MU == 1) {  // u0 - sg l1, u1 + sg l0
+      h[a] = {fmaf((float)re(l1), -sg, (float)re(u0)), fmaf((float)im(l1), -sg, (float)im(u0))};
+      h[3 + a] = {fmaf((float)re(l0), sg, (float)re(u1)), fmaf((float)im(l0), sg, (float)im(u1))};
+    } else if (MU == 2) {  // u0 + sg i l0, u1 - sg i l1
+      h[a] = {fmaf((float)im(l0), -sg, (float)re(u0)), fmaf((float)re(l0), sg, (float)im(u0))};
+      h[3 + a] = {fmaf((float)im(l1), sg, (float)re(u1)), fmaf((float)re(l1), -sg, (float)im(u1))};
+    } else {  // u0 + sg l0, u1 + sg l1
+      h[a] = {fmaf((float)re(l0), sg, (float)re(u0)), fmaf((float)im(l0), sg, (float)im(u0))};
+      h[3 + a] = {fmaf((float)re(l1), sg, (float)re(u1)), fmaf((float)im(l1), sg, (float)im(u1))};
+    }
+  }
+}
+
+template <bool DAG, int D>
+__device__ __forceinline__ void hop_compute_f16(const typename Store<DWF_F16S>::Raw& r, float one,
+                                                const cplx<float>* __restrict__ ll, int spb, int sl,
+                                                cplx<float> acc[12]) {
+  constexpr int MU = D / 2;
+  constexpr int BACK = D % 2;
+  constexpr int SIGMA = DAG ? (BACK ? -1 : +1) : (BACK ? +1 : -1);
+  cplx<float> hs[6];
+  project_f16<MU, SIGMA>(r, one, hs);
+  cplx<float> chi[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const cplx<float> u0 = ll[(D * 9 + 3 * i + 0) * spb + sl];
+    const cplx<float> u1 = ll[(D * 9 + 3 * i + 1) * spb + sl];
+    const cplx<float> u2 = ll[(D * 9 + 3 * i + 2) * spb + sl];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      cplx<float> v = cmul(u0, hs[3 * sp + 0]);
+      v = cfma(u1, hs[3 * sp + 1], v);
+      v = cfma(u2, hs[3 * sp + 2], v);
+      chi[3 * sp + i] = v;
+    }
+  }
+  // acc += scale * (chi, sigma B^dag chi): the lower half as in reconstruct, with the scale in the FMA
+  cplx<float> t[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) t[c] = {0.f, 0.f};
+  reconstruct<MU, SIGMA>(chi, t);
+  const float sc = r.scale;
+#pragma unroll
+  for (int c = 0; c < 12; ++c) acc[c] = {fmaf(sc, t[c].re, acc[c].re), fmaf(sc, t[c].im, acc[c].im)};
+}
+
 // Pipeline step K handles direction dir_at(K) = K (+x, -x, +y, ...): the +x and
 // -x neighbours of a wave's consecutive sites share most of their cache lines,
 // which then meet in L1.
 __host__ __device__ constexpr int dir_at(int k) { return k; }
 
-// compute the direction of step K from its buffer slot, then refill the slot
-// with the neighbour of step K + DEPTH.  The slots hold spinors as stored
-// (FP16 + scale stays packed until its direction is computed).
-template <int PREC, bool DAG, int K, int DEPTH>
+// Number of load slots of the neighbour pipeline: FP16 + scale keeps one spare
+// slot, so the neighbour DEPTH steps ahead is loaded into a free slot before
+// the packed one in use is computed (no register copy); the wider precisions
+// compute a slot in place and then refill it.
+template <int PREC, int DEPTH>
+struct Slots {
+  static constexpr int n = PREC == DWF_F16S ? DEPTH + 1 : DEPTH;
+};
+
+// compute the direction of step K from its slot; the neighbour of step
+// K + DEPTH goes into slot (K + DEPTH) % NS
+template <int PREC, bool DAG, int K, int DEPTH, int NS>
 __device__ __forceinline__ void hop_pipeline(const char* in, long long V4h, int Ls, int s, const int nh[8],
                                              const cplx<typename Store<PREC>::real>* __restrict__ ll, int spb,
-                                             int sl, typename Store<PREC>::Raw (&buf)[DEPTH],
-                                             cplx<typename Store<PREC>::real> acc[12]) {
+                                             int sl, typename Store<PREC>::Raw (&buf)[NS],
+                                             cplx<typename Store<PREC>::real> acc[12], float one) {
   if constexpr (K < 8) {
-    cplx<typename Store<PREC>::real> psi[12];
-    Store<PREC>::unpack(buf[K % DEPTH], psi);
+    constexpr int DN = dir_at(K + DEPTH);
     if constexpr (PREC == DWF_F16S) {
-      // the packed slot is refilled before the arithmetic (it is small next to psi)
-      if constexpr (K + DEPTH < 8) Store<PREC>::load_raw(in, V4h, Ls, nh[dir_at(K + DEPTH)], s, buf[K % DEPTH]);
-      hop_compute<typename Store<PREC>::real, DAG, dir_at(K)>(psi, ll, spb, sl, acc);
+      if constexpr (K + DEPTH < 8) Store<PREC>::load_raw(in, V4h, Ls, nh[DN], s, buf[(K + DEPTH) % NS]);
+      hop_compute_f16<DAG, dir_at(K)>(buf[K % NS], one, ll, spb, sl, acc);
     } else {
-      // psi is the slot itself: refill it once its direction is computed
+      cplx<typename Store<PREC>::real> psi[12];
+      Store<PREC>::unpack(buf[K % NS], psi);
       hop_compute<typename Store<PREC>::real, DAG, dir_at(K)>(psi, ll, spb, sl, acc);
-      if constexpr (K + DEPTH < 8) Store<PREC>::load_raw(in, V4h, Ls, nh[dir_at(K + DEPTH)], s, buf[K % DEPTH]);
+      if constexpr (K + DEPTH < 8) Store<PREC>::load_raw(in, V4h, Ls, nh[DN], s, buf[(K + DEPTH) % NS]);
     }
-    hop_pipeline<PREC, DAG, K + 1, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+    hop_pipeline<PREC, DAG, K + 1, DEPTH, NS>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc, one);
   }
 }
 
-template <int PREC, int J, int DEPTH>
+template <int PREC, int J, int DEPTH, int NS>
 __device__ __forceinline__ void hop_prologue(const char* in, long long V4h, int Ls, int s, const int nh[8],
-                                             typename Store<PREC>::Raw (&buf)[DEPTH]) {
+                                             typename Store<PREC>::Raw (&buf)[NS]) {
   if constexpr (J < DEPTH) {
     Store<PREC>::load_raw(in, V4h, Ls, nh[dir_at(J)], s, buf[J]);
-    hop_prologue<PREC, J + 1, DEPTH>(in, V4h, Ls, s, nh, buf);
+    hop_prologue<PREC, J + 1, DEPTH, NS>(in, V4h, Ls, s, nh, buf);
   }
 }
 
@@ -241,33 +311,33 @@ hop_kernel(HopArgs a) {
   // them.  A thread issues all its link loads (up to eight) before its first
   // LDS store, so the staging costs one memory round trip.
   {
+    // element (dk, site) of the [72][spb] copy is staged by thread dk % Ls * spb + site
+    // (blockDim = spb * Ls), so a thread's site and its first dk come from one division
     constexpr int U = 8;
     const V* lg = reinterpret_cast<const V*>(a.links);
-    const int total = spb * 72;
-    for (int base = 0; base < total; base += U * (int)blockDim.x) {
+    const int q0 = tid / spb;
+    const int r0 = tid - q0 * spb;
+    const int h2 = site_h[r0];
+    for (int dk0 = 0; dk0 < 72; dk0 += U * Ls) {
       V t[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int idx = base + u * (int)blockDim.x + tid;
+        const int dk = dk0 + u * Ls + q0;
         t[u] = V{0, 0};
-        if (idx < total) {
-          const int dk = idx / spb;
-          const int h2 = site_h[idx - dk * spb];
-          if (h2 >= 0) {
-            if constexpr (PREC == DWF_F64) {  // each site's links are read by its own workgroup only
-              typedef double dv2 __attribute__((ext_vector_type(2)));
-              const dv2 q = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(lg + (size_t)dk * V4h + h2));
-              t[u] = V{q.x, q.y};
-            } else {  // 8-byte links: plain loads (non-temporal ones were slower)
-              t[u] = lg[(size_t)dk * V4h + h2];
-            }
+        if (dk < 72 && h2 >= 0) {
+          if constexpr (PREC == DWF_F64) {  // each site's links are read by its own workgroup only
+            typedef double dv2 __attribute__((ext_vector_type(2)));
+            const dv2 q = __builtin_nontemporal_load(reinterpret_cast<const dv2*>(lg + (size_t)dk * V4h + h2));
+            t[u] = V{q.x, q.y};
+          } else {  // 8-byte links: plain loads (non-temporal ones were slower)
+            t[u] = lg[(size_t)dk * V4h + h2];
           }
         }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int idx = base + u * (int)blockDim.x + tid;
-        if (idx < total) ll[idx] = {t[u].x, t[u].y};
+        const int dk = dk0 + u * Ls + q0;
+        if (dk < 72) ll[dk * spb + r0] = {t[u].x, t[u].y};
       }
     }
   }
@@ -279,13 +349,14 @@ hop_kernel(HopArgs a) {
     const size_t off = (size_t)rhs * a.stride;
     const char* in = a.in + (size_t)rhs * a.in_stride;
     const char* xb = a.x ? a.x + (size_t)rhs * a.x_stride : nullptr;
-    typename Store<PIN>::Raw buf[DEPTH];
-    if (valid) hop_prologue<PIN, 0, DEPTH>(in, V4h, Ls, s, nh, buf);
+    constexpr int NS = Slots<PIN, DEPTH>::n;
+    typename Store<PIN>::Raw buf[NS];
+    if (valid) hop_prologue<PIN, 0, DEPTH, NS>(in, V4h, Ls, s, nh, buf);
     __syncthreads();  // links staged (first rhs); scratch free (later rhs)
     cplx<R> acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = {0, 0};
-    if (valid) hop_pipeline<PIN, DAG, 0, DEPTH>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc);
+    if (valid) hop_pipeline<PIN, DAG, 0, DEPTH, NS>(in, V4h, Ls, s, nh, ll, spb, sl, buf, acc, a.one);
 
     char* out = a.out + off;
     cplx<R> v[12];
@@ -568,6 +639,7 @@ hipError_t launch_hop_ex(dwf_context* ctx, int prec, int pin, int px, HopArgs a,
   a.x_stride = field_bytes_rhs(ctx, px);
   a.order = ctx->order_mode ? ctx->order + (size_t)out_parity * V4h : nullptr;
   a.lds_floor = ctx->lds_floor;
+  a.one = 1.0f;
   a.nrhs = nrhs;
   a.rpb = std::max(1, std::min(ctx->rpb, nrhs));
   const int depth = ctx->depth[pin];

@@ -15,7 +15,11 @@ pytestmark = pytest.mark.gpu
 EVEN = 0
 
 
-@pytest.mark.parametrize("dims,Ls", [((2, 2, 2, 2), 4), ((4, 4, 6, 8), 5), ((4, 4, 4, 4), 8)])
+# Ls = 1, 2, 4, 8, 16, 32: every width of the in-register sum over s (the lanes of a site);
+# Ls = 5, 12: the LDS sum; Ls = 72: one workgroup lane per (site, s) looping over directions
+@pytest.mark.parametrize("dims,Ls", [((2, 2, 2, 2), 4), ((4, 4, 6, 8), 5), ((4, 4, 4, 4), 8), ((2, 2, 2, 2), 1),
+                                     ((2, 2, 4, 2), 2), ((2, 2, 2, 4), 16), ((2, 4, 2, 2), 32), ((2, 2, 2, 2), 12),
+                                     ((2, 2, 2, 2), 72)])
 def test_force_kernel_given_X_Y(dims, Ls):
     op, U = make_operator(dims, Ls, eps=0.5, seed=30)
     X = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=31), EVEN)
