@@ -63,9 +63,12 @@ struct ForceArgs {
   const char* y[2];  // per-term passes: own spinor of the term, on even and odd sites (one pass: a)
   const char* z[2];  // per-term passes: neighbour spinor of the term (one pass: b)
   const int* nbr;    // [2][8][V4h]
+  const int* order;  // [2][V4h] traversal order of the sites of each parity, or null (lexicographic)
   double2* grad;     // natural [T][Z][Y][X][4][3][3]
   Geom g;
-  int spb, nblocks, nb8;
+  int spb;
+  int nblocks;  // site blocks of spb sites per parity
+  int nb8;      // workgroups per XCD (per parity and grid row in the per-term form)
   int accumulate;    // 0: grad = term; 1: grad += term
 };
 
@@ -136,23 +139,67 @@ __global__ void __launch_bounds__(256) force_kernel(ForceArgs fa) {
   }
 }
 
+// g -= sum_{n=0,1} hy[n]_i conj(hz[n]_j): one term of the gradient from the two
+// projected half spinors (negated, as in term_outer).
+__device__ __forceinline__ void outer_sub(const cplx<double> hy[6], const cplx<double> hz[6], cplx<double> g[9]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      cplx<double> acc = g[3 * i + j];
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const cplx<double> y = hy[3 * n + i], z = hz[3 * n + j];
+        acc.re = fma(-y.re, z.re, acc.re);
+        acc.re = fma(-y.im, z.im, acc.re);
+        acc.im = fma(-y.im, z.re, acc.im);
+        acc.im = fma(y.re, z.im, acc.im);
+      }
+      g[3 * i + j] = acc;
+    }
+}
+
+// (1 + sg g_mu) projection of a spinor held in LDS (component c at
+// own[c * stride]) for a direction mu known only at run time: h = u + sg B_mu l
+// with the lower spin picked by address and the factor of B_mu (+-1 or +-i)
+// applied as (cr, ci); one of cr, ci is zero, so each component is a single
+// rounded add, as in the compile-time projection.
+__device__ __forceinline__ void project_lds(const cplx<double>* own, int stride, int mu, double sg,
+                                            cplx<double> h[6]) {
+  // B_x l = (i l1, i l0), B_y l = (-l1, l0), B_z l = (i l0, -i l1), B_t l = (l0, l1)
+  const int first = mu < 2 ? 9 : 6;   // lower spin feeding h[0..2]
+  const int second = mu < 2 ? 6 : 9;  // lower spin feeding h[3..5]
+  const double c0r = mu == 1 ? -sg : (mu == 3 ? sg : 0.0), c0i = (mu == 0 || mu == 2) ? sg : 0.0;
+  const double c1r = (mu == 1 || mu == 3) ? sg : 0.0, c1i = mu == 0 ? sg : (mu == 2 ? -sg : 0.0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const cplx<double> u0 = own[(size_t)a * stride], u1 = own[(size_t)(3 + a) * stride];
+    const cplx<double> l = own[(size_t)(first + a) * stride], m = own[(size_t)(second + a) * stride];
+    h[a] = {fma(c0r, l.re, fma(-c0i, l.im, u0.re)), fma(c0r, l.im, fma(c0i, l.re, u0.im))};
+    h[3 + a] = {fma(c1r, m.re, fma(-c1i, m.im, u1.re)), fma(c1r, m.im, fma(c1i, m.re, u1.im))};
+  }
+}
+
 // Both terms in one pass, with the four directions on four groups of lanes:
 // lane (mu, site, s) with mu slowest, so a wave holds one direction when
-// spb * Ls is a multiple of 64.  The direction-0 lanes load a(x) and b(x) of
-// their (site, s) once into LDS ([12][spb * Ls] each, so a wave's reads are
-// contiguous); every lane loads its two neighbours a(x + mu), b(x + mu)
-// together, so the four directions' loads are in flight at once, and forms
-// term 0 (a(x) with b(x + mu)) and then term 1 (b(x) with a(x + mu)) from half
-// spinors.  Used for Ls <= 64.
+// spb * Ls is a multiple of 64.  Every lane loads its two neighbours a(x + mu),
+// b(x + mu) together, so the four directions' loads are in flight at once, and
+// three of the twelve components of the site's own a(x) and b(x) (lane group mu
+// takes components 3 mu .. 3 mu + 2) into LDS ([12][spb * Ls] each, so a
+// wave's reads are contiguous).  Used for Ls <= 64.
 template <bool SHUFFLE>
 __global__ void __launch_bounds__(256) force_dir_kernel(ForceArgs fa) {
   extern __shared__ char smem_raw[];
   const int Ls = fa.g.Ls;
   const int spb = fa.spb;
+  // one grid over (site block, parity) with the parity fastest, so the two
+  // parities' workgroups of neighbouring sites run together and a spinor read
+  // as a site's own is still in L2 when the other parity reads it as a neighbour
   const int bidx = blockIdx.x;
-  const int logical = (bidx & 7) * fa.nb8 + (bidx >> 3);
-  if (logical >= fa.nblocks) return;
-  const int p = blockIdx.y;
+  const int both = (bidx & 7) * fa.nb8 + (bidx >> 3);
+  if (both >= 2 * fa.nblocks) return;
+  const int p = both & 1;
+  const int logical = both >> 1;
   const int tid = threadIdx.x;
   const int per_dir = spb * Ls;
   const int mu = tid / per_dir;
@@ -161,52 +208,53 @@ __global__ void __launch_bounds__(256) force_dir_kernel(ForceArgs fa) {
   const int s = rem - sl * Ls;
   const long long V4h = fa.g.V4h;
   const long long h0 = (long long)logical * spb;
-  const long long h = h0 + sl;
-  const bool valid = h < V4h;
+  const long long hq = h0 + sl;  // processing index
+  const bool valid = hq < V4h;
+  const long long h = fa.order && valid ? (long long)fa.order[(size_t)p * V4h + hq] : hq;
   // LDS: [4][spb][Ls][9] sums (without shuffles), then a(x) and b(x)
   cplx<double>* buf = reinterpret_cast<cplx<double>*>(smem_raw);
   cplx<double>* abuf = buf + (SHUFFLE ? 0 : (size_t)4 * per_dir * 9);
   cplx<double>* bbuf = abuf + (size_t)12 * per_dir;
   cplx<double> an[12], bn[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) an[c] = bn[c] = {0, 0};
   if (valid) {
     const long long nh = fa.nbr[((size_t)p * 8 + 2 * mu) * V4h + h];
     Store<DWF_F64>::load(fa.y[1 - p], V4h, Ls, nh, s, an);
     Store<DWF_F64>::load(fa.z[1 - p], V4h, Ls, nh, s, bn);
-  }
-  if (mu == 0 && valid) {
-    cplx<double> t[12];
-    Store<DWF_F64>::load(fa.y[p], V4h, Ls, h, s, t);
+    const double2* pa = reinterpret_cast<const double2*>(fa.y[p]) + h * 12 * Ls + s;
+    const double2* pb = reinterpret_cast<const double2*>(fa.z[p]) + h * 12 * Ls + s;
+    double2 ta[3], tb[3];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) abuf[(size_t)c * per_dir + rem] = t[c];
-    Store<DWF_F64>::load(fa.z[p], V4h, Ls, h, s, t);
+    for (int k = 0; k < 3; ++k) {
+      ta[k] = pa[(size_t)(3 * mu + k) * Ls];
+      tb[k] = pb[(size_t)(3 * mu + k) * Ls];
+    }
 #pragma unroll
-    for (int c = 0; c < 12; ++c) bbuf[(size_t)c * per_dir + rem] = t[c];
+    for (int k = 0; k < 3; ++k) {
+      abuf[(size_t)(3 * mu + k) * per_dir + rem] = {ta[k].x, ta[k].y};
+      bbuf[(size_t)(3 * mu + k) * per_dir + rem] = {tb[k].x, tb[k].y};
+    }
   }
   __syncthreads();
+  // neighbours projected as soon as they are in: term 0 takes (1 - g_mu) b(x + mu),
+  // term 1 (1 + g_mu) a(x + mu)
+  cplx<double> hz0[6], hz1[6];
+  switch (mu) {
+    case 0: project<0, -1>(bn, hz0); project<0, +1>(an, hz1); break;
+    case 1: project<1, -1>(bn, hz0); project<1, +1>(an, hz1); break;
+    case 2: project<2, -1>(bn, hz0); project<2, +1>(an, hz1); break;
+    default: project<3, -1>(bn, hz0); project<3, +1>(an, hz1); break;
+  }
   cplx<double> gm[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) gm[k] = {0, 0};
   if (valid) {
-    cplx<double> own[12];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) own[c] = abuf[(size_t)c * per_dir + rem];
-    switch (mu) {  // term 0: a(x) with (1 - g_mu) b(x + mu)
-      case 0: term_outer<0, -1>(own, bn, gm); break;
-      case 1: term_outer<1, -1>(own, bn, gm); break;
-      case 2: term_outer<2, -1>(own, bn, gm); break;
-      default: term_outer<3, -1>(own, bn, gm); break;
-    }
-#pragma unroll
-    for (int c = 0; c < 12; ++c) own[c] = bbuf[(size_t)c * per_dir + rem];
-    cplx<double> g1[9];
-    switch (mu) {  // term 1: (1 + g_mu) b(x) with a(x + mu)
-      case 0: term_outer<0, +1>(own, an, g1); break;
-      case 1: term_outer<1, +1>(own, an, g1); break;
-      case 2: term_outer<2, +1>(own, an, g1); break;
-      default: term_outer<3, +1>(own, an, g1); break;
-    }
-#pragma unroll
-    for (int k = 0; k < 9; ++k) gm[k] = cadd(gm[k], g1[k]);
+    cplx<double> hy[6];
+    project_lds(abuf + rem, per_dir, mu, -1.0, hy);  // term 0: a(x)
+    outer_sub(hy, hz0, gm);
+    project_lds(bbuf + rem, per_dir, mu, +1.0, hy);  // term 1: (1 + g_mu) b(x)
+    outer_sub(hy, hz1, gm);
   }
   if constexpr (SHUFFLE) {
 #pragma unroll
@@ -231,8 +279,9 @@ __global__ void __launch_bounds__(256) force_dir_kernel(ForceArgs fa) {
       const int k = idx - 9 * g;
       const int mu2 = g / spb;
       const int sl2 = g - mu2 * spb;
-      const long long h2 = h0 + sl2;
-      if (h2 >= V4h) continue;
+      const long long hq2 = h0 + sl2;
+      if (hq2 >= V4h) continue;
+      const long long h2 = fa.order ? (long long)fa.order[(size_t)p * V4h + hq2] : hq2;
       // four interleaved partial sums over s, added in a fixed order
       cplx<double> p4[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
       const cplx<double>* col = buf + (size_t)g * Ls * 9 + k;
@@ -254,6 +303,7 @@ hipError_t launch_force(dwf_context* ctx, const char* a_even, const char* a_odd,
                         const char* b_odd, double* grad_U) {
   ForceArgs fa;
   fa.nbr = ctx->nbr;
+  fa.order = nullptr;
   fa.grad = reinterpret_cast<double2*>(grad_U);
   fa.g = ctx->g;
   const int Ls = ctx->g.Ls;
@@ -262,15 +312,16 @@ hipError_t launch_force(dwf_context* ctx, const char* a_even, const char* a_odd,
     if (spb < 1) spb = 1;
     fa.spb = spb;
     fa.nblocks = (int)((ctx->g.V4h + spb - 1) / spb);
-    fa.nb8 = (fa.nblocks + 7) / 8;
+    fa.nb8 = (2 * fa.nblocks + 7) / 8;  // both parities in one interleaved grid
     fa.y[0] = a_even;
     fa.y[1] = a_odd;
     fa.z[0] = b_even;
     fa.z[1] = b_odd;
     fa.accumulate = 0;
+    fa.order = ctx->order_mode ? ctx->order : nullptr;  // the hop kernels' site order
     const bool shuffle = (Ls & (Ls - 1)) == 0;
     const size_t lds = ((shuffle ? 0 : (size_t)4 * spb * Ls * 9) + (size_t)2 * spb * Ls * 12) * sizeof(cplx<double>);
-    const dim3 grid(fa.nb8 * 8, 2), block(4 * spb * Ls);
+    const dim3 grid(fa.nb8 * 8), block(4 * spb * Ls);
     if (shuffle)
       hipLaunchKernelGGL((force_dir_kernel<true>), grid, block, lds, ctx->stream, fa);
     else

@@ -29,6 +29,28 @@ def test_force_kernel_given_X_Y(dims, Ls):
     assert rel(G, Go) < 1e-13
 
 
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("Ls", [4, 5])
+def test_force_kernel_traversal_order(order, Ls):
+    """The force kernel walks the sites in the handle's traversal order (XCD octants,
+    XCD t-slabs); the order only permutes which workgroup forms a site's links, so
+    the gradient is bitwise the lexicographic one (Ls = 4: in-register sums over s,
+    Ls = 5: the LDS sums)."""
+    import torch
+
+    dims = (4, 4, 4, 8)
+    op, U = make_operator(dims, Ls, eps=0.5, seed=33)
+    X = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=34), EVEN)
+    Y = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=35), EVEN)
+    Xd, Yd = pack(op, X[None], EVEN), pack(op, Y[None], EVEN)
+    G0 = op.force(Xd, Yd)
+    op.set_order(order)
+    G1 = op.force(Xd, Yd)
+    torch.cuda.synchronize()
+    assert torch.equal(G0, G1)
+    assert rel(G1.cpu().numpy(), F.link_gradient(U, X, Y, M5, MF)) < 1e-13
+
+
 def _gpu_X(op, phi_dev, tol=1e-13):
     x = op.new_field(1)
     op.cg(phi_dev, x, 1, tol=tol, maxiter=20000, allow_noconv=True)
