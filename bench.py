@@ -93,11 +93,12 @@ def cg_hop_bytes_per_launch(V5h, Ls):
     return V5h * per_site
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes):
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, prefixes=None):
     """HBM bytes per hop launch of a CG iteration from four rocprofv3 --pmc runs (FETCH_SIZE and
     WRITE_SIZE of the rb_solve bench, and of the copy workload).  Each counter is scaled by the
     factor that maps its reading on the copy kernel (copy_bytes read, copy_bytes written) onto
-    the known size; the result is the mean over the four launch kinds of a CG iteration."""
+    the known size; the result is the mean over the four launch kinds of a CG iteration (or over
+    the kernels named by `prefixes`)."""
     import csv
     import glob
     from collections import defaultdict
@@ -120,7 +121,7 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
     w_scale = copy_bytes / copy_kib(copy_write_dir)
     fetch, write = per_dispatch(fetch_dir), per_dispatch(write_dir)
     kinds = {}
-    for prefix, _ in CG_ITERATION_HOPS:
+    for prefix in prefixes or [p for p, _ in CG_ITERATION_HOPS]:
         fv = [v for n, v in fetch if n.startswith(prefix)]
         wv = [v for n, v in write if n.startswith(prefix)]
         if not fv or not wv:
@@ -132,6 +133,27 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
         }
     per_launch = sum(k["fetch_bytes"] + k["write_bytes"] for k in kinds.values()) / len(kinds)
     return {"fetch_scale": f_scale, "write_scale": w_scale, "kinds": kinds, "bytes_per_launch": per_launch}
+
+
+FORCE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_traffic.json")
+FORCE_SOURCE = os.path.join(ROOT, "paper_2103_05034_amd", "csrc", "force.hip")
+# the Ls = 16 force launches of the force workload (its Ls = 12 lattice takes the LDS-sum variant)
+FORCE_KERNEL_PREFIX = "void dwf::force_dir_kernel<true>"
+
+
+def measured_force_traffic():
+    """HBM bytes per launch of the force kernel on the 16^3 x 32, Ls = 16 lattice from the
+    rocprofv3 runs recorded in profiles/force_traffic.json, or None when force.hip changed since."""
+    import hashlib
+
+    try:
+        rec = json.load(open(FORCE_TRAFFIC_FILE))
+        digest = hashlib.sha256(open(FORCE_SOURCE, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("force_source_sha256") != digest:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def measured_traffic(key):
@@ -752,7 +774,7 @@ def run_force(args):
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": None,
+            "traffic": measured_force_traffic(),
             "kernel": "force_kernel, 16^3x32 Ls=16 (both parities; bytes: a, b on both parities + the gradient)",
             "bytes_per_launch": nbytes,
             "avg_launch_ms": kernel_ms,
@@ -1168,7 +1190,23 @@ def main():
         help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this bench and of --workload copy "
         "into profiles/hop_traffic.json (no GPU needed)",
     )
+    ap.add_argument(
+        "--traffic-force",
+        nargs=4,
+        metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+        help="the same for the force kernel of --workload force, into profiles/force_traffic.json",
+    )
     args = ap.parse_args()
+    if args.traffic_force:
+        import hashlib
+
+        rec = summarize_traffic(*args.traffic_force, copy_bytes=WORKLOADS["copy"]["bytes"],
+                                prefixes=[FORCE_KERNEL_PREFIX])
+        out = {"force_source_sha256": hashlib.sha256(open(FORCE_SOURCE, "rb").read()).hexdigest(), **rec}
+        with open(FORCE_TRAFFIC_FILE, "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps(out, indent=1))
+        return
     if args.traffic:
         import hashlib
 

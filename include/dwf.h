@@ -483,9 +483,20 @@ int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu);
  * for each candidate launch shape -- workgroups of 256, 128 and 64 lanes,
  * load-pipeline depth 1..3, 1/2/4/8 rhs per workgroup (<= nrhs) -- over
  * `reps` applications each, keeps the fastest in the handle and reports it
- * (any output pointer may be NULL). */
+ * (any output pointer may be NULL).  The result is cached per (GPU
+ * architecture, lattice, Ls, nrhs, precision, traversal order, occupancy cap,
+ * Schur form) for the life of the process, and in the text file named by the
+ * environment variable DWF_TUNE_CACHE when it is set (read on first use,
+ * appended to); a cached shape is applied without timing, and best_ms then
+ * reports the time measured when it was tuned. */
 int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb,
                  double* best_ms);
+
+/* Library plumbing (no passage of the paper defines this call).
+ * Empties the process's cache of tuned launch shapes (dwf_autotune); the
+ * DWF_TUNE_CACHE file is not changed and is read again on the next tuning.
+ * Always DWF_OK. */
+int dwf_tune_cache_clear(void);
 
 /* Library plumbing (no passage of the paper defines this call).
  * Average duration (ms) of the hopping-term kernels since the last reset, as

@@ -123,6 +123,7 @@ _PROTOS = {
     "dwf_set_occupancy": (_i, [_vp, _i]),
     "dwf_set_progress": (_i, [_vp, PROGRESS_FN, _vp, _i]),
     "dwf_autotune": (_i, [_vp, _i, _i, _c_int_p, _c_int_p, _c_int_p, _c_dbl_p]),
+    "dwf_tune_cache_clear": (_i, []),
     "dwf_enable_timing": (_i, [_vp, _i]),
     "dwf_kernel_time": (_i, [_vp, _c_dbl_p, ctypes.POINTER(ctypes.c_longlong)]),
 }
@@ -167,6 +168,12 @@ def dwf_workspace_bytes(dims, Ls, prec, max_nrhs, max_cg_rhs):
 
 def dwf_field_bytes(dims, Ls, prec, nrhs):
     return load_library().dwf_field_bytes(_dims(dims), Ls, prec, nrhs)
+
+
+def tune_cache_clear():
+    """Forget the launch shapes dwf_autotune cached in this process (the DWF_TUNE_CACHE
+    file, if any, is kept and read again on the next tuning)."""
+    _check(load_library().dwf_tune_cache_clear())
 
 
 def dwf_dot_noalloc(dims, Ls, prec, a, b, nrhs, result, stream=None):

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdwf.so")
 
-SOURCES = ["api.hip", "hop.hip", "setup.hip", "blas.hip", "force.hip", "coarse.hip", "hdcr.hip", "noalloc.hip"]
+SOURCES = ["api.hip", "hop.hip", "setup.hip", "blas.hip", "force.hip", "coarse.hip", "hdcr.hip", "noalloc.hip", "plan.cpp"]
 
 ARCH = os.environ.get("DWF_OFFLOAD_ARCH", "gfx950")
 

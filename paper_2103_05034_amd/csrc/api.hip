@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -42,91 +43,47 @@ int sync(dwf_context* c) {
 
 namespace {
 
-constexpr size_t ALIGN = 256;
-constexpr int GS_MAX = 256;
+static_assert(SPINOR_BYTES[DWF_F64] == Store<DWF_F64>::bytes_per_spinor &&
+                  SPINOR_BYTES[DWF_F32] == Store<DWF_F32>::bytes_per_spinor &&
+                  SPINOR_BYTES[DWF_F16S] == Store<DWF_F16S>::bytes_per_spinor,
+              "the workspace plan and the kernels agree on the packed spinor sizes");
 
-size_t up(size_t n) { return (n + ALIGN - 1) / ALIGN * ALIGN; }
+size_t up(size_t n) { return (n + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
 
-bool valid_dims(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs, std::string* why) {
-  if (!dims) {
-    *why = "dims is NULL";
-    return false;
-  }
-  for (int i = 0; i < 4; ++i)
-    if (dims[i] < 2 || (dims[i] & 1)) {
-      char b[96];
-      snprintf(b, sizeof b, "lattice extent %d (dim %d) must be even and >= 2", dims[i], i);
-      *why = b;
-      return false;
-    }
-  if (Ls < 1 || Ls > 128) {
-    *why = "Ls must be in [1, 128]";
-    return false;
-  }
-  if (prec != DWF_F64 && prec != DWF_F32 && prec != DWF_F16S) {
-    *why = "unknown precision";
-    return false;
-  }
-  if (max_nrhs < 1 || max_nrhs > 4096 || max_cg_rhs < 0 || max_cg_rhs > 4096) {
-    *why = "max_nrhs must be in [1, 4096], max_cg_rhs in [0, 4096]";
-    return false;
-  }
-  const long long V4 = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-  if (V4 / 2 > (1LL << 31) - 1) {
-    *why = "lattice too large for 32-bit neighbour indices";
-    return false;
-  }
-  return true;
-}
+using plan::valid_dims;
 
-// Carves (or sizes, when base == nullptr) the workspace; returns bytes used.
-size_t carve(dwf_context* c, const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs, char* base) {
-  const long long V4 = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-  const long long V4h = V4 / 2;
-  auto fb = [&](int p) { return spinor_bytes(p) * (size_t)Ls * (size_t)V4h; };
-  size_t off = 0;
-  auto take = [&](size_t n) -> char* {
-    char* p = base ? base + off : nullptr;
-    off += up(n);
-    return p;
-  };
-  const int chunk = max_nrhs > max_cg_rhs ? max_nrhs : max_cg_rhs;
-  dwf_context tmp{};
-  dwf_context* d = c ? c : &tmp;
-  d->links64 = take((size_t)2 * 8 * 9 * V4h * 16);
-  d->links32 = prec != DWF_F64 ? take((size_t)2 * 8 * 9 * V4h * 8) : nullptr;
-  d->nbr = reinterpret_cast<int*>(take((size_t)2 * 8 * V4h * 4));
-  d->t_buf = take(fb(prec) * chunk);
-  d->u_buf = take(fb(prec) * chunk);
-  d->cheb_a = take(fb(prec) * (max_nrhs > 2 ? max_nrhs : 2));
-  if (max_cg_rhs > 0) {
-    d->r64 = take(fb(DWF_F64) * max_cg_rhs);
-    d->p64 = take(fb(DWF_F64) * max_cg_rhs);
-    d->q64 = take(fb(DWF_F64) * max_cg_rhs);
-    d->b64 = take(fb(DWF_F64) * max_cg_rhs);
-    if (prec != DWF_F64) {
-      d->t64 = take(fb(DWF_F64) * max_cg_rhs);
-      d->u64 = take(fb(DWF_F64) * max_cg_rhs);
-      d->lo_r = take(fb(DWF_F32) * max_cg_rhs);
-      d->lo_x = take(fb(DWF_F32) * max_cg_rhs);
-      d->lo_p = take(fb(prec) * max_cg_rhs);
-      d->lo_q = take(fb(prec) * max_cg_rhs);
-    } else {
-      d->t64 = d->t_buf;
-      d->u64 = d->u_buf;
-    }
+// Points the handle's buffers into its workspace by the host-side plan.
+void carve(dwf_context* d, const plan::Workspace& w, char* base) {
+  auto at = [&](plan::Buffer b) -> char* { return w.offset[b] == plan::ABSENT ? nullptr : base + w.offset[b]; };
+  d->links64 = at(plan::B_LINKS64);
+  d->links32 = at(plan::B_LINKS32);
+  d->nbr = reinterpret_cast<int*>(at(plan::B_NBR));
+  d->t_buf = at(plan::B_T);
+  d->u_buf = at(plan::B_U);
+  d->cheb_a = at(plan::B_CHEB);
+  d->r64 = at(plan::B_R64);
+  d->p64 = at(plan::B_P64);
+  d->q64 = at(plan::B_Q64);
+  d->b64 = at(plan::B_B64);
+  d->lo_r = at(plan::B_LO_R);
+  d->lo_x = at(plan::B_LO_X);
+  d->lo_p = at(plan::B_LO_P);
+  d->lo_q = at(plan::B_LO_Q);
+  if (d->prec == DWF_F64) {  // FP64 handles run their CG in the handle-precision temporaries
+    d->t64 = d->t_buf;
+    d->u64 = d->u_buf;
+  } else {
+    d->t64 = at(plan::B_T64);
+    d->u64 = at(plan::B_U64);
   }
-  d->order = reinterpret_cast<int*>(take((size_t)2 * V4h * sizeof(int)));
-  d->bsite = reinterpret_cast<int*>(take((size_t)2 * V4h * sizeof(int)));
-  d->bnbr = reinterpret_cast<int*>(take((size_t)8 * V4h * sizeof(int)));
-  d->hop_partials = max_cg_rhs > 0 ? reinterpret_cast<double*>(take((size_t)max_cg_rhs * V4h * sizeof(double)))
-                                    : nullptr;
-  int pc = chunk;
-  d->partial_count = (size_t)pc;
-  d->partials = reinterpret_cast<double*>(take((size_t)pc * RED_BLOCKS * 2 * sizeof(double)));
-  d->scalars = reinterpret_cast<double*>(take((size_t)(chunk * NSCAL) * sizeof(double)));
-  d->coef = reinterpret_cast<double*>(take((size_t)(4 * GS_MAX + 8) * sizeof(double)));
-  return off;
+  d->order = reinterpret_cast<int*>(at(plan::B_ORDER));
+  d->bsite = reinterpret_cast<int*>(at(plan::B_BSITE));
+  d->bnbr = reinterpret_cast<int*>(at(plan::B_BNBR));
+  d->hop_partials = reinterpret_cast<double*>(at(plan::B_HOP_PARTIALS));
+  d->partial_count = (size_t)w.chunk;
+  d->partials = reinterpret_cast<double*>(at(plan::B_PARTIALS));
+  d->scalars = reinterpret_cast<double*>(at(plan::B_SCALARS));
+  d->coef = reinterpret_cast<double*>(at(plan::B_COEF));
 }
 
 size_t fbytes(const dwf_context* c, int prec) { return field_bytes_rhs(c, prec); }
@@ -302,7 +259,7 @@ size_t dwf_workspace_bytes(const int dims[4], int Ls, int prec, int max_nrhs, in
     fail(DWF_EINVAL, "%s", why.c_str());
     return 0;
   }
-  return carve(nullptr, dims, Ls, prec, max_nrhs, max_cg_rhs, nullptr);
+  return plan::plan_workspace(dims, Ls, prec, max_nrhs, max_cg_rhs).total;
 }
 
 int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double M5, double mf, int prec,
@@ -313,9 +270,10 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   if (!valid_dims(dims, Ls, prec, max_nrhs, max_cg_rhs, &why)) return fail(DWF_EINVAL, "%s", why.c_str());
   if (!U || !workspace) return fail(DWF_EINVAL, "U and workspace must be device pointers");
   if (!std::isfinite(M5) || !std::isfinite(mf) || M5 == 5.0) return fail(DWF_EINVAL, "M5 must be finite and != 5");
-  const size_t need = carve(nullptr, dims, Ls, prec, max_nrhs, max_cg_rhs, nullptr);
+  const plan::Workspace layout = plan::plan_workspace(dims, Ls, prec, max_nrhs, max_cg_rhs);
+  const size_t need = layout.total;
   if (ws_bytes < need) return fail(DWF_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
-  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(DWF_EINVAL, "workspace must be 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(workspace) % WS_ALIGN) return fail(DWF_EINVAL, "workspace must be 256-byte aligned");
   dwf_context* c = new (std::nothrow) dwf_context();
   if (!c) return fail(DWF_ENOMEM, "host allocation failed");
   c->g = {dims[0], dims[1], dims[2], dims[3], Ls, (long long)dims[0] * dims[1] * dims[2] * dims[3], 0};
@@ -328,7 +286,7 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   c->stream = reinterpret_cast<hipStream_t>(stream);
   c->ws = reinterpret_cast<char*>(workspace);
   c->ws_bytes = ws_bytes;
-  carve(c, dims, Ls, prec, max_nrhs, max_cg_rhs, c->ws);
+  carve(c, layout, c->ws);
   c->spb = 0;
   c->depth[0] = c->depth[1] = c->depth[2] = 2;
   c->rpb = 1;
@@ -1146,52 +1104,6 @@ int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_
   return DWF_OK;
 }
 
-// Host-built traversal orders of the half-lattice sites of each parity.
-//  mode 1: the (x, y, z) box is split into 8 equal boxes (2 x 2 x 2), one per
-//  XCD (workgroups are dealt round-robin over the XCDs and the hop kernels
-//  remap them so that XCD k runs the k-th eighth of the processing order);
-//  inside a box the sites run with t slowest, then z, y, x.  The ±t
-//  neighbours of a site are then read again while its box's few t-slices are
-//  still in that XCD's L2.
-static bool build_order(const Geom& g, int mode, std::vector<int>& ord) {
-  ord.assign((size_t)2 * g.V4h, 0);
-  if (mode == 1) {
-    if (g.X % 4 || g.Y % 4 || g.Z % 4) return false;
-    const int bx = g.X / 2, by = g.Y / 2, bz = g.Z / 2;
-    for (int p = 0; p < 2; ++p) {
-      size_t k = (size_t)p * g.V4h;
-      for (int r = 0; r < 8; ++r) {
-        const int ox = (r & 1) * bx, oy = ((r >> 1) & 1) * by, oz = ((r >> 2) & 1) * bz;
-        for (int t = 0; t < g.T; ++t)
-          for (int z = oz; z < oz + bz; ++z)
-            for (int y = oy; y < oy + by; ++y)
-              for (int x = ox; x < ox + bx; ++x)
-                if (((x + y + z + t) & 1) == p) ord[k++] = (int)half_index(g, x, y, z, t);
-      }
-      if (k != (size_t)(p + 1) * g.V4h) return false;
-    }
-    return true;
-  }
-  if (mode == 2) {
-    // eight slabs of consecutive t, one per XCD; inside a slab t runs fastest,
-    // then x, z, y, so the z- and t-neighbours of a site are visited soon after it
-    if (g.T % 8) return false;
-    const int st = g.T / 8;
-    for (int p = 0; p < 2; ++p) {
-      size_t k = (size_t)p * g.V4h;
-      for (int slab = 0; slab < 8; ++slab)
-        for (int y = 0; y < g.Y; ++y)
-          for (int z = 0; z < g.Z; ++z)
-            for (int x = 0; x < g.X; ++x)
-              for (int t = slab * st; t < (slab + 1) * st; ++t)
-                if (((x + y + z + t) & 1) == p) ord[k++] = (int)half_index(g, x, y, z, t);
-      if (k != (size_t)(p + 1) * g.V4h) return false;
-    }
-    return true;
-  }
-  return false;
-}
-
 // ---------------------------------------------------------------------------
 // Coarse-space transfer (blocks, chirality split, block orthonormalisation,
 // restriction, prolongation)
@@ -1202,47 +1114,11 @@ int dwf_set_blocks_ex(dwf_handle h, const int block[4], int parity, int* nblocks
   if (parity != DWF_EVEN && parity != DWF_BOTH) return fail(DWF_EINVAL, "dwf_set_blocks: parity must be DWF_EVEN or DWF_BOTH");
   const bool both = parity == DWF_BOTH;
   const Geom& g = h->g;
-  const int ext[4] = {g.X, g.Y, g.Z, g.T};
-  for (int i = 0; i < 4; ++i)
-    if (block[i] < 1 || ext[i] % block[i])
-      return fail(DWF_EINVAL, "dwf_set_blocks: block extent %d (dim %d) must divide the lattice extent %d", block[i],
-                  i, ext[i]);
-  const int vol = block[0] * block[1] * block[2] * block[3];
-  if (vol % 2) return fail(DWF_EINVAL, "dwf_set_blocks: the block volume must be even");
-  const int nsb = both ? vol : vol / 2;
-  if ((long long)nsb * g.Ls > 1024)
-    return fail(DWF_EINVAL, "dwf_set_blocks: %s per block x Ls = %lld exceeds 1024", both ? "sites" : "even sites",
-                (long long)nsb * g.Ls);
-  if (both && 2 * g.V4h > (1LL << 31) - 1) return fail(DWF_EINVAL, "dwf_set_blocks: lattice too large for DWF_BOTH");
-  const int n[4] = {g.X / block[0], g.Y / block[1], g.Z / block[2], g.T / block[3]};
-  const long long nb = (long long)n[0] * n[1] * n[2] * n[3];
-  std::vector<int> tab((size_t)nb * nsb), nbt((size_t)nb * 8);
-  for (int bt = 0; bt < n[3]; ++bt)
-    for (int bz = 0; bz < n[2]; ++bz)
-      for (int by = 0; by < n[1]; ++by)
-        for (int bx = 0; bx < n[0]; ++bx) {
-          const long long b = ((long long)(bt * n[2] + bz) * n[1] + by) * n[0] + bx;
-          // neighbouring block in hop direction d = 2 mu + (0 forward, 1 backward)
-          const int bc[4] = {bx, by, bz, bt};
-          for (int d = 0; d < 8; ++d) {
-            int c[4] = {bc[0], bc[1], bc[2], bc[3]};
-            const int mu = d / 2;
-            c[mu] = (c[mu] + (d % 2 ? n[mu] - 1 : 1)) % n[mu];
-            nbt[(size_t)b * 8 + d] = (int)(((long long)(c[3] * n[2] + c[2]) * n[1] + c[1]) * n[0] + c[0]);
-          }
-          int j = 0, odd = 0;
-          for (int t = bt * block[3]; t < (bt + 1) * block[3]; ++t)
-            for (int z = bz * block[2]; z < (bz + 1) * block[2]; ++z)
-              for (int y = by * block[1]; y < (by + 1) * block[1]; ++y)
-                for (int x = bx * block[0]; x < (bx + 1) * block[0]; ++x) {
-                  const int par = (x + y + z + t) & 1;
-                  odd += par;
-                  if (par && !both) continue;
-                  if (j == nsb) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
-                  tab[(size_t)b * nsb + j++] = (int)(half_index(g, x, y, z, t) + par * g.V4h);
-                }
-          if (2 * odd != vol) return fail(DWF_EINVAL, "dwf_set_blocks: blocks must hold equal even/odd counts");
-        }
+  std::vector<int> tab, nbt;
+  int nb = 0, nsb = 0;
+  std::string why;
+  if (!plan::build_blocks(g.X, g.Y, g.Z, g.T, g.Ls, block, both, tab, nbt, &nb, &nsb, &why))
+    return fail(DWF_EINVAL, "dwf_set_blocks: %s", why.c_str());
   HIP_TRY(hipMemcpyAsync(h->bsite, tab.data(), tab.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipMemcpyAsync(h->bnbr, nbt.data(), nbt.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1275,7 +1151,7 @@ int dwf_chiral_split(dwf_handle h, const void* in, void* out, int nvec) {
 
 size_t dwf_block_scratch_bytes(dwf_handle h, int nvec) {
   if (!h || h->nb <= 0 || nvec < 1 || nvec > 64) return 0;
-  return 2 * up((size_t)h->nb * nvec * nvec * 16) + ALIGN;
+  return 2 * up((size_t)h->nb * nvec * nvec * 16) + WS_ALIGN;
 }
 
 int dwf_block_orthonormalize(dwf_handle h, void* basis, int nvec, void* scratch, size_t scratch_bytes) {
@@ -1404,7 +1280,7 @@ int dwf_set_order(dwf_handle h, int mode) {
     return DWF_OK;
   }
   std::vector<int> ord;
-  if (!build_order(h->g, mode, ord)) return fail(DWF_EINVAL, "traversal order %d not available for this lattice", mode);
+  if (!plan::build_order(h->g.X, h->g.Y, h->g.Z, h->g.T, mode, ord)) return fail(DWF_EINVAL, "traversal order %d not available for this lattice", mode);
   HIP_TRY(hipMemcpyAsync(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->order_mode = mode;
@@ -1429,11 +1305,58 @@ int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu) {
   return DWF_OK;
 }
 
+// the tuning-cache key of a handle's current configuration
+static int tune_key(dwf_handle h, int nrhs, plan::TuneKey* k) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  k->arch = prop.gcnArchName;
+  for (char& ch : k->arch)
+    if (ch == ' ' || ch == '\t') ch = '_';
+  if (k->arch.empty()) k->arch = "unknown";
+  k->dims[0] = h->g.X;
+  k->dims[1] = h->g.Y;
+  k->dims[2] = h->g.Z;
+  k->dims[3] = h->g.T;
+  k->Ls = h->g.Ls;
+  k->nrhs = nrhs;
+  k->prec = h->prec;
+  k->order = h->order_mode;
+  k->lds_floor = h->lds_floor;
+  k->schur_form = h->schur_form;
+  return DWF_OK;
+}
+
+static void apply_tile(dwf_handle h, int spb, int depth, int rpb) {
+  h->spb = spb;
+  h->depth[h->prec] = depth;
+  h->rpb = rpb;
+  if (h->prec != DWF_F64) h->depth[DWF_F64] = depth;
+}
+
+int dwf_tune_cache_clear(void) {
+  plan::tune_clear();
+  return DWF_OK;
+}
+
 int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb, double* best_ms) {
   if (int r = check_h(h)) return r;
   if (nrhs < 1 || nrhs > h->max_nrhs || reps < 1) return fail(DWF_EINVAL, "dwf_autotune: nrhs in [1, max_nrhs], reps >= 1");
   const int P = h->prec;
   const int Ls = h->g.Ls;
+  plan::TuneKey key;
+  if (int rc = tune_key(h, nrhs, &key)) return rc;
+  const char* cache_file = std::getenv("DWF_TUNE_CACHE");
+  plan::TuneEntry hit;
+  if (plan::tune_lookup(key, &hit, cache_file)) {
+    apply_tile(h, hit.spb, hit.depth, hit.rpb);
+    if (best_spb) *best_spb = hit.spb;
+    if (best_depth) *best_depth = hit.depth;
+    if (best_rpb) *best_rpb = hit.rpb;
+    if (best_ms) *best_ms = hit.ms;
+    return DWF_OK;
+  }
   char* v = h->cheb_a;  // zero field; M_pc^dag M_pc maps it onto itself
   HIP_TRY(blas_zero(h, P, v, nrhs));
   hipEvent_t e0, e1;
@@ -1479,10 +1402,8 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
     h->rpb = old_rpb;
     return fail(DWF_EINVAL, "dwf_autotune: no candidate shape for Ls = %d", Ls);
   }
-  h->spb = bs;
-  h->depth[P] = bd;
-  h->rpb = br;
-  if (P != DWF_F64) h->depth[DWF_F64] = bd;
+  apply_tile(h, bs, bd, br);
+  plan::tune_store(key, plan::TuneEntry{bs, bd, br, bms}, cache_file);
   if (best_spb) *best_spb = bs;
   if (best_depth) *best_depth = bd;
   if (best_rpb) *best_rpb = br;

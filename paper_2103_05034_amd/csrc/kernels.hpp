@@ -2,6 +2,7 @@
 #pragma once
 
 #include "dwf_internal.hpp"
+#include "plan.hpp"
 
 namespace dwf {
 
@@ -41,9 +42,8 @@ hipError_t launch_neighbours(dwf_context* ctx);
 hipError_t launch_pack(dwf_context* ctx, int prec, const void* natural, char* packed, int nrhs, int parity,
                        bool unpack);
 
-// blas.hip -- per-rhs reductions land in ctx->scalars[rhs * NSCAL + slot]
-constexpr int NSCAL = 16;
-constexpr int RED_BLOCKS = 1024;  // partial sums per rhs
+// blas.hip -- per-rhs reductions land in ctx->scalars[rhs * NSCAL + slot] (NSCAL and
+// RED_BLOCKS, the partial sums per rhs, come with the workspace plan)
 enum Slot {
   S_RR = 0,      // |r|^2 (recursive)
   S_RR_OLD = 1,

@@ -44,17 +44,12 @@ int scratch_on_current_device(double** out) {
 extern "C" int dwf_dot_noalloc(const int dims[4], int Ls, int prec, const void* a, const void* b, int nrhs,
                                double* result, void* stream) {
   if (!dims || !a || !b || !result) return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: null pointer");
-  for (int i = 0; i < 4; ++i)
-    if (dims[i] < 2 || (dims[i] & 1))
-      return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: lattice extent %d (dim %d) must be even and >= 2", dims[i], i);
-  if (Ls < 1 || Ls > 128) return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: Ls must be in [1, 128]");
-  if (prec != DWF_F64 && prec != DWF_F32 && prec != DWF_F16S)
-    return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: unknown precision");
+  std::string why;
+  if (!dwf::plan::valid_dims(dims, Ls, prec, 1, 0, &why)) return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: %s", why.c_str());
   if (nrhs < 1 || nrhs > DWF_DOT_NOALLOC_MAX_RHS)
     return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: nrhs %d outside [1, %d] (the size of its fixed scratch array)",
                      nrhs, DWF_DOT_NOALLOC_MAX_RHS);
-  const long long V4 = (long long)dims[0] * dims[1] * dims[2] * dims[3];
-  if (V4 / 2 > (1LL << 31) - 1) return dwf::fail(DWF_EINVAL, "dwf_dot_noalloc: lattice too large");
+  const long long V4 = (long long)dims[0] * dims[1] * dims[2] * dims[3];  // below 2^32 after the check
   double* partials = nullptr;
   if (int rc = scratch_on_current_device(&partials)) return rc;
   // a host-side description of the lattice and the stream: no workspace is carved

@@ -1,0 +1,119 @@
+// Host-side planning behind the entry points: argument checks, the layout of
+// a handle's workspace and the site traversal orders of the hop kernels.
+// Plain C++17 with no HIP dependency, so the same source also builds into a
+// host-only test program under AddressSanitizer and UBSan.
+#pragma once
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "dwf.h"
+
+namespace dwf {
+
+constexpr size_t WS_ALIGN = 256;  // alignment of every carved buffer (and of the workspace)
+constexpr int NSCAL = 16;         // device scalars per rhs
+constexpr int RED_BLOCKS = 1024;  // reduction partial sums per rhs
+constexpr int GS_MAX = 256;       // most vectors one Gram-Schmidt call orthonormalises
+
+// Bytes of one packed 5D spinor (12 complex components) per storage
+// precision: FP64 complex, FP32 complex, 24 FP16 values plus one FP32 scale.
+constexpr size_t SPINOR_BYTES[3] = {192, 96, 52};
+
+namespace plan {
+
+// Checks the lattice and capacity arguments of dwf_create and its sizing
+// calls; on failure fills *why with the reason.
+bool valid_dims(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs, std::string* why);
+
+// The buffers carved out of a handle's workspace, in carving order.
+enum Buffer {
+  B_LINKS64,      // [2][8][9][V4h] complex128
+  B_LINKS32,      // [2][8][9][V4h] complex64 (handles below FP64)
+  B_NBR,          // [2][8][V4h] int
+  B_T,            // odd half field x chunk, handle precision
+  B_U,            // even half field x chunk, handle precision
+  B_CHEB,         // Chebyshev partner set, max(max_nrhs, 2) rhs
+  B_R64,          // FP64 CG vectors (max_cg_rhs > 0)
+  B_P64,
+  B_Q64,
+  B_B64,
+  B_T64,          // FP64 temporaries of low-precision handles
+  B_U64,
+  B_LO_R,         // FP32 CG vectors of low-precision handles
+  B_LO_X,
+  B_LO_P,         // handle-precision search direction and product
+  B_LO_Q,
+  B_ORDER,        // [2][V4h] int
+  B_BSITE,        // [2][V4h] int
+  B_BNBR,         // [8][V4h] int
+  B_HOP_PARTIALS, // [max_cg_rhs][V4h] double
+  B_PARTIALS,     // [chunk][RED_BLOCKS][2] double
+  B_SCALARS,      // [chunk][NSCAL] double
+  B_COEF,         // [4 GS_MAX + 8] double
+  B_COUNT
+};
+
+constexpr size_t ABSENT = (size_t)-1;
+
+struct Workspace {
+  size_t offset[B_COUNT];  // byte offset of each buffer, or ABSENT
+  size_t bytes[B_COUNT];   // bytes asked for (0 when absent)
+  size_t total;            // workspace bytes, a multiple of WS_ALIGN
+  int chunk;               // rhs capacity of the temporaries: max(max_nrhs, max_cg_rhs)
+};
+
+// Layout for arguments that passed valid_dims.  FP64 handles alias their
+// FP64 temporaries to B_T / B_U (B_T64 / B_U64 absent).
+Workspace plan_workspace(const int dims[4], int Ls, int prec, int max_nrhs, int max_cg_rhs);
+
+// Half-lattice index of the site (x, y, z, t): its lexicographic index
+// (x fastest) halved.
+inline long long half_index(int X, int Y, int Z, int x, int y, int z, int t) {
+  return ((long long)x + (long long)X * (y + (long long)Y * (z + (long long)Z * t))) / 2;
+}
+
+// Site traversal order of the hop kernels for each parity, [2][V4h]: mode 1
+// cuts the (x, y, z) box into 2 x 2 x 2 sub-boxes, one per XCD, each streamed
+// with t slowest; mode 2 cuts t into eight slabs, one per XCD, each streamed
+// with t fastest, then x, z, y.  Returns false when the lattice does not admit
+// the mode (mode 0, lexicographic, needs no table).
+bool build_order(int X, int Y, int Z, int T, int mode, std::vector<int>& ord);
+
+// Coarse-space blocks of extents block[4] over the lattice: `sites` gets, per
+// block (numbered x fastest), its sites in lexicographic order (even sites
+// only, as half-lattice indices, unless `both`; with `both`, odd sites as
+// V4h + their half index), `nbrs` the neighbouring block in each of the 8 hop
+// directions (2 mu forward, 2 mu + 1 backward).  Returns false with *why set
+// when the extents do not tile the lattice into blocks of equal even and odd
+// counts holding at most 1024 5D sites.
+bool build_blocks(int X, int Y, int Z, int T, int Ls, const int block[4], bool both, std::vector<int>& sites,
+                  std::vector<int>& nbrs, int* nblocks, int* sites_per_block, std::string* why);
+
+// Launch shapes found by the autotuner, kept per (GPU architecture, lattice,
+// Ls, rhs count, precision, traversal order, occupancy cap, Schur form) for
+// the life of the process and, when a file path is given, in that file (one
+// entry per line, appended as found; lines that do not parse are skipped).
+struct TuneKey {
+  std::string arch;  // the device's architecture name, without spaces
+  int dims[4];
+  int Ls, nrhs, prec, order, lds_floor, schur_form;
+};
+struct TuneEntry {
+  int spb, depth, rpb;
+  double ms;  // time per M_pc^dag M_pc measured when the shape was tuned
+};
+std::string format_tune_line(const TuneKey& k, const TuneEntry& e);
+bool parse_tune_line(const std::string& line, TuneKey* k, TuneEntry* e);
+// Looks the key up in the process cache, first loading the file at `path`
+// (null or empty: none) if it has not been read yet.
+bool tune_lookup(const TuneKey& k, TuneEntry* e, const char* path);
+// Records an entry in the process cache and appends it to the file at `path`.
+void tune_store(const TuneKey& k, const TuneEntry& e, const char* path);
+// Empties the process cache; the file is left as it is and read again on the
+// next lookup.
+void tune_clear();
+
+}  // namespace plan
+}  // namespace dwf

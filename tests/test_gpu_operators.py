@@ -220,3 +220,47 @@ def test_cg_batched_with_rhs_per_block():
         ref = krylov.cg(lambda v: L.mpcdagmpc(U, v, M5, MF), b[k], tol=1e-10)
         assert abs(iters[k] - ref.iterations) <= 3 and res[k] < 1.5e-10
         assert rel(xg[k], ref.x) < 1e-6
+
+
+def test_autotune_cache(tmp_path, monkeypatch):
+    """dwf_autotune keeps the shape it found per (architecture, lattice, Ls, nrhs,
+    precision, order, occupancy cap, Schur form): a second handle of the same
+    configuration gets it without timing (the reported time is the tuned one), a
+    different traversal order is tuned afresh, and with DWF_TUNE_CACHE set the shapes
+    survive a cleared process cache through the file.  The cached shape computes
+    M_pc^dag M_pc bitwise as the tuned one."""
+    import torch
+
+    import paper_2103_05034_amd as dwf
+
+    dims, Ls = (8, 4, 4, 8), 6
+    monkeypatch.delenv("DWF_TUNE_CACHE", raising=False)
+    dwf.tune_cache_clear()
+    op1, U = make_operator(dims, Ls, seed=21, max_nrhs=2)
+    r1 = op1.autotune(2, 2)
+    op2, _ = make_operator(dims, Ls, seed=21, max_nrhs=2)
+    r2 = op2.autotune(2, 2)
+    assert r1 == r2 and op1.tile == op2.tile
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 2, seed=22)])
+    a, b = op1.new_field(2), op2.new_field(2)
+    op1.mpcdagmpc(pack(op1, nat, EVEN), a, 2)
+    op2.mpcdagmpc(pack(op2, nat, EVEN), b, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    op2.set_order(1)
+    spb, depth, ms = op2.autotune(2, 2)
+    assert (spb, depth) != (0, 0) and ms > 0
+    # through the file
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("DWF_TUNE_CACHE", str(path))
+    dwf.tune_cache_clear()
+    op3, _ = make_operator(dims, Ls, seed=21, max_nrhs=2)
+    r3 = op3.autotune(1, 2)
+    assert path.exists() and len(path.read_text().splitlines()) == 1
+    dwf.tune_cache_clear()
+    op4, _ = make_operator(dims, Ls, seed=21, max_nrhs=2)
+    assert op4.autotune(1, 2) == r3
+    assert len(path.read_text().splitlines()) == 1  # a hit appends nothing
+    dwf.tune_cache_clear()
+    for op in (op1, op2, op3, op4):
+        op.close()
