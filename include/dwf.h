@@ -499,8 +499,14 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
 int dwf_tune_cache_clear(void);
 
 /* Library plumbing (no passage of the paper defines this call).
- * Average duration (ms) of the hopping-term kernels since the last reset, as
- * measured by HIP events on the handle's stream when timing is enabled. */
+ * Timing of the hopping-term kernels by HIP events on the handle's stream.
+ * dwf_enable_timing: enable = 0 stops it; 1 times every hop launch; n > 1
+ * times every n-th hop launch (a stride coprime with the launches of one
+ * solver iteration -- four per CG iteration -- samples every kind evenly and
+ * puts fewer event records between the kernels); every call resets the sums.
+ * DWF_EINVAL for enable < 0.  dwf_kernel_time reports the summed duration
+ * (ms) and the number of timed launches since the last reset (it synchronises
+ * the stream). */
 int dwf_enable_timing(dwf_handle h, int enable);
 int dwf_kernel_time(dwf_handle h, double* ms_total, long long* launches);
 

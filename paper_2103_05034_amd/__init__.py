@@ -611,8 +611,9 @@ class Operator:
         self._progress_cb = PROGRESS_FN(tramp)  # kept alive while registered
         _check(self.lib.dwf_set_progress(self.h, self._progress_cb, None, int(every)))
 
-    def enable_timing(self, on=True):
-        _check(self.lib.dwf_enable_timing(self.h, int(on)))
+    def enable_timing(self, on=True, stride=1):
+        """Time hop launches with HIP events (every `stride`-th one when stride > 1)."""
+        _check(self.lib.dwf_enable_timing(self.h, (int(stride) if stride > 1 else 1) if on else 0))
 
     def kernel_time(self):
         ms = ctypes.c_double()

@@ -83,6 +83,7 @@ void carve(dwf_context* d, const plan::Workspace& w, char* base) {
   d->partial_count = (size_t)w.chunk;
   d->partials = reinterpret_cast<double*>(at(plan::B_PARTIALS));
   d->scalars = reinterpret_cast<double*>(at(plan::B_SCALARS));
+  d->counters = reinterpret_cast<unsigned*>(at(plan::B_COUNTERS));
   d->coef = reinterpret_cast<double*>(at(plan::B_COEF));
 }
 
@@ -143,7 +144,7 @@ hipError_t mpc_chunk(dwf_context* c, int prec, const char* in, char* out, char* 
 hipError_t mdagm_pap(dwf_context* c, int prec, const char* p, char* q, char* t, char* u, int n) {
   hipError_t e = mpc_chunk(c, prec, p, u, t, n, 0, c->hop_partials);
   if (e != hipSuccess) return e;
-  e = reduce_partials(c, c->hop_partials, hop_blocks(c), n, S_PAP);
+  e = reduce_sites(c, c->hop_partials, (int)c->g.V4h, n, S_PAP, 0, 0.0);
   if (e != hipSuccess) return e;
   return mpc_chunk(c, prec, u, q, t, n, 1);
 }
@@ -154,7 +155,7 @@ hipError_t mdagm_pap(dwf_context* c, int prec, const char* p, char* q, char* t, 
 hipError_t cg_step_f64(dwf_context* c, const char* p, char* r, char* t, char* u, int n, double tol2) {
   hipError_t e = mpc_chunk(c, DWF_F64, p, u, t, n, 0, c->hop_partials);
   if (e != hipSuccess) return e;
-  e = reduce_partials_step(c, c->hop_partials, hop_blocks(c), n, S_PAP, 1, tol2);  // p.Ap, alpha
+  e = reduce_sites(c, c->hop_partials, (int)c->g.V4h, n, S_PAP, 1, tol2);  // p.Ap, alpha
   if (e != hipSuccess) return e;
   HopArgs a{};
   a.in = u;
@@ -171,7 +172,7 @@ hipError_t cg_step_f64(dwf_context* c, const char* p, char* r, char* t, char* u,
   b.scal = c->scalars;
   e = launch_hop(c, DWF_F64, b, DWF_EVEN, 1, EPI_CGR, n);
   if (e != hipSuccess) return e;
-  return reduce_partials_step(c, c->hop_partials, hop_blocks(c), n, S_RR, 2, tol2);  // |r|^2, beta, convergence
+  return reduce_sites(c, c->hop_partials, (int)c->g.V4h, n, S_RR, 2, tol2);  // |r|^2, beta, convergence
 }
 
 hipError_t mdagm_chunk(dwf_context* c, int prec, const char* in, char* out, char* t, char* u, int n) {
@@ -218,7 +219,10 @@ int read_scalars(dwf_context* c, int nrhs, std::vector<double>& out) {
 // kernel timing (used by launch_hop)
 namespace dwf {
 void timing_begin(dwf_context* ctx) {
+  ctx->ev_open = false;
   if (!ctx->timing) return;
+  if (ctx->ev_seq++ % ctx->ev_stride != 0) return;  // a launch between the sampled ones
+  ctx->ev_open = true;
   if (ctx->ev_used == ctx->ev_pool.size()) {
     // drain
     (void)hipStreamSynchronize(ctx->stream);
@@ -233,7 +237,8 @@ void timing_begin(dwf_context* ctx) {
   (void)hipEventRecord(ctx->ev_pool[ctx->ev_used].a, ctx->stream);
 }
 void timing_end(dwf_context* ctx) {
-  if (!ctx->timing) return;
+  if (!ctx->timing || !ctx->ev_open) return;
+  ctx->ev_open = false;
   (void)hipEventRecord(ctx->ev_pool[ctx->ev_used].b, ctx->stream);
   ctx->ev_used++;
 }
@@ -297,9 +302,14 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   c->ev_used = 0;
   c->ev_ms = 0;
   c->ev_launches = 0;
+  c->ev_stride = 1;
+  c->ev_seq = 0;
+  c->ev_open = false;
   hipError_t e = launch_pack_links(c, U);
   if (e == hipSuccess) e = launch_neighbours(c);
   if (e == hipSuccess) e = hipMemsetAsync(c->scalars, 0, (size_t)(c->partial_count * NSCAL) * sizeof(double), c->stream);
+  // the per-site reductions' completion counts start at zero and are reset by the kernel itself
+  if (e == hipSuccess) e = hipMemsetAsync(c->counters, 0, c->partial_count * sizeof(unsigned), c->stream);
   if (e == hipSuccess && max_cg_rhs > 0 && prec != DWF_F64) {
     e = hipHostMalloc(reinterpret_cast<void**>(&c->pin_scal), (size_t)2 * max_cg_rhs * NSCAL * sizeof(double),
                       hipHostMallocDefault);
@@ -573,7 +583,7 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
   for (int rr = 0; rr < nrhs; ++rr) best[rr] = sc[(size_t)rr * NSCAL + S_RR];
   std::vector<int> idle(nrhs, 0);
   std::vector<char> cycle(nrhs, 0);
-  const int nb = hop_blocks(h);
+  const int nb = (int)h->g.V4h;  // per-site partial sums of the fused passes
   const size_t slot_doubles = (size_t)nrhs * NSCAL;
   bool stagnant = false, stopped = false;
   int it = 0, last = 0;
@@ -600,7 +610,7 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
       m.alpha = -0.25;
       m.partial = h->hop_partials;
       HIP_TRY(launch_hop_ex(h, DWF_F32, DWF_F32, P, m, DWF_EVEN, 0, EPI_M5, nrhs));
-      HIP_TRY(reduce_partials_step(h, h->hop_partials, nb, nrhs, S_PAP, 1, tol2));  // p.Ap, alpha
+      HIP_TRY(reduce_sites(h, h->hop_partials, nb, nrhs, S_PAP, 1, tol2));  // p.Ap, alpha
       HopArgs c{};
       c.in = u32;
       c.out = t32;
@@ -614,7 +624,7 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
       d.partial = h->hop_partials;
       d.scal = h->scalars;
       HIP_TRY(launch_hop(h, DWF_F32, d, DWF_EVEN, 1, EPI_CGR, nrhs));
-      HIP_TRY(reduce_partials_step(h, h->hop_partials, nb, nrhs, S_RR, 3, tol2));  // |r|^2, beta, max |r|^2
+      HIP_TRY(reduce_sites(h, h->hop_partials, nb, nrhs, S_RR, 3, tol2));  // |r|^2, beta, max |r|^2
       HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
       new_slot = prev_slot == 0 ? 1 : 0;
       HIP_TRY(hipMemcpyAsync(h->pin_scal + new_slot * slot_doubles, h->scalars, slot_doubles * sizeof(double),
@@ -1413,6 +1423,7 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
 
 int dwf_enable_timing(dwf_handle h, int enable) {
   if (int r = check_h(h)) return r;
+  if (enable < 0) return fail(DWF_EINVAL, "dwf_enable_timing: enable must be >= 0");
   if (enable && h->ev_pool.empty()) {
     h->ev_pool.resize(4096);
     for (auto& p : h->ev_pool) {
@@ -1421,6 +1432,9 @@ int dwf_enable_timing(dwf_handle h, int enable) {
     }
   }
   h->timing = enable != 0;
+  h->ev_stride = enable > 1 ? enable : 1;
+  h->ev_seq = 0;
+  h->ev_open = false;
   h->ev_used = 0;
   h->ev_ms = 0;
   h->ev_launches = 0;

@@ -60,29 +60,6 @@ __global__ void finalize_kernel(const double* __restrict__ partials, double* __r
   }
 }
 
-// out[rhs * ostride] = sum_k partials[rhs * count + k].  Each thread keeps
-// eight independent sums (k = tid + j*BS mod 8*BS), so eight loads are in
-// flight instead of one dependent chain; the order is fixed by count alone.
-__device__ __forceinline__ double partial_total(const double* __restrict__ p, int count) {  // valid on thread 0
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int k = threadIdx.x;
-  for (; k + 7 * BS < count; k += 8 * BS) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) acc[j] += p[k + j * BS];
-  }
-  for (int j = 0; k < count; k += BS, ++j) acc[j] += p[k];
-  double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])), b = 0;
-  block_reduce2(a, b);
-  return a;
-}
-
-__global__ void sum_partials_kernel(const double* __restrict__ partials, int count, double* __restrict__ out,
-                                    int ostride) {
-  const int rhs = blockIdx.x;
-  const double a = partial_total(partials + (size_t)rhs * count, count);
-  if (threadIdx.x == 0) out[(size_t)rhs * ostride] = a;
-}
-
 // <a, b> per rhs; rhs stride given per argument (GS uses Q_k as "rhs" of a
 // batch against one fixed vector b with b_stride = 0)
 template <int PA, int PB>
@@ -350,23 +327,55 @@ __global__ void scal_beta_kernel(double* scal, int nrhs) {
   if (r < nrhs) beta_step(scal + r * NSCAL);
 }
 
-// The reduction of per-workgroup partials into slot, then on the same thread the
-// CG step that needs it: mode 1 alpha (slot = S_PAP), mode 2 beta and the
-// convergence step (slot = S_RR).  One launch instead of two or three.
-__global__ void sum_partials_step_kernel(const double* __restrict__ partials, int count, double* __restrict__ scal,
-                                         int slot, int mode, double tol2) {
-  const int rhs = blockIdx.x;
-  const double a = partial_total(partials + (size_t)rhs * count, count);
+// Per-site sums (one FP64 value per half-lattice site and rhs, at the site's
+// index) reduced into slot, then on the same thread the CG step that needs the
+// total: mode 0 none, 1 alpha (slot = S_PAP), 2 beta and the convergence step
+// (slot = S_RR), 3 as 2 without stopping a rhs, plus the largest |r|^2 since
+// the last reliable update.  Workgroup b of a rhs adds the b-th of
+// SITE_RED_BLOCKS equal index ranges (four sums per thread, then the
+// workgroup); the last workgroup of the rhs to finish -- found by an atomic
+// count that it resets for the next launch -- adds the range sums in index
+// order.  The order is fixed by the lattice alone, so the result does not
+// depend on which workgroup finishes last or on the hop kernels' launch shape.
+constexpr int SITE_RED_BLOCKS = 64;
+
+__global__ void __launch_bounds__(BS) sum_sites_kernel(const double* __restrict__ partials, int count,
+                                                       double* __restrict__ ranges, unsigned* __restrict__ counters,
+                                                       double* __restrict__ scal, int slot, int mode, double tol2) {
+  const int rhs = blockIdx.y;
+  const int b = blockIdx.x;
+  const long long per = ((long long)count + SITE_RED_BLOCKS - 1) / SITE_RED_BLOCKS;
+  const long long k0 = (long long)b * per;
+  const long long k1 = k0 + per < count ? k0 + per : count;
+  const double* q = partials + (size_t)rhs * count;
+  double acc[4] = {0, 0, 0, 0};
+  int j = 0;
+  for (long long k = k0 + threadIdx.x; k < k1; k += BS, j = (j + 1) & 3) acc[j] += q[k];
+  double a = (acc[0] + acc[1]) + (acc[2] + acc[3]), unused = 0;
+  block_reduce2(a, unused);
+  __shared__ int last;
+  unsigned long long* rbits = reinterpret_cast<unsigned long long*>(ranges) + (size_t)rhs * SITE_RED_BLOCKS;
   if (threadIdx.x == 0) {
-    double* s = scal + (size_t)rhs * NSCAL;
-    s[slot] = a;
-    if (mode == 1) {
-      alpha_step(s);
-    } else {
-      beta_step(s);
-      converge_step(s, tol2, 1, mode == 2);
-      if (mode == 3 && s[S_ACTIVE] != 0.0) s[S_RRMAX] = fmax(s[S_RRMAX], s[S_RR]);
-    }
+    __hip_atomic_store(rbits + b, __builtin_bit_cast(unsigned long long, a), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    // release of this range sum; acquire of the others' for the last workgroup
+    const unsigned prev = __hip_atomic_fetch_add(counters + rhs, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == (unsigned)(SITE_RED_BLOCKS - 1);
+  }
+  __syncthreads();
+  if (!last || threadIdx.x != 0) return;
+  double t = 0;
+  for (int i = 0; i < SITE_RED_BLOCKS; ++i)
+    t += __builtin_bit_cast(double, __hip_atomic_load(rbits + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  __hip_atomic_store(counters + rhs, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  double* s = scal + (size_t)rhs * NSCAL;
+  s[slot] = t;
+  if (mode == 1) {
+    alpha_step(s);
+  } else if (mode >= 2) {
+    beta_step(s);
+    converge_step(s, tol2, 1, mode == 2);
+    if (mode == 3 && s[S_ACTIVE] != 0.0) s[S_RRMAX] = fmax(s[S_RRMAX], s[S_RR]);
   }
 }
 
@@ -446,16 +455,12 @@ static void dot_la(dwf_context* ctx, int pb, VecGeom g, const char* a, size_t sa
   }
 }
 
-hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot) {
-  hipLaunchKernelGGL(sum_partials_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, partials, count, ctx->scalars + slot,
-                     NSCAL);
-  return hipGetLastError();
-}
-
-hipError_t reduce_partials_step(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
-                                double tol2) {
-  hipLaunchKernelGGL(sum_partials_step_kernel, dim3(nrhs), dim3(BS), 0, ctx->stream, partials, count, ctx->scalars,
-                     slot, mode, tol2);
+hipError_t reduce_sites(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
+                        double tol2) {
+  if ((size_t)nrhs * SITE_RED_BLOCKS > ctx->partial_count * RED_BLOCKS * 2 || nrhs > (int)ctx->partial_count)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sum_sites_kernel, dim3(SITE_RED_BLOCKS, nrhs), dim3(BS), 0, ctx->stream, partials, count,
+                     ctx->partials, ctx->counters, ctx->scalars, slot, mode, tol2);
   return hipGetLastError();
 }
 

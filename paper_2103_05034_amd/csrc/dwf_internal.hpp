@@ -103,6 +103,30 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
   }
 }
 
+// One butterfly step on a double with a DPP lane swizzle (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_swap(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of v over each group of `width` consecutive lanes (width a power of two
+// up to 64), returned in every lane of the group; a fixed order for a given
+// width.  Within a row of 16 lanes the partners come from DPP swizzles (row
+// mirror, half-row mirror, then the quad permutations of lane xor 2 and xor
+// 1), which pair every lane with one of the other half at each step; wider
+// groups first add across rows with shuffles.
+__device__ __forceinline__ double group_sum(double v, int width) {
+  for (int off = width >> 1; off >= 16; off >>= 1) v += __shfl_xor(v, off, width);
+  if (width >= 16) v += dpp_swap<0x140>(v);  // row_mirror: lane i <-> 15 - i
+  if (width >= 8) v += dpp_swap<0x141>(v);   // row_half_mirror: lane i <-> 7 - i within 8
+  if (width >= 4) v += dpp_swap<0x4e>(v);    // quad_perm [2, 3, 0, 1]
+  if (width >= 2) v += dpp_swap<0xb1>(v);    // quad_perm [1, 0, 3, 2]
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Field storage.  A packed half field of one right-hand side holds the 12
 // spin-colour components (c = 3 spin + colour) of every (site h, slice s),
@@ -390,7 +414,7 @@ struct HopArgs {
   double alpha, beta, ca, cb, cc, cw;
   double d, inv_d, corner;  // 5 - M5, 1/d, -mf / (1 + mf d^{-Ls})
   double mf;
-  double* partial;    // optional per-workgroup FP64 partial sums (reductions)
+  double* partial;    // optional per-site FP64 |out|^2 sums, [rhs][V4h] (reductions)
   const int* order;   // optional traversal order of the out parity: processing index -> site h
   int lds_floor;      // minimum dynamic LDS of the launch (occupancy cap), bytes
   int nrhs;           // right-hand sides of the launch
@@ -437,13 +461,14 @@ struct dwf_context {
   char* cheb_a;      // Chebyshev partner set, handle precision, max(max_nrhs, 2)
   double* partials;  // reduction partials
   double* scalars;   // device scalars (per rhs)
+  unsigned* counters;  // per-rhs completion counts of the per-site reductions (zero between launches)
   double* coef;      // Gram-Schmidt projection coefficients
   size_t partial_count;
   // launch shape of the hop kernels (sites per workgroup; load-pipeline depth per precision)
   int spb;
   int depth[3];
   int rpb;
-  double* hop_partials;  // per-workgroup |M_pc p|^2 sums of CG, [max_cg_rhs][V4h]
+  double* hop_partials;  // per-site |M_pc p|^2 (or |r|^2) sums of CG, [max_cg_rhs][V4h]
   int* order;            // site traversal order per out parity, [2][V4h] (device)
   int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
   int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
@@ -471,4 +496,7 @@ struct dwf_context {
   size_t ev_used;
   double ev_ms;
   long long ev_launches;
+  int ev_stride;       // time every ev_stride-th hop launch (1: all)
+  long long ev_seq;    // hop launches seen since timing was enabled
+  bool ev_open;        // the current launch is being timed
 };

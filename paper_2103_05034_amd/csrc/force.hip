@@ -35,30 +35,6 @@ __device__ __forceinline__ void term_outer(const cplx<double> y[12], const cplx<
     }
 }
 
-// One butterfly step on a double with a DPP lane swizzle (two 32-bit moves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_swap(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Sum of v over each group of `width` consecutive lanes (width a power of two
-// up to 64), returned in every lane of the group; a fixed order for a given
-// width.  Within a row of 16 lanes the partners come from DPP swizzles (row
-// mirror, half-row mirror, then the quad permutations of lane xor 2 and xor
-// 1), which pair every lane with one of the other half at each step; wider
-// groups first add across rows with shuffles.
-__device__ __forceinline__ double group_sum(double v, int width) {
-  for (int off = width >> 1; off >= 16; off >>= 1) v += __shfl_xor(v, off, width);
-  if (width >= 16) v += dpp_swap<0x140>(v);  // row_mirror: lane i <-> 15 - i
-  if (width >= 8) v += dpp_swap<0x141>(v);   // row_half_mirror: lane i <-> 7 - i within 8
-  if (width >= 4) v += dpp_swap<0x4e>(v);    // quad_perm [2, 3, 0, 1]
-  if (width >= 2) v += dpp_swap<0xb1>(v);    // quad_perm [1, 0, 3, 2]
-  return v;
-}
-
 struct ForceArgs {
   const char* y[2];  // per-term passes: own spinor of the term, on even and odd sites (one pass: a)
   const char* z[2];  // per-term passes: neighbour spinor of the term (one pass: b)

@@ -248,13 +248,6 @@ __device__ __forceinline__ void m5inv_columns(cplx<R>* buf, int spb, int Ls, lon
   }
 }
 
-// sum over the workgroup of v (FP64), valid on thread 0; scratch holds 8 doubles
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
-  double unused = 0;
-  block_sum2(v, unused, scratch);
-  return v;
-}
-
 // MULTI: the workgroup loops over rpb right-hand sides (links staged once);
 // without it the body runs once, which keeps the loop-carried addresses out of
 // the register budget of the common single-rhs launches.
@@ -467,15 +460,32 @@ hop_kernel(HopArgs a) {
           Store<PREC>::store_nt(out, V4h, Ls, h, s, v);
       }
     }
-    if (a.partial != nullptr) {  // |out|^2 of this workgroup (FP64): p.Ap = |M_pc p|^2, or CG's |r|^2
+    if (a.partial != nullptr) {
+      // |out|^2 per site (FP64): p.Ap = |M_pc p|^2, or CG's |r|^2.  The s-slices of a
+      // site are added in a fixed order (an in-wave butterfly for Ls a power of two, in
+      // order through LDS otherwise) and the sum is stored at the site's own index, so
+      // the totals do not depend on the launch shape or the traversal order.
       if (EPI != EPI_LIN) __syncthreads();  // scratch still holds x or the M5D^{-1} columns
       double n2 = 0;
       if (valid) {
 #pragma unroll
         for (int c = 0; c < 12; ++c) n2 += (double)v[c].re * v[c].re + (double)v[c].im * v[c].im;
       }
-      const double tot = block_sum(n2, reinterpret_cast<double*>(scratch));
-      if (tid == 0) a.partial[(size_t)rhs * a.nblocks + logical] = tot;
+      if ((Ls & (Ls - 1)) == 0 && Ls <= 64) {
+        // a site's lanes are one aligned group of Ls lanes inside a wave
+        const double tot = group_sum(n2, Ls);
+        if (valid && s == 0) a.partial[(size_t)rhs * V4h + h] = tot;
+      } else {
+        double* red = reinterpret_cast<double*>(scratch);
+        red[tid] = n2;
+        __syncthreads();
+        if (valid && s == 0) {
+          double tot = 0;
+          for (int k = 0; k < Ls; ++k) tot += red[sl * Ls + k];
+          a.partial[(size_t)rhs * V4h + h] = tot;
+        }
+        __syncthreads();  // the next rhs of the workgroup reuses scratch
+      }
     }
   }
 }
@@ -660,12 +670,6 @@ hipError_t launch_hop_ex(dwf_context* ctx, int prec, int pin, int px, HopArgs a,
 
 hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int dag, int epi, int nrhs) {
   return launch_hop_ex(ctx, prec, prec, prec, a, out_parity, dag, epi, nrhs);
-}
-
-int hop_blocks(const dwf_context* ctx) {
-  HopArgs a{};
-  fill_shape(ctx, a);
-  return a.nblocks;
 }
 
 template <int PREC, bool DAG, bool INV>

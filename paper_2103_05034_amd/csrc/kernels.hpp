@@ -33,7 +33,6 @@ hipError_t launch_hop(dwf_context* ctx, int prec, HopArgs a, int out_parity, int
 // out (EPI_M5)
 hipError_t launch_hop_ex(dwf_context* ctx, int prec, int pin, int px, HopArgs a, int out_parity, int dag, int epi,
                          int nrhs);
-int hop_blocks(const dwf_context* ctx);  // workgroups per rhs of a hop launch
 hipError_t launch_site5(dwf_context* ctx, int prec, const char* in, char* out, int dag, int inv, int nrhs);
 
 // setup.hip
@@ -60,14 +59,14 @@ enum Slot {
   S_ITERS = 12,  // iterations done while active
 };
 
-// out[rhs * NSCAL + slot] = sum_k partials[rhs * count + k] (fixed order)
-hipError_t reduce_partials(dwf_context* ctx, const double* partials, int count, int nrhs, int slot);
-// the same, then on the same thread mode 1: alpha (slot S_PAP); mode 2: beta and the
-// convergence step with tol2 (slot S_RR) -- scal_alpha / scal_beta + scal_converge fused;
-// mode 3: beta, the iteration count and S_RRMAX = max(S_RRMAX, |r|^2), without retiring a rhs
-// (the low-precision CG retires one only on its FP64 true residual)
-hipError_t reduce_partials_step(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
-                                double tol2);
+// scal[rhs * NSCAL + slot] = sum_k partials[rhs * count + k] over per-site values (a
+// fixed order set by count), then on one thread mode 0: nothing more; mode 1: alpha (slot
+// S_PAP); mode 2: beta and the convergence step with tol2 (slot S_RR) -- scal_alpha /
+// scal_beta + scal_converge fused; mode 3: beta, the iteration count and S_RRMAX =
+// max(S_RRMAX, |r|^2), without retiring a rhs (the low-precision CG retires one only on its
+// FP64 true residual).  Uses ctx->partials and ctx->counters as scratch.
+hipError_t reduce_sites(dwf_context* ctx, const double* partials, int count, int nrhs, int slot, int mode,
+                        double tol2);
 // result[rhs] = <a, b> (complex, FP64 accumulation) into scalars[rhs*NSCAL + slot (+1 imag)]
 hipError_t blas_dot(dwf_context* ctx, int pa, const char* a, int pb, const char* b, int nrhs, int slot,
                     bool imag);

@@ -102,6 +102,7 @@ Workspace plan_workspace(const int dims[4], int Ls, int prec, int max_nrhs, int 
   take(B_PARTIALS, (size_t)chunk * RED_BLOCKS * 2 * sizeof(double));
   take(B_SCALARS, (size_t)chunk * NSCAL * sizeof(double));
   take(B_COEF, (size_t)(4 * GS_MAX + 8) * sizeof(double));
+  take(B_COUNTERS, (size_t)chunk * sizeof(unsigned));
   w.total = off;
   return w;
 }

@@ -52,6 +52,7 @@ enum Buffer {
   B_PARTIALS,     // [chunk][RED_BLOCKS][2] double
   B_SCALARS,      // [chunk][NSCAL] double
   B_COEF,         // [4 GS_MAX + 8] double
+  B_COUNTERS,     // [chunk] unsigned: completion counts of the per-site reductions
   B_COUNT
 };
 

@@ -69,7 +69,8 @@ static void check_workspace(const int dims[4], int Ls, int prec, int max_nrhs, i
   // presence
   const bool cg = max_cg_rhs > 0, low = prec != DWF_F64;
   const bool want[plan::B_COUNT] = {true, low, true, true, true, true, cg, cg, cg, cg, cg && low, cg && low,
-                                    cg && low, cg && low, cg && low, cg && low, true, true, true, cg, true, true, true};
+                                    cg && low, cg && low, cg && low, cg && low, true, true, true, cg, true, true, true,
+                                    true};
   // least sizes the kernels rely on
   size_t need[plan::B_COUNT] = {};
   need[plan::B_LINKS64] = 2 * 8 * 9 * V4h * 16;
@@ -87,6 +88,7 @@ static void check_workspace(const int dims[4], int Ls, int prec, int max_nrhs, i
   need[plan::B_PARTIALS] = (size_t)chunk * RED_BLOCKS * 2 * sizeof(double);
   need[plan::B_SCALARS] = (size_t)chunk * NSCAL * sizeof(double);
   need[plan::B_COEF] = (4 * GS_MAX + 8) * sizeof(double);
+  need[plan::B_COUNTERS] = (size_t)chunk * sizeof(unsigned);
   std::vector<std::pair<size_t, size_t>> spans;
   for (int b = 0; b < plan::B_COUNT; ++b) {
     const bool present = w.offset[b] != plan::ABSENT;

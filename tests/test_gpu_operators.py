@@ -264,3 +264,33 @@ def test_autotune_cache(tmp_path, monkeypatch):
     dwf.tune_cache_clear()
     for op in (op1, op2, op3, op4):
         op.close()
+
+
+def test_hop_timing_counts_and_sampling():
+    """dwf_enable_timing: 1 times every hop launch (four per M_pc^dag M_pc), n > 1 every
+    n-th one; the sums reset on every enable call; timing changes no result."""
+    import torch
+
+    dims, Ls = (4, 4, 4, 8), 4
+    op, _ = make_operator(dims, Ls, seed=25)
+    nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 1, seed=26)])
+    v = pack(op, nat, EVEN)
+    ref, w = op.new_field(1), op.new_field(1)
+    op.mpcdagmpc(v, ref, 1)
+    op.enable_timing(True)
+    for _ in range(4):
+        op.mpcdagmpc(v, w, 1)
+    ms, n = op.kernel_time()
+    assert n == 16 and ms > 0
+    op.enable_timing(True, stride=5)  # launches 0, 5, 10 and 15 of the next sixteen
+    for _ in range(4):
+        op.mpcdagmpc(v, w, 1)
+    ms5, n5 = op.kernel_time()
+    assert n5 == 4 and ms5 > 0
+    op.enable_timing(False)
+    torch.cuda.synchronize()
+    assert torch.equal(w, ref)
+    import paper_2103_05034_amd as dwf
+
+    with pytest.raises(dwf.DWFError):
+        dwf._check(op.lib.dwf_enable_timing(op.h, -1))

@@ -267,3 +267,32 @@ def test_filter_warns_when_its_top_is_below_the_measured_lambda_max():
         op.chebyshev_filter(pack(op, x, EVEN), 1, 3, 0.1, 1.01 * lam)
         op.update_links(dev_tensor(U))  # the operator may have changed: the estimate is dropped
         op.chebyshev_filter(pack(op, x, EVEN), 1, 3, 0.1, low)
+
+
+@pytest.mark.parametrize("prec", [F64, F32, F16S])
+def test_cg_independent_of_launch_shape(prec):
+    """CG's reductions are sums per site (over s in order) added in site order, so the
+    whole solve -- iteration counts and the solution, bit for bit -- is the same for
+    every launch shape (sites per workgroup, pipeline depth, rhs per workgroup) and
+    traversal order."""
+    import torch
+
+    dims, Ls = (8, 4, 4, 8), 6
+    op, U = make_operator(dims, Ls, seed=0, prec=prec, max_nrhs=2, max_cg_rhs=2)
+    op64, _ = make_operator(dims, Ls, seed=0, prec=F64)
+    b_dev = pack(op64, even_fields(dims, Ls, 2, seed=7), EVEN)
+    ref = None
+    for order in (0, 1, 2):
+        op.set_order(order)
+        for spb, depth, rpb in ((4, 2, 1), (8, 3, 1), (16, 3, 2), (42, 1, 1)):
+            op.set_tile(spb, depth, rpb)
+            x = op.new_field(2, prec=F64)
+            code, iters, res = op.cg(b_dev, x, 2, tol=1e-10, maxiter=20000)
+            torch.cuda.synchronize()
+            assert code == 0 and max(res) < 1.5e-10
+            if ref is None:
+                ref = (iters, res, x.clone())
+            else:
+                assert iters == ref[0], (order, spb, depth, rpb)
+                assert res == ref[1]
+                assert torch.equal(x, ref[2]), (order, spb, depth, rpb)
