@@ -363,10 +363,18 @@ __global__ void __launch_bounds__(BS) sum_sites_kernel(const double* __restrict_
     last = prev == (unsigned)(SITE_RED_BLOCKS - 1);
   }
   __syncthreads();
-  if (!last || threadIdx.x != 0) return;
+  if (!last) return;
+  // the last workgroup: one load per range (in parallel), then the sum in index order
+  __shared__ double rs[SITE_RED_BLOCKS];
+  static_assert(SITE_RED_BLOCKS <= BS, "one range per thread of the last workgroup");
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // every loading wave sees the released sums
+  if (threadIdx.x < SITE_RED_BLOCKS)
+    rs[threadIdx.x] = __builtin_bit_cast(
+        double, __hip_atomic_load(rbits + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  __syncthreads();
+  if (threadIdx.x != 0) return;
   double t = 0;
-  for (int i = 0; i < SITE_RED_BLOCKS; ++i)
-    t += __builtin_bit_cast(double, __hip_atomic_load(rbits + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  for (int i = 0; i < SITE_RED_BLOCKS; ++i) t += rs[i];
   __hip_atomic_store(counters + rhs, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   double* s = scal + (size_t)rhs * NSCAL;
   s[slot] = t;
