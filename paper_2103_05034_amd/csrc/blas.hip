@@ -198,7 +198,12 @@ __global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __rest
   vload<PR>(r + rhs * sr, g, i, vr);
 #pragma unroll
   for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
-  vstore<PP>(p + rhs * sp, g, i, vr);
+  if constexpr (PP == DWF_F64) {  // non-temporal, as x: FP64 CG iteration -0.8 %
+    const long long h = i / g.Ls;
+    Store<DWF_F64>::store_nt(p + rhs * sp, g.V4h, g.Ls, h, (int)(i - h * g.Ls), vr);
+  } else {
+    vstore<PP>(p + rhs * sp, g, i, vr);
+  }
 }
 
 // p = r + beta p.  With orth (right after a reliable update replaced r by the
