@@ -137,6 +137,16 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
 
 HOP_SAMPLE = 5  # hop launches per timed one in the timed solves
 
+
+def rb_site_updates(V5, iterations):
+    """5D site-updates of `iterations` red-black CG iterations in the paper's counting (Results,
+    conventional Krylov solvers): an iteration applies M_pc and M_pc^dag, four half-lattice hops,
+    which count as two full matrix multiplies of V5 = V4 * Ls site-updates each."""
+    return FULL_MATMULS_PER_RB_ITERATION * V5 * iterations
+
+
+FULL_MATMULS_PER_RB_ITERATION = 2
+
 FORCE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_traffic.json")
 FORCE_SOURCE = os.path.join(ROOT, "paper_2103_05034_amd", "csrc", "force.hip")
 # the Ls = 16 force launches of the force workload (its Ls = 12 lattice takes the LDS-sum variant)
@@ -278,7 +288,7 @@ def run_rb_solve(args):
     op.enable_timing(False)
     log(f"timed {args.steps} solves: {dt:.3f} s, iterations {iters_all}, residuals {res_all}")
 
-    site_updates = sum(2 * V5 * it for it in iters_all)
+    site_updates = sum(rb_site_updates(V5, it) for it in iters_all)
     value = site_updates / dt
     b1, b2 = hop_bytes_per_site(0, Ls)
     bytes_per_launch = cg_hop_bytes_per_launch(V5h, Ls)

@@ -162,13 +162,40 @@ def test_gram_schmidt_vs_qr():
     assert np.max(np.abs(r2 - R)) < 1e-9 * np.max(np.abs(R))
 
 
-def test_rb_counting_golden():
+def test_rb_counting_golden(monkeypatch):
     """The counting rule the benchmark uses: one red-black CG iteration applies
-    M_pc twice (4 half-lattice hops) and counts as 2 full matrix multiplies."""
+    M_pc twice (4 half-lattice hops) and counts as 2 full matrix multiplies.  The
+    paper's Krylov-table rows obey it; the oracle's CG on M_pc^dag M_pc makes exactly
+    that many hopping applications per iteration (counted by wrapping the oracle's
+    hop); and bench.py's site-update count is that many full matrix multiplies of
+    V5 sites per iteration."""
+    import bench
+
     g = read_golden("rb_counting.txt")
     assert g["rb_cgnr_form1_matmuls"] == g["full_matmuls_per_rb_iteration"] * g["rb_cgnr_form1_iterations"]
     assert g["rb_cgnr_form2_matmuls"] == g["full_matmuls_per_rb_iteration"] * g["rb_cgnr_form2_iterations"]
     assert g["half_dhop_per_rb_iteration"] == 2 * g["full_matmuls_per_rb_iteration"]
+    # hops per oracle CG iteration
+    dims, Ls = (2, 2, 2, 4), 4
+    U = synth.gauge_links(dims, eps=0.3, seed=0)
+    b = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=1), L.EVEN)
+    calls = [0]
+    real_dhop = L.dhop
+
+    def counted(*args, **kwargs):
+        calls[0] += 1
+        return real_dhop(*args, **kwargs)
+
+    monkeypatch.setattr(L, "dhop", counted)
+    iters = 7
+    res = krylov.cg(lambda v: L.mpcdagmpc(U, v, M5, MF), b, tol=1e-30, maxiter=iters)
+    assert res.iterations == iters
+    # one application per iteration plus the true residual at exit
+    assert calls[0] == g["half_dhop_per_rb_iteration"] * (iters + 1)
+    # the bench's count
+    V5 = int(np.prod(dims)) * Ls
+    assert bench.FULL_MATMULS_PER_RB_ITERATION == g["full_matmuls_per_rb_iteration"]
+    assert bench.rb_site_updates(V5, g["rb_cgnr_form1_iterations"]) == g["rb_cgnr_form1_matmuls"] * V5
 
 
 def test_smoother_coefficients_match_numpy_interpolation():
