@@ -1235,7 +1235,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
-            json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described, not built"}),
+            json.dumps({"error": "one GPU only: the library drives a single device (no domain decomposition across GPUs)"}),
             flush=True,
         )
         sys.exit(2)
