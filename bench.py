@@ -230,7 +230,7 @@ def run_rb_solve(args):
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
     eta_nat = torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=1)[None]).to("cuda")
     op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=1)
-    if args.order > 0:
+    if args.order >= 0:
         op.set_order(args.order)
     if args.tile:
         op.set_tile(args.tile, args.depth)
@@ -243,7 +243,9 @@ def run_rb_solve(args):
     else:
         spb, depth, _ = op.autotune(1, 10)
         tile = (spb, depth)
-    log(f"hop launch shape: {tile[0]} sites per workgroup, pipeline depth {tile[1]}, order {args.order}")
+    mode, box = op.get_order()
+    order_desc = {"mode": mode, "box": list(box)} if mode == 3 else {"mode": mode}
+    log(f"hop launch shape: {tile[0]} sites per workgroup, pipeline depth {tile[1]}, order {order_desc}")
     eta = op.pack(eta_nat, dwf.DWF_BOTH)
     del eta_nat
     psi = op.new_field(1, both=True)
@@ -317,7 +319,7 @@ def run_rb_solve(args):
             "cg_iterations": iters_all,
             "true_rel_residual": max(res_all),
             "parallelism": "single GPU",
-            "hop_tile": {"sites_per_block": tile[0], "pipeline_depth": tile[1], "order": args.order},
+            "hop_tile": {"sites_per_block": tile[0], "pipeline_depth": tile[1], "order": order_desc},
         },
         "roofline": {
             "bound": "hbm",
@@ -350,10 +352,33 @@ def run_rb_solve(args):
     return out
 
 
+# traversal orders the bench tries: modes 0-2 and box cuts (nx, ny, nz) of the (x, y, z) volume
+ORDER_CANDIDATES = [0, 1, 2, (1, 2, 4), (1, 4, 2), (1, 4, 4), (1, 2, 8), (1, 4, 8), (1, 3, 8), (1, 6, 4), (1, 6, 8),
+                    (1, 8, 1)]
+
+
+def _set_order(op, cand):
+    """Apply an ORDER_CANDIDATES entry; False when the lattice does not admit it."""
+    import paper_2103_05034_amd as dwf
+
+    try:
+        if isinstance(cand, tuple):
+            op.set_order_box(*cand)
+        else:
+            op.set_order(cand)
+    except dwf.DWFError:
+        return False
+    return True
+
+
+def _order_name(cand):
+    return f"boxes {cand[0]}x{cand[1]}x{cand[2]}" if isinstance(cand, tuple) else str(cand)
+
+
 def _pick_shape_by_cg(op, dims, Ls, iters=60):
-    """Sites per workgroup, load-pipeline depth and traversal order of the hop kernels that
-    make 60 FP64 CG iterations (the timed solve's own mix of passes) fastest, best of two
-    timings per shape; orders a lattice does not admit are skipped."""
+    """Traversal order, then sites per workgroup and load-pipeline depth of the hop kernels,
+    that make 60 FP64 CG iterations (the timed solve's own mix of passes) fastest, best of two
+    timings each; orders a lattice does not admit are skipped."""
     import torch
 
     import paper_2103_05034_amd as dwf
@@ -361,52 +386,56 @@ def _pick_shape_by_cg(op, dims, Ls, iters=60):
 
     b = op.pack(torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=9)[None]).cuda(), dwf.DWF_EVEN)
     x = op.new_field(1)
+
+    def time_cg():
+        op.cg(b, x, 1, tol=1e-30, maxiter=10, allow_noconv=True)
+        t = None
+        for _ in range(2):
+            x.zero_()
+            tk, _ = _timed(lambda: op.cg(b, x, 1, tol=1e-30, maxiter=iters, allow_noconv=True))
+            t = tk if t is None else min(t, tk)
+        return t
+
     best = None
-    for mode in (0, 1, 2):
-        try:
-            op.set_order(mode)
-        except dwf.DWFError:
+    op.set_tile(8, 3, 1)
+    for cand in ORDER_CANDIDATES:
+        if not _set_order(op, cand):
             continue
-        for spb in (4, 8, 16):
-            for depth in (2, 3):
-                op.set_tile(spb, depth, 1)
-                op.cg(b, x, 1, tol=1e-30, maxiter=10, allow_noconv=True)
-                t = None
-                for _ in range(2):
-                    x.zero_()
-                    tk, _ = _timed(lambda: op.cg(b, x, 1, tol=1e-30, maxiter=iters, allow_noconv=True))
-                    t = tk if t is None else min(t, tk)
-                if best is None or t < best[0]:
-                    best = (t, spb, depth, mode)
-    _, spb, depth, mode = best
-    op.set_order(mode)
+        t = time_cg()
+        if best is None or t < best[0]:
+            best = (t, cand)
+    order = best[1]
+    _set_order(op, order)
+    best = None
+    for spb in (4, 8, 16):
+        for depth in (2, 3):
+            op.set_tile(spb, depth, 1)
+            t = time_cg()
+            if best is None or t < best[0]:
+                best = (t, spb, depth)
+    _, spb, depth = best
     op.set_tile(spb, depth, 1)
-    log(f"launch shape by CG timing: {spb} sites, depth {depth}, order {mode} ({best[0] / iters * 1e3:.3f} ms per iteration)")
-    return spb, depth, mode
+    log(f"launch shape by CG timing: {spb} sites, depth {depth}, order {_order_name(order)} "
+        f"({best[0] / iters * 1e3:.3f} ms per iteration)")
+    return spb, depth, order
 
 
 def _pick_order(op, reps=20):
-    """Fastest site traversal order (0 lexicographic, 1 XCD octants, 2 XCD t-slabs) for
-    M_pc^dag M_pc on the handle's lattice; orders a lattice does not admit are skipped."""
-    import torch
-
-    import paper_2103_05034_amd as dwf
-
+    """Fastest site traversal order (ORDER_CANDIDATES) for M_pc^dag M_pc on the handle's lattice
+    in its current launch shape; orders a lattice does not admit are skipped."""
     v = op.new_field(1)
     w = op.new_field(1)
     best = None
-    for mode in (0, 1, 2):
-        try:
-            op.set_order(mode)
-        except dwf.DWFError:
+    for cand in ORDER_CANDIDATES:
+        if not _set_order(op, cand):
             continue
         for _ in range(3):
             op.mpcdagmpc(v, w, 1)
         t, _ = _timed(lambda: [op.mpcdagmpc(v, w, 1) for _ in range(reps)])
-        log(f"order {mode}: {t / reps * 1e3:.3f} ms per M_pc^dag M_pc")
+        log(f"order {_order_name(cand)}: {t / reps * 1e3:.3f} ms per M_pc^dag M_pc")
         if best is None or t < best[0]:
-            best = (t, mode)
-    op.set_order(best[1])
+            best = (t, cand)
+    _set_order(op, best[1])
     return best[1]
 
 
@@ -733,10 +762,8 @@ def run_force(args):
     by_order = {}
     best = None
     # the force kernel walks the sites in the handle's traversal order: time each order
-    for mode in (0, 1, 2) if args.order < 0 else (args.order,):
-        try:
-            op2.set_order(mode)
-        except dwf.DWFError:
+    for mode in ORDER_CANDIDATES if args.order < 0 else (args.order,):
+        if not _set_order(op2, mode):
             continue
         op2.force(X2, Y2, G2)
         torch.cuda.synchronize()
@@ -751,8 +778,8 @@ def run_force(args):
         op2.enable_timing(False)
         total_ms = e0.elapsed_time(e1)
         k_ms = (total_ms - hop_ms) / reps
-        by_order[mode] = k_ms
-        log(f"force kernel, order {mode}: {k_ms:.4f} ms ({total_ms / reps:.4f} ms per dwf_force)")
+        by_order[_order_name(mode)] = k_ms
+        log(f"force kernel, order {_order_name(mode)}: {k_ms:.4f} ms ({total_ms / reps:.4f} ms per dwf_force)")
         if best is None or k_ms < best[0]:
             best = (k_ms, mode, total_ms, hop_ms)
     kernel_ms, order, total_ms, hop_ms = best
@@ -780,7 +807,7 @@ def run_force(args):
                 "dwf_force_ms": total_ms / reps,
                 "hop_passes_ms": hop_ms / reps,
                 "force_kernel_ms": kernel_ms,
-                "order": order,
+                "order": _order_name(order),
                 "force_kernel_ms_by_order": by_order,
             },
         },

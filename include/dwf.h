@@ -464,13 +464,26 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U);
 int dwf_set_tile(dwf_handle h, int sites_per_block, int pipeline_depth, int rhs_per_block);
 
 /* Library plumbing (no passage of the paper defines this call).
- * SYNCHRONOUS.  Traversal order of the half-lattice sites in the hop kernels:
- * 0 = lexicographic (x fastest, t slowest); 1 = the (x,y,z) box split into
- * 2x2x2 sub-boxes, one per XCD, each streamed with t slowest (needs X, Y, Z
- * divisible by 4); 2 = eight slabs of consecutive t, one per XCD, each
- * streamed with t fastest, then x, z, y (needs T divisible by 8).  Results
- * do not depend on the order. */
+ * SYNCHRONOUS.  Traversal order of the half-lattice sites in the hop kernels
+ * (and the force kernel): 0 = lexicographic (x fastest, t slowest); 1 = the
+ * (x,y,z) box split into 2x2x2 sub-boxes, one per XCD, each streamed with t
+ * slowest (needs X, Y, Z divisible by 4); 2 = eight slabs of consecutive t,
+ * one per XCD, each streamed with t fastest, then x, z, y (needs T divisible
+ * by 8).  DWF_EINVAL for another mode or one the lattice does not admit.
+ * Results do not depend on the order.  An order set here (or by
+ * dwf_set_order_box) is kept by dwf_autotune; otherwise the autotuner picks
+ * one. */
 int dwf_set_order(dwf_handle h, int mode);
+
+/* Library plumbing (no passage of the paper defines this call).
+ * SYNCHRONOUS.  Traversal order 3: the (x,y,z) volume cut into nx x ny x nz
+ * equal boxes (X/nx even), numbered x fastest and dealt to the XCDs in
+ * contiguous groups; inside a box the sites run with t slowest, then z, y, x.
+ * nx = 1 keeps whole x rows together.  DWF_EINVAL when the cut does not
+ * divide the lattice so.  dwf_get_order reports the order in use (mode 0-3
+ * and, for 3, the cut; box may be NULL). */
+int dwf_set_order_box(dwf_handle h, int nx, int ny, int nz);
+int dwf_get_order(dwf_handle h, int* mode, int box[3]);
 
 /* Library plumbing (no passage of the paper defines this call).
  * Cap the resident hop workgroups per compute unit (0 = no cap) by reserving
@@ -479,16 +492,19 @@ int dwf_set_order(dwf_handle h, int mode);
 int dwf_set_occupancy(dwf_handle h, int workgroups_per_cu);
 
 /* Library plumbing (no passage of the paper defines this call).
- * SYNCHRONOUS.  Times M_pc^dag M_pc on nrhs right-hand sides (<= max_nrhs)
- * for each candidate launch shape -- workgroups of 256, 128 and 64 lanes,
- * load-pipeline depth 1..3, 1/2/4/8 rhs per workgroup (<= nrhs) -- over
- * `reps` applications each, keeps the fastest in the handle and reports it
- * (any output pointer may be NULL).  The result is cached per (GPU
- * architecture, lattice, Ls, nrhs, precision, traversal order, occupancy cap,
- * Schur form) for the life of the process, and in the text file named by the
- * environment variable DWF_TUNE_CACHE when it is set (read on first use,
- * appended to); a cached shape is applied without timing, and best_ms then
- * reports the time measured when it was tuned. */
+ * SYNCHRONOUS.  Times M_pc^dag M_pc on nrhs right-hand sides (<= max_nrhs),
+ * `reps` applications per candidate.  Unless the caller set a traversal
+ * order, it first picks one (modes 0-2 and a fixed list of box cuts the
+ * lattice admits, in a middle-sized launch shape); then the launch shape --
+ * workgroups of 256, 128 and 64 lanes, load-pipeline depth 1..3, 1/2/4/8 rhs
+ * per workgroup (<= nrhs).  Keeps the fastest in the handle and reports the
+ * shape (any output pointer may be NULL; dwf_get_order reports the order).
+ * The result is cached per (GPU architecture, lattice, Ls, nrhs, precision,
+ * the caller's traversal order or none, occupancy cap, Schur form) for the
+ * life of the process, and in the text file named by the environment variable
+ * DWF_TUNE_CACHE when it is set (read on first use, appended to); a cached
+ * choice is applied without timing, and best_ms then reports the time
+ * measured when it was tuned. */
 int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb,
                  double* best_ms);
 

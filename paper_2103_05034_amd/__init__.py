@@ -120,6 +120,8 @@ _PROTOS = {
     "dwf_prolong": (_i, [_vp, _vp, _i, _vp, _i, _vp]),
     "dwf_set_tile": (_i, [_vp, _i, _i, _i]),
     "dwf_set_order": (_i, [_vp, _i]),
+    "dwf_set_order_box": (_i, [_vp, _i, _i, _i]),
+    "dwf_get_order": (_i, [_vp, _c_int_p, _c_int_p]),
     "dwf_set_occupancy": (_i, [_vp, _i]),
     "dwf_set_progress": (_i, [_vp, PROGRESS_FN, _vp, _i]),
     "dwf_autotune": (_i, [_vp, _i, _i, _c_int_p, _c_int_p, _c_int_p, _c_dbl_p]),
@@ -577,6 +579,17 @@ class Operator:
 
     def set_order(self, mode):
         _check(self.lib.dwf_set_order(self.h, int(mode)))
+
+    def set_order_box(self, nx, ny, nz):
+        """Traversal order 3: the (x, y, z) volume cut into nx x ny x nz boxes, one group per XCD."""
+        _check(self.lib.dwf_set_order_box(self.h, int(nx), int(ny), int(nz)))
+
+    def get_order(self):
+        """(mode, (nx, ny, nz)) of the traversal order in use; the cut is (0, 0, 0) unless mode is 3."""
+        mode = ctypes.c_int()
+        box = (ctypes.c_int * 3)()
+        _check(self.lib.dwf_get_order(self.h, ctypes.byref(mode), box))
+        return mode.value, tuple(box)
 
     def set_occupancy(self, workgroups_per_cu):
         _check(self.lib.dwf_set_occupancy(self.h, int(workgroups_per_cu)))

@@ -296,6 +296,8 @@ int dwf_create(dwf_handle* out, const void* U, const int dims[4], int Ls, double
   c->depth[0] = c->depth[1] = c->depth[2] = 2;
   c->rpb = 1;
   c->order_mode = 0;
+  c->order_box[0] = c->order_box[1] = c->order_box[2] = 0;
+  c->order_explicit = 0;
   c->lds_floor = 0;
   c->schur_form = 1;
   c->timing = false;
@@ -1283,17 +1285,58 @@ int dwf_solve_unprec(dwf_handle h, const void* eta, void* psi, double tol, int m
   return DWF_OK;
 }
 
-int dwf_set_order(dwf_handle h, int mode) {
-  if (int r = check_h(h)) return r;
+// Builds and uploads a traversal order (mode 0-2, or 3 with a box cut); false
+// when the lattice does not admit it (nothing changes then).
+static int apply_order(dwf_handle h, int mode, const int box[3], bool* ok) {
+  *ok = true;
   if (mode == 0) {
     h->order_mode = 0;
+    h->order_box[0] = h->order_box[1] = h->order_box[2] = 0;
     return DWF_OK;
   }
   std::vector<int> ord;
-  if (!plan::build_order(h->g.X, h->g.Y, h->g.Z, h->g.T, mode, ord)) return fail(DWF_EINVAL, "traversal order %d not available for this lattice", mode);
+  const Geom& g = h->g;
+  const bool built = mode == 3 ? plan::build_box_order(g.X, g.Y, g.Z, g.T, box[0], box[1], box[2], ord)
+                               : plan::build_order(g.X, g.Y, g.Z, g.T, mode, ord);
+  if (!built) {
+    *ok = false;
+    return DWF_OK;
+  }
   HIP_TRY(hipMemcpyAsync(h->order, ord.data(), ord.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   h->order_mode = mode;
+  for (int i = 0; i < 3; ++i) h->order_box[i] = mode == 3 ? box[i] : 0;
+  return DWF_OK;
+}
+
+int dwf_set_order(dwf_handle h, int mode) {
+  if (int r = check_h(h)) return r;
+  if (mode < 0 || mode > 2) return fail(DWF_EINVAL, "traversal order %d unknown (0, 1, 2; boxes: dwf_set_order_box)", mode);
+  const int none[3] = {0, 0, 0};
+  bool ok = true;
+  if (int rc = apply_order(h, mode, none, &ok)) return rc;
+  if (!ok) return fail(DWF_EINVAL, "traversal order %d not available for this lattice", mode);
+  h->order_explicit = 1;
+  return DWF_OK;
+}
+
+int dwf_set_order_box(dwf_handle h, int nx, int ny, int nz) {
+  if (int r = check_h(h)) return r;
+  const int box[3] = {nx, ny, nz};
+  bool ok = true;
+  if (int rc = apply_order(h, 3, box, &ok)) return rc;
+  if (!ok)
+    return fail(DWF_EINVAL, "box cut %d x %d x %d does not divide the %d x %d x %d volume into boxes of even x extent",
+                nx, ny, nz, h->g.X, h->g.Y, h->g.Z);
+  h->order_explicit = 1;
+  return DWF_OK;
+}
+
+int dwf_get_order(dwf_handle h, int* mode, int box[3]) {
+  if (int r = check_h(h)) return r;
+  if (mode) *mode = h->order_mode;
+  if (box)
+    for (int i = 0; i < 3; ++i) box[i] = h->order_box[i];
   return DWF_OK;
 }
 
@@ -1332,7 +1375,10 @@ static int tune_key(dwf_handle h, int nrhs, plan::TuneKey* k) {
   k->Ls = h->g.Ls;
   k->nrhs = nrhs;
   k->prec = h->prec;
-  k->order = h->order_mode;
+  // an order the caller set is part of the key; otherwise the tuner picks it (-1)
+  k->order = h->order_explicit
+                 ? h->order_mode + 4 * (h->order_box[0] + 64 * (h->order_box[1] + 64 * h->order_box[2]))
+                 : -1;
   k->lds_floor = h->lds_floor;
   k->schur_form = h->schur_form;
   return DWF_OK;
@@ -1350,33 +1396,56 @@ int dwf_tune_cache_clear(void) {
   return DWF_OK;
 }
 
-int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb, double* best_ms) {
-  if (int r = check_h(h)) return r;
-  if (nrhs < 1 || nrhs > h->max_nrhs || reps < 1) return fail(DWF_EINVAL, "dwf_autotune: nrhs in [1, max_nrhs], reps >= 1");
+// ms per M_pc^dag M_pc on nrhs zero fields in the handle's current launch shape and order
+static int time_mdagm(dwf_handle h, char* v, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1, double* per) {
+  const int P = h->prec;
+  for (int w = 0; w < 2; ++w) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
+  HIP_TRY(hipEventRecord(e0, h->stream));
+  for (int k = 0; k < reps; ++k) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
+  HIP_TRY(hipEventRecord(e1, h->stream));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  *per = ms / reps;
+  return DWF_OK;
+}
+
+// The traversal order (unless the caller set one), then the launch shape.
+static int autotune_search(dwf_handle h, int nrhs, int reps, hipEvent_t e0, hipEvent_t e1, plan::TuneEntry* best) {
   const int P = h->prec;
   const int Ls = h->g.Ls;
-  plan::TuneKey key;
-  if (int rc = tune_key(h, nrhs, &key)) return rc;
-  const char* cache_file = std::getenv("DWF_TUNE_CACHE");
-  plan::TuneEntry hit;
-  if (plan::tune_lookup(key, &hit, cache_file)) {
-    apply_tile(h, hit.spb, hit.depth, hit.rpb);
-    if (best_spb) *best_spb = hit.spb;
-    if (best_depth) *best_depth = hit.depth;
-    if (best_rpb) *best_rpb = hit.rpb;
-    if (best_ms) *best_ms = hit.ms;
-    return DWF_OK;
-  }
   char* v = h->cheb_a;  // zero field; M_pc^dag M_pc maps it onto itself
   HIP_TRY(blas_zero(h, P, v, nrhs));
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  const bool was_timing = h->timing;
-  h->timing = false;
-  const int old_spb = h->spb, old_depth = h->depth[P], old_rpb = h->rpb;
-  int bs = 0, bd = 0, br = 1;
-  double bms = 1e30;
+  best->order = h->order_mode;
+  for (int i = 0; i < 3; ++i) best->box[i] = h->order_box[i];
+  if (!h->order_explicit) {
+    // stage 1: orders in a middle-sized shape
+    apply_tile(h, std::max(1, 128 / Ls), 3, 1);
+    double bms = 1e30;
+    const int none[3] = {0, 0, 0};
+    for (int c = -3; c < plan::NUM_BOX_CANDIDATES; ++c) {
+      const int mode = c < 0 ? c + 3 : 3;
+      if (mode == 3 && plan::BOX_CANDIDATES[c][0] == 2 && plan::BOX_CANDIDATES[c][1] == 2 &&
+          plan::BOX_CANDIDATES[c][2] == 2)
+        continue;  // the octants of mode 1
+      const int* box = mode == 3 ? plan::BOX_CANDIDATES[c] : none;
+      bool ok = true;
+      if (int rc = apply_order(h, mode, box, &ok)) return rc;
+      if (!ok) continue;
+      double per = 0;
+      if (int rc = time_mdagm(h, v, nrhs, reps, e0, e1, &per)) return rc;
+      if (per < bms) {
+        bms = per;
+        best->order = mode;
+        for (int i = 0; i < 3; ++i) best->box[i] = box[i];
+      }
+    }
+    bool ok = true;
+    if (int rc = apply_order(h, best->order, best->box, &ok)) return rc;
+  }
+  // stage 2: sites per workgroup, pipeline depth, rhs per workgroup
+  best->spb = 0;
+  best->ms = 1e30;
   for (int threads = 256; threads >= 64; threads /= 2) {
     const int spb = threads / Ls;
     if (spb < 1) continue;
@@ -1384,40 +1453,55 @@ int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_dept
       const int depth = 1 + cand % 3;
       const int rpb = 1 << (cand / 3);
       if (rpb > nrhs) continue;
-      h->spb = spb;
-      h->depth[P] = depth;
-      h->rpb = rpb;
-      for (int w = 0; w < 2; ++w) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
-      HIP_TRY(hipEventRecord(e0, h->stream));
-      for (int k = 0; k < reps; ++k) HIP_TRY(mdagm_chunk(h, P, v, v, h->t_buf, h->u_buf, nrhs));
-      HIP_TRY(hipEventRecord(e1, h->stream));
-      HIP_TRY(hipEventSynchronize(e1));
-      float ms = 0;
-      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      const double per = ms / reps;
-      if (per < bms) {
-        bms = per;
-        bs = spb;
-        bd = depth;
-        br = rpb;
+      apply_tile(h, spb, depth, rpb);
+      double per = 0;
+      if (int rc = time_mdagm(h, v, nrhs, reps, e0, e1, &per)) return rc;
+      if (per < best->ms) {
+        best->ms = per;
+        best->spb = spb;
+        best->depth = depth;
+        best->rpb = rpb;
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  h->timing = was_timing;
-  if (bs == 0) {
-    h->spb = old_spb;
-    h->depth[P] = old_depth;
-    h->rpb = old_rpb;
-    return fail(DWF_EINVAL, "dwf_autotune: no candidate shape for Ls = %d", Ls);
+  return DWF_OK;
+}
+
+int dwf_autotune(dwf_handle h, int nrhs, int reps, int* best_spb, int* best_depth, int* best_rpb, double* best_ms) {
+  if (int r = check_h(h)) return r;
+  if (nrhs < 1 || nrhs > h->max_nrhs || reps < 1) return fail(DWF_EINVAL, "dwf_autotune: nrhs in [1, max_nrhs], reps >= 1");
+  const int P = h->prec;
+  plan::TuneKey key;
+  if (int rc = tune_key(h, nrhs, &key)) return rc;
+  const char* cache_file = std::getenv("DWF_TUNE_CACHE");
+  plan::TuneEntry best{};
+  if (!plan::tune_lookup(key, &best, cache_file)) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const bool was_timing = h->timing;
+    h->timing = false;
+    const int old_spb = h->spb, old_depth = h->depth[P], old_rpb = h->rpb;
+    const int rc = autotune_search(h, nrhs, reps, e0, e1, &best);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->timing = was_timing;
+    if (rc) return rc;
+    if (best.spb == 0) {
+      apply_tile(h, old_spb, old_depth, old_rpb);
+      return fail(DWF_EINVAL, "dwf_autotune: no candidate shape for Ls = %d", h->g.Ls);
+    }
+    plan::tune_store(key, best, cache_file);
+  } else if (!h->order_explicit) {
+    bool ok = true;
+    if (int rc = apply_order(h, best.order, best.box, &ok)) return rc;
+    if (!ok) return fail(DWF_EINVAL, "dwf_autotune: cached traversal order does not fit this lattice");
   }
-  apply_tile(h, bs, bd, br);
-  plan::tune_store(key, plan::TuneEntry{bs, bd, br, bms}, cache_file);
-  if (best_spb) *best_spb = bs;
-  if (best_depth) *best_depth = bd;
-  if (best_rpb) *best_rpb = br;
-  if (best_ms) *best_ms = bms;
+  apply_tile(h, best.spb, best.depth, best.rpb);
+  if (best_spb) *best_spb = best.spb;
+  if (best_depth) *best_depth = best.depth;
+  if (best_rpb) *best_rpb = best.rpb;
+  if (best_ms) *best_ms = best.ms;
   return DWF_OK;
 }
 

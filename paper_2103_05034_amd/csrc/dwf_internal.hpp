@@ -470,7 +470,9 @@ struct dwf_context {
   int rpb;
   double* hop_partials;  // per-site |M_pc p|^2 (or |r|^2) sums of CG, [max_cg_rhs][V4h]
   int* order;            // site traversal order per out parity, [2][V4h] (device)
-  int order_mode;        // 0: lexicographic (no table); 1: XCD octants streamed along t
+  int order_mode;        // 0: lexicographic (no table); 1: XCD octants; 2: XCD t-slabs; 3: boxes of order_box
+  int order_box[3];      // the (x, y, z) cut of order 3
+  int order_explicit;    // the caller chose the order (the autotuner then keeps it)
   int lds_floor;         // minimum LDS bytes requested by a hop launch (caps workgroups per CU)
   int schur_form;  // 1: M_ee - M_eo M_oo^{-1} M_oe; 2: 1 - M_ee^{-1} M_eo M_oo^{-1} M_oe
   double lam_max;  // lambda_max of M_pc^dag M_pc last measured by dwf_power (0: none since the operator changed)

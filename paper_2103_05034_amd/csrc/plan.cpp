@@ -107,25 +107,35 @@ Workspace plan_workspace(const int dims[4], int Ls, int prec, int max_nrhs, int 
   return w;
 }
 
+bool build_box_order(int X, int Y, int Z, int T, int nx, int ny, int nz, std::vector<int>& ord) {
+  const size_t V4h = (size_t)X * Y * Z * T / 2;
+  ord.assign(2 * V4h, 0);
+  if (nx < 1 || ny < 1 || nz < 1 || X % nx || Y % ny || Z % nz) return false;
+  const int bx = X / nx, by = Y / ny, bz = Z / nz;
+  if (bx % 2) return false;
+  for (int p = 0; p < 2; ++p) {
+    size_t k = (size_t)p * V4h;
+    for (int rz = 0; rz < nz; ++rz)
+      for (int ry = 0; ry < ny; ++ry)
+        for (int rx = 0; rx < nx; ++rx) {
+          const int ox = rx * bx, oy = ry * by, oz = rz * bz;
+          for (int t = 0; t < T; ++t)
+            for (int z = oz; z < oz + bz; ++z)
+              for (int y = oy; y < oy + by; ++y)
+                for (int x = ox; x < ox + bx; ++x)
+                  if (((x + y + z + t) & 1) == p) ord[k++] = (int)half_index(X, Y, Z, x, y, z, t);
+        }
+    if (k != (size_t)(p + 1) * V4h) return false;
+  }
+  return true;
+}
+
 bool build_order(int X, int Y, int Z, int T, int mode, std::vector<int>& ord) {
   const size_t V4h = (size_t)X * Y * Z * T / 2;
   ord.assign(2 * V4h, 0);
   if (mode == 1) {
     if (X % 4 || Y % 4 || Z % 4) return false;
-    const int bx = X / 2, by = Y / 2, bz = Z / 2;
-    for (int p = 0; p < 2; ++p) {
-      size_t k = (size_t)p * V4h;
-      for (int r = 0; r < 8; ++r) {
-        const int ox = (r & 1) * bx, oy = ((r >> 1) & 1) * by, oz = ((r >> 2) & 1) * bz;
-        for (int t = 0; t < T; ++t)
-          for (int z = oz; z < oz + bz; ++z)
-            for (int y = oy; y < oy + by; ++y)
-              for (int x = ox; x < ox + bx; ++x)
-                if (((x + y + z + t) & 1) == p) ord[k++] = (int)half_index(X, Y, Z, x, y, z, t);
-      }
-      if (k != (size_t)(p + 1) * V4h) return false;
-    }
-    return true;
+    return build_box_order(X, Y, Z, T, 2, 2, 2, ord);
   }
   if (mode == 2) {
     if (T % 8) return false;
@@ -213,8 +223,9 @@ bool build_blocks(int X, int Y, int Z, int T, int Ls, const int block[4], bool b
 
 std::string format_tune_line(const TuneKey& k, const TuneEntry& e) {
   char b[512];
-  snprintf(b, sizeof b, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %.17g", k.arch.c_str(), k.dims[0], k.dims[1],
-           k.dims[2], k.dims[3], k.Ls, k.nrhs, k.prec, k.order, k.lds_floor, k.schur_form, e.spb, e.depth, e.rpb, e.ms);
+  snprintf(b, sizeof b, "%s %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %d %.17g", k.arch.c_str(), k.dims[0],
+           k.dims[1], k.dims[2], k.dims[3], k.Ls, k.nrhs, k.prec, k.order, k.lds_floor, k.schur_form, e.spb, e.depth,
+           e.rpb, e.order, e.box[0], e.box[1], e.box[2], e.ms);
   return b;
 }
 
@@ -223,12 +234,13 @@ bool parse_tune_line(const std::string& line, TuneKey* k, TuneEntry* e) {
   TuneKey kk;
   TuneEntry ee;
   if (!(in >> kk.arch >> kk.dims[0] >> kk.dims[1] >> kk.dims[2] >> kk.dims[3] >> kk.Ls >> kk.nrhs >> kk.prec >>
-        kk.order >> kk.lds_floor >> kk.schur_form >> ee.spb >> ee.depth >> ee.rpb >> ee.ms))
+        kk.order >> kk.lds_floor >> kk.schur_form >> ee.spb >> ee.depth >> ee.rpb >> ee.order >> ee.box[0] >>
+        ee.box[1] >> ee.box[2] >> ee.ms))
     return false;
   std::string rest;
   if (in >> rest) return false;  // trailing fields: not a line of this format
   if (ee.spb < 1 || ee.spb * kk.Ls > 256 || ee.depth < 1 || ee.depth > 3 || ee.rpb < 1 || ee.rpb > 64 ||
-      !(ee.ms >= 0))
+      !(ee.ms >= 0) || ee.order < 0 || ee.order > 3 || ee.box[0] < 0 || ee.box[1] < 0 || ee.box[2] < 0)
     return false;  // a shape the launchers would refuse
   *k = kk;
   *e = ee;

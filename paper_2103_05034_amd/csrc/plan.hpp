@@ -82,6 +82,20 @@ inline long long half_index(int X, int Y, int Z, int x, int y, int z, int t) {
 // the mode (mode 0, lexicographic, needs no table).
 bool build_order(int X, int Y, int Z, int T, int mode, std::vector<int>& ord);
 
+// Traversal order in boxes: the (x, y, z) volume cut into nx x ny x nz equal
+// boxes (x extent even), numbered x fastest and dealt to the XCDs in
+// contiguous groups (XCD k runs the k-th eighth of the order); inside a box
+// the sites run with t slowest, then z, y, x.  nx = 1 keeps whole x rows, so a
+// workgroup's ±x neighbours stay inside its row; (2, 2, 2) is mode 1.  Returns
+// false when the cut does not divide the lattice.
+bool build_box_order(int X, int Y, int Z, int T, int nx, int ny, int nz, std::vector<int>& ord);
+
+// The box cuts the autotuner times (besides modes 0 and 2), in order; those a
+// lattice does not admit are skipped.
+constexpr int BOX_CANDIDATES[][3] = {{2, 2, 2}, {1, 2, 4}, {1, 4, 2}, {1, 4, 4}, {1, 2, 8},
+                                     {1, 4, 8}, {1, 3, 8}, {1, 6, 4}, {1, 6, 8}, {1, 8, 1}};
+constexpr int NUM_BOX_CANDIDATES = sizeof(BOX_CANDIDATES) / sizeof(BOX_CANDIDATES[0]);
+
 // Coarse-space blocks of extents block[4] over the lattice: `sites` gets, per
 // block (numbered x fastest), its sites in lexicographic order (even sites
 // only, as half-lattice indices, unless `both`; with `both`, odd sites as
@@ -93,17 +107,21 @@ bool build_blocks(int X, int Y, int Z, int T, int Ls, const int block[4], bool b
                   std::vector<int>& nbrs, int* nblocks, int* sites_per_block, std::string* why);
 
 // Launch shapes found by the autotuner, kept per (GPU architecture, lattice,
-// Ls, rhs count, precision, traversal order, occupancy cap, Schur form) for
+// Ls, rhs count, precision, traversal order or "tuned", occupancy cap, Schur form) for
 // the life of the process and, when a file path is given, in that file (one
 // entry per line, appended as found; lines that do not parse are skipped).
 struct TuneKey {
   std::string arch;  // the device's architecture name, without spaces
   int dims[4];
-  int Ls, nrhs, prec, order, lds_floor, schur_form;
+  int Ls, nrhs, prec;
+  int order;  // -1: the traversal order is tuned too; else the code of the order the caller set
+  int lds_floor, schur_form;
 };
 struct TuneEntry {
   int spb, depth, rpb;
-  double ms;  // time per M_pc^dag M_pc measured when the shape was tuned
+  int order;      // traversal order mode chosen (0, 1, 2, or 3 for boxes)
+  int box[3];     // the box cut of order 3
+  double ms;      // time per M_pc^dag M_pc measured when the shape was tuned
 };
 std::string format_tune_line(const TuneKey& k, const TuneEntry& e);
 bool parse_tune_line(const std::string& line, TuneKey* k, TuneEntry* e);

@@ -164,6 +164,50 @@ static void check_orders(const int d[4]) {
   }
 }
 
+// box orders: a permutation per parity; the k-th eighth of the order (XCD k) holds whole
+// boxes when the box count is a multiple of 8; x rows stay whole with nx = 1
+static void check_box_orders(const int d[4]) {
+  const size_t V4h = (size_t)d[0] * d[1] * d[2] * d[3] / 2;
+  static const int extra[2][3] = {{3, 1, 1}, {0, 1, 1}};  // an odd cut of x, and a zero cut
+  for (int c = 0; c < plan::NUM_BOX_CANDIDATES + 2; ++c) {
+    const int* cut = c < plan::NUM_BOX_CANDIDATES ? plan::BOX_CANDIDATES[c] : extra[c - plan::NUM_BOX_CANDIDATES];
+    std::vector<int> ord;
+    const bool ok = plan::build_box_order(d[0], d[1], d[2], d[3], cut[0], cut[1], cut[2], ord);
+    const bool admits = cut[0] >= 1 && d[0] % cut[0] == 0 && d[1] % cut[1] == 0 && d[2] % cut[2] == 0 &&
+                        (d[0] / cut[0]) % 2 == 0;
+    CHECK(ok == admits, "box %d,%d,%d on %dx%dx%dx%d: built=%d expected %d", cut[0], cut[1], cut[2], d[0], d[1],
+          d[2], d[3], ok, admits);
+    if (!ok) continue;
+    const int bx = d[0] / cut[0], by = d[1] / cut[1], bz = d[2] / cut[2];
+    const int nbox = cut[0] * cut[1] * cut[2];
+    const size_t per_box = V4h / nbox;
+    for (int p = 0; p < 2; ++p) {
+      std::vector<char> seen(V4h, 0);
+      for (size_t k = 0; k < V4h; ++k) {
+        const int h = ord[p * V4h + k];
+        if (h < 0 || (size_t)h >= V4h) {
+          CHECK(false, "box order index out of range");
+          continue;
+        }
+        CHECK(!seen[h], "box order: site twice");
+        seen[h] = 1;
+        int cc[4];
+        decode(d, p, h, cc);
+        CHECK(((cc[0] + cc[1] + cc[2] + cc[3]) & 1) == p, "box order: wrong parity");
+        // the k-th site lies in box k / per_box (boxes numbered x fastest)
+        const int b = (int)(k / per_box);
+        const int rx = b % cut[0], ry = (b / cut[0]) % cut[1], rz = b / (cut[0] * cut[1]);
+        CHECK(cc[0] / bx == rx && cc[1] / by == ry && cc[2] / bz == rz, "box order: site outside its box");
+      }
+    }
+  }
+  // mode 1 is the 2 x 2 x 2 cut
+  std::vector<int> a, b;
+  if (plan::build_order(d[0], d[1], d[2], d[3], 1, a)) {
+    CHECK(plan::build_box_order(d[0], d[1], d[2], d[3], 2, 2, 2, b) && a == b, "mode 1 differs from the 2x2x2 cut");
+  }
+}
+
 static void check_blocks(const int d[4], int Ls, const int blk[4], bool both, bool expect_ok) {
   const size_t V4h = (size_t)d[0] * d[1] * d[2] * d[3] / 2;
   std::vector<int> sites, nbrs;
@@ -219,21 +263,30 @@ static void check_blocks(const int d[4], int Ls, const int blk[4], bool both, bo
 
 static void check_tune_cache(const std::string& dir) {
   plan::TuneKey k{"gfx950:sramecc+:xnack-", {16, 16, 16, 32}, 16, 1, DWF_F64, 1, 0, 1};
-  plan::TuneEntry e{8, 3, 1, 0.6192718505859375};
+  plan::TuneEntry e{8, 3, 1, 3, {1, 2, 4}, 0.6192718505859375};
   plan::TuneKey k2;
   plan::TuneEntry e2;
   CHECK(plan::parse_tune_line(plan::format_tune_line(k, e), &k2, &e2), "formatted line does not parse");
   CHECK(k2.arch == k.arch && std::memcmp(k2.dims, k.dims, sizeof k.dims) == 0 && k2.Ls == k.Ls && k2.nrhs == k.nrhs &&
             k2.prec == k.prec && k2.order == k.order && k2.lds_floor == k.lds_floor && k2.schur_form == k.schur_form,
         "key does not round-trip");
-  CHECK(e2.spb == e.spb && e2.depth == e.depth && e2.rpb == e.rpb && e2.ms == e.ms, "entry does not round-trip");
-  const char* bad[] = {"", "gfx950", "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 1",            // too short
-                       "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 1 0.5 extra",                   // trailing field
-                       "gfx950 16 16 16 32 16 1 0 1 0 1 32 3 1 0.5",                        // 32 x 16 lanes
-                       "gfx950 16 16 16 32 16 1 0 1 0 1 8 0 1 0.5", "gfx950 16 16 16 32 16 1 0 1 0 1 8 4 1 0.5",
-                       "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 0 0.5", "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 65 0.5",
-                       "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 1 nan", "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 1 -1",
-                       "gfx950 x 16 16 32 16 1 0 1 0 1 8 3 1 0.5", "gfx950 16 16 16 32 16 1 0 1 0 1 8 3 1 1e999x"};
+  CHECK(e2.spb == e.spb && e2.depth == e.depth && e2.rpb == e.rpb && e2.order == e.order && e2.box[0] == 1 &&
+            e2.box[1] == 2 && e2.box[2] == 4 && e2.ms == e.ms,
+        "entry does not round-trip");
+  const char* bad[] = {"", "gfx950", "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 3 1 2 4",          // too short
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 3 1 2 4 0.5 extra",                // trailing field
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 0.5",                              // the older format
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 32 3 1 3 1 2 4 0.5",                     // 32 x 16 lanes
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 0 1 3 1 2 4 0.5",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 4 1 3 1 2 4 0.5",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 0 3 1 2 4 0.5",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 65 3 1 2 4 0.5",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 4 1 2 4 0.5",                      // order 4
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 3 -1 2 4 0.5",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 3 1 2 4 nan",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 3 1 2 4 -1",
+                       "gfx950 x 16 16 32 16 1 0 -1 0 1 8 3 1 3 1 2 4 0.5",
+                       "gfx950 16 16 16 32 16 1 0 -1 0 1 8 3 1 3 1 2 4 1e999x"};
   for (const char* line : bad) CHECK(!plan::parse_tune_line(line, &k2, &e2), "bad line parsed: '%s'", line);
   // random bytes and numbers: the parser must reject or accept cleanly
   unsigned seed = 12345;
@@ -256,14 +309,15 @@ static void check_tune_cache(const std::string& dir) {
   plan::TuneKey k3 = k;
   k3.nrhs = 40;
   k3.prec = DWF_F32;
-  plan::tune_store(k3, plan::TuneEntry{16, 3, 2, 3.125}, path.c_str());
+  plan::tune_store(k3, plan::TuneEntry{16, 3, 2, 1, {0, 0, 0}, 3.125}, path.c_str());
   {
     FILE* f = std::fopen(path.c_str(), "a");
     std::fputs("this line is not an entry\n", f);
     std::fclose(f);
   }
   plan::tune_clear();  // forget: the next lookup reads the file
-  CHECK(plan::tune_lookup(k, &e2, path.c_str()) && e2.spb == 8 && e2.depth == 3 && e2.ms == e.ms,
+  CHECK(plan::tune_lookup(k, &e2, path.c_str()) && e2.spb == 8 && e2.depth == 3 && e2.order == 3 && e2.box[2] == 4 &&
+            e2.ms == e.ms,
         "entry not read back from the file");
   CHECK(plan::tune_lookup(k3, &e2, path.c_str()) && e2.spb == 16 && e2.rpb == 2, "second entry not read back");
   plan::TuneKey k4 = k;
@@ -284,6 +338,8 @@ int main(int argc, char** argv) {
         for (int cg : {0, 1, 2}) check_workspace(d, Ls, prec, cg == 2 ? 40 : 1, cg);
   const int small[][4] = {{2, 2, 2, 2}, {4, 4, 4, 8}, {8, 4, 4, 8}, {4, 8, 12, 16}, {6, 2, 10, 4}, {16, 16, 16, 32}};
   for (const auto& d : small) check_orders(d);
+  const int boxed[][4] = {{16, 16, 16, 32}, {24, 24, 24, 8}, {8, 4, 4, 8}, {12, 6, 8, 4}, {2, 2, 2, 2}};
+  for (const auto& d : boxed) check_box_orders(d);
   const int d1[4] = {8, 4, 4, 8};
   const int b_ok[][4] = {{2, 2, 2, 2}, {4, 2, 4, 2}, {4, 4, 4, 4}, {2, 1, 1, 1}, {1, 1, 1, 2}};
   for (const auto& b : b_ok) {

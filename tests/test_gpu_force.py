@@ -29,7 +29,7 @@ def test_force_kernel_given_X_Y(dims, Ls):
     assert rel(G, Go) < 1e-13
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, (1, 2, 4)])
 @pytest.mark.parametrize("Ls", [4, 5])
 def test_force_kernel_traversal_order(order, Ls):
     """The force kernel walks the sites in the handle's traversal order (XCD octants,
@@ -44,7 +44,10 @@ def test_force_kernel_traversal_order(order, Ls):
     Y = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=35), EVEN)
     Xd, Yd = pack(op, X[None], EVEN), pack(op, Y[None], EVEN)
     G0 = op.force(Xd, Yd)
-    op.set_order(order)
+    if isinstance(order, tuple):
+        op.set_order_box(*order)
+    else:
+        op.set_order(order)
     G1 = op.force(Xd, Yd)
     torch.cuda.synchronize()
     assert torch.equal(G0, G1)

@@ -189,17 +189,22 @@ def test_repeat_is_bitwise_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("order", [1, 2, (1, 2, 2), (2, 1, 4), (1, 4, 1)])
 @pytest.mark.parametrize("prec", [F64, F32, F16S])
 def test_traversal_order_gives_identical_results(prec, order):
-    """The XCD-octant and t-slab traversals only permute which workgroup computes a site."""
+    """The XCD-octant, t-slab and box traversals only permute which workgroup computes a site."""
     dims, Ls = (8, 4, 4, 8), 6
     op, U = make_operator(dims, Ls, seed=17, prec=prec)
     nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 2, seed=18)])
     inp = pack(op, nat, EVEN)
     a, b = op.new_field(2), op.new_field(2)
     op.mpcdagmpc(inp, a, 2)
-    op.set_order(order)
+    if isinstance(order, tuple):
+        op.set_order_box(*order)
+        assert op.get_order() == (3, order)
+    else:
+        op.set_order(order)
+        assert op.get_order() == (order, (0, 0, 0))
     op.mpcdagmpc(inp, b, 2)
     import torch
 
@@ -252,6 +257,18 @@ def test_cg_batched_with_rhs_per_block():
         assert rel(xg[k], ref.x) < 1e-6
 
 
+def test_box_order_rejects_cuts_that_do_not_fit():
+    import paper_2103_05034_amd as dwf
+
+    op, _ = make_operator((8, 4, 4, 8), 4, seed=19)
+    for cut in ((3, 1, 1), (1, 3, 1), (8, 1, 1), (0, 1, 1), (1, 1, 8)):
+        with pytest.raises(dwf.DWFError):
+            op.set_order_box(*cut)  # x extent odd, not dividing, or zero
+    with pytest.raises(dwf.DWFError):
+        op.set_order(3)  # boxes only through set_order_box
+    assert op.get_order() == (0, (0, 0, 0))
+
+
 def test_autotune_cache(tmp_path, monkeypatch):
     """dwf_autotune keeps the shape it found per (architecture, lattice, Ls, nrhs,
     precision, order, occupancy cap, Schur form): a second handle of the same
@@ -271,6 +288,7 @@ def test_autotune_cache(tmp_path, monkeypatch):
     op2, _ = make_operator(dims, Ls, seed=21, max_nrhs=2)
     r2 = op2.autotune(2, 2)
     assert r1 == r2 and op1.tile == op2.tile
+    assert op1.get_order() == op2.get_order()  # the tuned traversal order comes with the cached shape
     nat = np.stack([L.on_parity(f, EVEN) for f in fields(dims, Ls, 2, seed=22)])
     a, b = op1.new_field(2), op2.new_field(2)
     op1.mpcdagmpc(pack(op1, nat, EVEN), a, 2)

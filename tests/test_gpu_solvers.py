@@ -282,8 +282,11 @@ def test_cg_independent_of_launch_shape(prec):
     op64, _ = make_operator(dims, Ls, seed=0, prec=F64)
     b_dev = pack(op64, even_fields(dims, Ls, 2, seed=7), EVEN)
     ref = None
-    for order in (0, 1, 2):
-        op.set_order(order)
+    for order in (0, 1, 2, (1, 2, 2)):
+        if isinstance(order, tuple):
+            op.set_order_box(*order)
+        else:
+            op.set_order(order)
         for spb, depth, rpb in ((4, 2, 1), (8, 3, 1), (16, 3, 2), (42, 1, 1)):
             op.set_tile(spb, depth, rpb)
             x = op.new_field(2, prec=F64)
