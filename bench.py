@@ -168,9 +168,10 @@ def measured_force_traffic():
     return rec["bytes_per_launch"]
 
 
-def measured_traffic(key):
+def measured_traffic(key, order=None):
     """HBM bytes per hop launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in
-    profiles/hop_traffic.json, or None when the hop kernel source changed since they were taken."""
+    profiles/hop_traffic.json, or None when the hop kernel source changed since they were taken,
+    or when they were taken in another traversal order than `order` ({"mode": m[, "box": [..]]})."""
     import hashlib
 
     try:
@@ -180,7 +181,13 @@ def measured_traffic(key):
         return None
     if rec.get("hop_source_sha256") != digest or key not in rec.get("workloads", {}):
         return None
-    return rec["workloads"][key]["bytes_per_launch"]
+    entry = rec["workloads"][key].get("orders", {}).get(_order_key(order) if order is not None else "", None)
+    return entry["bytes_per_launch"] if entry else None
+
+
+def _order_key(order):
+    """'3:1,4,2' for boxes, '1' for mode 1: the key of a traffic record's traversal order."""
+    return f"3:{','.join(map(str, order['box']))}" if order.get("mode") == 3 else str(order.get("mode", 0))
 
 
 def log(msg):
@@ -230,7 +237,10 @@ def run_rb_solve(args):
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
     eta_nat = torch.from_numpy(synth.gaussian_fermion(dims, Ls, seed=1)[None]).to("cuda")
     op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F64, max_nrhs=1, max_cg_rhs=1)
-    if args.order >= 0:
+    if args.box:
+        op.set_order_box(*(int(v) for v in args.box.split(",")))
+        args.order = 3
+    elif args.order >= 0:
         op.set_order(args.order)
     if args.tile:
         op.set_tile(args.tile, args.depth)
@@ -327,7 +337,7 @@ def run_rb_solve(args):
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_traffic("rb_solve"),
+            "traffic": measured_traffic("rb_solve", order_desc),
             "kernel": "hop_kernel (all passes of the timed solves, every 5th launch timed; bytes = mean of a "
             "CG iteration's four)",
             "bytes_per_launch": bytes_per_launch,
@@ -1226,6 +1236,9 @@ def main():
     ap.add_argument("--depth", type=int, default=0, help="neighbour-load pipeline depth with --tile (0 = keep)")
     ap.add_argument("--order", type=int, default=-1,
                     help="site traversal order (0 lexicographic, 1 XCD octants, 2 XCD t-slabs; -1 = fastest)")
+    ap.add_argument("--box", type=str, default="",
+                    help="traversal order in boxes: the cut NX,NY,NZ of the (x, y, z) volume (overrides --order); "
+                    "with --traffic, the order the counters were taken in")
     ap.add_argument(
         "--traffic",
         nargs=4,
@@ -1254,11 +1267,20 @@ def main():
         import hashlib
 
         rec = summarize_traffic(*args.traffic, copy_bytes=WORKLOADS["copy"]["bytes"])
-        rec["hop_source_sha256"] = hashlib.sha256(open(HOP_SOURCE, "rb").read()).hexdigest()
-        out = {"hop_source_sha256": rec.pop("hop_source_sha256"), "workloads": {"rb_solve": rec}}
+        order = ({"mode": 3, "box": [int(v) for v in args.box.split(",")]} if args.box
+                 else {"mode": max(args.order, 0)})
+        digest = hashlib.sha256(open(HOP_SOURCE, "rb").read()).hexdigest()
+        # one record per traversal order, kept while the hop source is unchanged
+        try:
+            out = json.load(open(TRAFFIC_FILE))
+        except (OSError, ValueError):
+            out = {}
+        if out.get("hop_source_sha256") != digest or "orders" not in out.get("workloads", {}).get("rb_solve", {}):
+            out = {"hop_source_sha256": digest, "workloads": {"rb_solve": {"orders": {}}}}
+        out["workloads"]["rb_solve"]["orders"][_order_key(order)] = {"order": order, **rec}
         with open(TRAFFIC_FILE, "w") as f:
             json.dump(out, f, indent=1)
-        print(json.dumps(out, indent=1))
+        print(json.dumps(out["workloads"]["rb_solve"]["orders"][_order_key(order)], indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
