@@ -205,10 +205,16 @@ __global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __rest
       vstore<PX>(x + rhs * sx, g, i, vx);
     }
   }
-  if constexpr (PR == DWF_F64)
+  if constexpr (PR == DWF_F64) {
     Store<DWF_F64>::load_nt(r + rhs * sr, g.V4h, g.Ls, hh, ss, vr);
-  else
+  } else if constexpr (PR == DWF_F32) {
+    cplx<float> t[12];
+    Store<DWF_F32>::load_nt(r + rhs * sr, g.V4h, g.Ls, hh, ss, t);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) vr[c] = {(double)t[c].re, (double)t[c].im};
+  } else {
     vload<PR>(r + rhs * sr, g, i, vr);
+  }
 #pragma unroll
   for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
   if constexpr (PP == DWF_F64) {  // non-temporal, as x: FP64 CG iteration -0.8 %
