@@ -364,7 +364,7 @@ def run_rb_solve(args):
 
 # traversal orders the bench tries: modes 0-2 and box cuts (nx, ny, nz) of the (x, y, z) volume
 ORDER_CANDIDATES = [0, 1, 2, (1, 2, 4), (1, 4, 2), (1, 4, 4), (1, 2, 8), (1, 4, 8), (1, 3, 8), (1, 6, 4), (1, 6, 8),
-                    (1, 8, 1)]
+                    (1, 8, 1), (1, 8, 8)]
 
 
 def _set_order(op, cand):

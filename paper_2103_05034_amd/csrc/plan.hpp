@@ -92,8 +92,8 @@ bool build_box_order(int X, int Y, int Z, int T, int nx, int ny, int nz, std::ve
 
 // The box cuts the autotuner times (besides modes 0 and 2), in order; those a
 // lattice does not admit are skipped.
-constexpr int BOX_CANDIDATES[][3] = {{2, 2, 2}, {1, 2, 4}, {1, 4, 2}, {1, 4, 4}, {1, 2, 8},
-                                     {1, 4, 8}, {1, 3, 8}, {1, 6, 4}, {1, 6, 8}, {1, 8, 1}};
+constexpr int BOX_CANDIDATES[][3] = {{2, 2, 2}, {1, 2, 4}, {1, 4, 2}, {1, 4, 4}, {1, 2, 8}, {1, 4, 8},
+                                     {1, 3, 8}, {1, 6, 4}, {1, 6, 8}, {1, 8, 1}, {1, 8, 8}};
 constexpr int NUM_BOX_CANDIDATES = sizeof(BOX_CANDIDATES) / sizeof(BOX_CANDIDATES[0]);
 
 // Coarse-space blocks of extents block[4] over the lattice: `sites` gets, per
