@@ -854,9 +854,13 @@ def run_operator(args):
     V5h = X * Y * Z * T * Ls // 2
     U = torch.from_numpy(synth.gauge_links(dims, eps, seed=0)).to("cuda")
     op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=prec, max_nrhs=nrhs, max_cg_rhs=0)
-    if args.order >= 0:
+    if args.box:
+        op.set_order_box(*(int(v) for v in args.box.split(",")))
+    elif args.order >= 0:
         op.set_order(args.order)
     spb, depth, _ = op.autotune(nrhs, 3)
+    mode, box = op.get_order()
+    log(f"operator: order {mode}{' boxes ' + 'x'.join(map(str, box)) if mode == 3 else ''}, tile {spb} x {depth}")
     v = op.new_field(nrhs)
     _fill_gaussian(op, v, nrhs, dims, Ls, seed=2)
     w = op.new_field(nrhs)
@@ -884,7 +888,8 @@ def run_operator(args):
         "dtype": args.prec,
         "data": "synthetic",
         "config": {"workload": f"M_pc^dag M_pc, {args.lattice} Ls={Ls}, {args.prec}, {nrhs} rhs per launch",
-                   "tile": {"sites_per_block": spb, "pipeline_depth": depth}},
+                   "tile": {"sites_per_block": spb, "pipeline_depth": depth},
+                   "order": {"mode": mode, "box": list(box)} if mode == 3 else {"mode": mode}},
         "roofline": _roofline(per_app / 4, hop_ms, hop_n, f"hop_kernel, {args.prec}, {nrhs} rhs (mean of the 4 passes)"),
     }
 
