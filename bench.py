@@ -153,9 +153,10 @@ FORCE_SOURCE = os.path.join(ROOT, "paper_2103_05034_amd", "csrc", "force.hip")
 FORCE_KERNEL_PREFIX = "void dwf::force_dir_kernel<true>"
 
 
-def measured_force_traffic():
+def measured_force_traffic(order):
     """HBM bytes per launch of the force kernel on the 16^3 x 32, Ls = 16 lattice from the
-    rocprofv3 runs recorded in profiles/force_traffic.json, or None when force.hip changed since."""
+    rocprofv3 runs recorded in profiles/force_traffic.json for the traversal order `order`
+    ({"mode": m[, "box": [..]]}), or None when force.hip changed since or no record has that order."""
     import hashlib
 
     try:
@@ -165,7 +166,8 @@ def measured_force_traffic():
         return None
     if rec.get("force_source_sha256") != digest:
         return None
-    return rec["bytes_per_launch"]
+    entry = rec.get("orders", {}).get(_order_key(order))
+    return entry["bytes_per_launch"] if entry else None
 
 
 def measured_traffic(key, order=None):
@@ -772,7 +774,8 @@ def run_force(args):
     by_order = {}
     best = None
     # the force kernel walks the sites in the handle's traversal order: time each order
-    for mode in ORDER_CANDIDATES if args.order < 0 else (args.order,):
+    fixed = tuple(int(v) for v in args.box.split(",")) if args.box else (args.order if args.order >= 0 else None)
+    for mode in ORDER_CANDIDATES if fixed is None else (fixed,):
         if not _set_order(op2, mode):
             continue
         op2.force(X2, Y2, G2)
@@ -827,7 +830,8 @@ def run_force(args):
             "peak": PEAK_HBM_GBS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
-            "traffic": measured_force_traffic(),
+            "traffic": measured_force_traffic({"mode": 3, "box": list(order)} if isinstance(order, tuple)
+                                              else {"mode": order}),
             "kernel": "force_kernel, 16^3x32 Ls=16 (both parities; bytes: a, b on both parities + the gradient)",
             "bytes_per_launch": nbytes,
             "avg_launch_ms": kernel_ms,
@@ -1263,10 +1267,19 @@ def main():
 
         rec = summarize_traffic(*args.traffic_force, copy_bytes=WORKLOADS["copy"]["bytes"],
                                 prefixes=[FORCE_KERNEL_PREFIX])
-        out = {"force_source_sha256": hashlib.sha256(open(FORCE_SOURCE, "rb").read()).hexdigest(), **rec}
+        order = ({"mode": 3, "box": [int(v) for v in args.box.split(",")]} if args.box
+                 else {"mode": max(args.order, 0)})
+        digest = hashlib.sha256(open(FORCE_SOURCE, "rb").read()).hexdigest()
+        try:
+            out = json.load(open(FORCE_TRAFFIC_FILE))
+        except (OSError, ValueError):
+            out = {}
+        if out.get("force_source_sha256") != digest or "orders" not in out:
+            out = {"force_source_sha256": digest, "orders": {}}
+        out["orders"][_order_key(order)] = {"order": order, **rec}
         with open(FORCE_TRAFFIC_FILE, "w") as f:
             json.dump(out, f, indent=1)
-        print(json.dumps(out, indent=1))
+        print(json.dumps(out["orders"][_order_key(order)], indent=1))
         return
     if args.traffic:
         import hashlib
