@@ -65,6 +65,7 @@ void carve(dwf_context* d, const plan::Workspace& w, char* base) {
   d->p64 = at(plan::B_P64);
   d->q64 = at(plan::B_Q64);
   d->b64 = at(plan::B_B64);
+  d->dir64 = at(plan::B_DIR64);
   d->lo_r = at(plan::B_LO_R);
   d->lo_x = at(plan::B_LO_X);
   d->lo_p = at(plan::B_LO_P);
@@ -491,9 +492,22 @@ static hipError_t true_residual(dwf_handle h, const char* b, const char* x, char
   return blas_dot(h, DWF_F64, r, DWF_F64, r, nrhs, slot, false);
 }
 
+// FP64 CG on M_pc^dag M_pc.  On the first Schur form an iteration is the fused
+// operator step (alpha, r -= alpha A p with |r|^2, beta and the convergence step)
+// and the new direction p' = r + beta p written beside p, while x += alpha p waits:
+// every DEFER iterations one pass adds the last DEFER directions to x, with the
+// same roundings as one update per iteration, and writes the next direction.
+// That streams x once per DEFER iterations instead of every iteration.
 static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, int maxiter, int* iters, double* resid) {
+  constexpr int DEFER = 4;
   const double tol2 = tol * tol;
   char *r = h->r64, *p = h->p64, *q = h->q64;
+  const size_t fb64 = fbytes(h, DWF_F64) * (size_t)h->max_cg_rhs;
+  // the directions of one deferral cycle, on the first Schur form (q is free there)
+  char* dir[DEFER] = {p, q, h->dir64, h->dir64 ? h->dir64 + fb64 : nullptr};
+  const int kept[DEFER] = {S_ALPHA_K, S_ALPHA_K + 1, S_ALPHA_K + 2, S_ALPHA};
+  const bool defer = h->schur_form == 1 && h->dir64 != nullptr;
+  int pending = 0;  // directions whose alpha p is not yet in x
   HIP_TRY(true_residual(h, b, x, r, nrhs, S_RR));
   HIP_TRY(blas_dot(h, DWF_F64, b, DWF_F64, b, nrhs, S_BB, false));
   HIP_TRY(blas_copy(h, DWF_F64, r, DWF_F64, p, nrhs));
@@ -516,7 +530,17 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
         break;
       }
     }
-    if (h->schur_form == 1) {
+    if (defer) {
+      const int m = it % DEFER;
+      HIP_TRY(cg_step_f64(h, dir[m], r, h->t64, h->u64, nrhs, tol2));
+      if (m < DEFER - 1) {
+        HIP_TRY(cg_next_dir(h, r, dir[m], dir[m + 1], kept[m], nrhs));
+        pending = m + 1;
+      } else {
+        HIP_TRY(cg_flush_x(h, x, dir, kept, DEFER, r, dir[0], nrhs));
+        pending = 0;
+      }
+    } else if (h->schur_form == 1) {
       // alpha, r -= alpha A p, |r|^2, beta and the convergence step; then x += alpha p,
       // p = r + beta p (the convergence step changes neither alpha nor beta)
       HIP_TRY(cg_step_f64(h, p, r, h->t64, h->u64, nrhs, tol2));
@@ -530,6 +554,7 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
       HIP_TRY(scal_converge(h, nrhs, tol2, true));
     }
   }
+  if (pending > 0) HIP_TRY(cg_flush_x(h, x, dir, kept, pending, nullptr, nullptr, nrhs));
   // true residual at exit
   HIP_TRY(true_residual(h, b, x, q, nrhs, S_TRUE));
   if (int rc = read_scalars(h, nrhs, sc)) return rc;

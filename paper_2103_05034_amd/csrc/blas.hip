@@ -224,6 +224,76 @@ __global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __rest
   }
 }
 
+// FP64 CG with the solution update deferred.  pn = r + beta p into a new buffer
+// (p is kept for the deferred x += alpha p), and alpha copied to slot `keep`.
+__global__ void cg_dir_kernel(VecGeom g, const char* __restrict__ r, const char* __restrict__ p,
+                              char* __restrict__ pn, size_t sf, double* __restrict__ scal, int keep) {
+  const int rhs = blockIdx.y;
+  double* s = scal + rhs * NSCAL;
+  if (blockIdx.x == 0 && threadIdx.x == 0) s[keep] = s[S_ALPHA];
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double beta = s[S_BETA];
+  const long long hh = i / g.Ls;
+  const int ss = (int)(i - hh * g.Ls);
+  cplx<double> vr[12], vp[12];
+  Store<DWF_F64>::load_nt(p + rhs * sf, g.V4h, g.Ls, hh, ss, vp);
+  Store<DWF_F64>::load_nt(r + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
+  Store<DWF_F64>::store_nt(pn + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+}
+
+struct DirSet {
+  const char* p[4];  // directions p_0 .. p_{N-1}, in the order of their iterations
+  int slot[4];       // scalar slot of each direction's alpha
+};
+
+// x += alpha_0 p_0 + ... + alpha_{N-1} p_{N-1}, one fma per term in this order and a
+// term skipped when its alpha is 0: the same roundings as N single updates
+// x += alpha p.  With pn: pn = r + beta p_{N-1} (pn may alias p_0; every thread
+// reads its elements before it writes them).
+template <int N>
+__global__ void cg_flush_kernel(VecGeom g, char* x, DirSet d, const char* r, char* pn, size_t sf,
+                                const double* __restrict__ scal) {
+  const int rhs = blockIdx.y;
+  const long long i = (long long)blockIdx.x * BS + threadIdx.x;
+  if (i >= g.n) return;
+  const double* s = scal + rhs * NSCAL;
+  const long long hh = i / g.Ls;
+  const int ss = (int)(i - hh * g.Ls);
+  double alpha[N];
+  bool any = false;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    alpha[k] = s[d.slot[k]];
+    any |= alpha[k] != 0.0;
+  }
+  cplx<double> vp[12];
+  bool have_last = false;
+  if (any) {
+    cplx<double> vx[12];
+    Store<DWF_F64>::load_nt(x + rhs * sf, g.V4h, g.Ls, hh, ss, vx);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      if (alpha[k] == 0.0) continue;
+      Store<DWF_F64>::load_nt(d.p[k] + rhs * sf, g.V4h, g.Ls, hh, ss, vp);
+#pragma unroll
+      for (int c = 0; c < 12; ++c) vx[c] = {fma(alpha[k], vp[c].re, vx[c].re), fma(alpha[k], vp[c].im, vx[c].im)};
+      have_last = k == N - 1;
+    }
+    Store<DWF_F64>::store_nt(x + rhs * sf, g.V4h, g.Ls, hh, ss, vx);
+  }
+  if (pn == nullptr) return;
+  const double beta = s[S_BETA];
+  if (!have_last) Store<DWF_F64>::load_nt(d.p[N - 1] + rhs * sf, g.V4h, g.Ls, hh, ss, vp);
+  cplx<double> vr[12];
+  Store<DWF_F64>::load_nt(r + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+#pragma unroll
+  for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
+  Store<DWF_F64>::store_nt(pn + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+}
+
 // p = r + beta p.  With orth (right after a reliable update replaced r by the
 // true residual), p first loses its component along the new r,
 // p <- p - (r^dag p / |r|^2) r, so that p = (1 - beta c) r + beta p with
@@ -629,6 +699,35 @@ hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r
     xp_l<DWF_F64, DWF_F32, DWF_F16S>(ctx, g, x, r, p, nrhs);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t cg_next_dir(dwf_context* ctx, const char* r, const char* p, char* pn, int keep, int nrhs) {
+  if (keep < S_ALPHA_K || keep >= NSCAL) return hipErrorInvalidValue;
+  VecGeom g = vgeom(ctx);
+  hipLaunchKernelGGL(cg_dir_kernel, dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, r, p, pn,
+                     field_bytes_rhs(ctx, DWF_F64), ctx->scalars, keep);
+  return hipGetLastError();
+}
+
+hipError_t cg_flush_x(dwf_context* ctx, char* x, char* const p[], const int slot[], int n, const char* r, char* pn,
+                      int nrhs) {
+  if (n < 1 || n > 4 || (pn != nullptr && r == nullptr)) return hipErrorInvalidValue;
+  DirSet d{};
+  for (int k = 0; k < n; ++k) {
+    if (p[k] == nullptr || slot[k] < 0 || slot[k] >= NSCAL) return hipErrorInvalidValue;
+    d.p[k] = p[k];
+    d.slot[k] = slot[k];
+  }
+  VecGeom g = vgeom(ctx);
+  const dim3 grid(grid_n(g.n), nrhs);
+  const size_t sf = field_bytes_rhs(ctx, DWF_F64);
+  switch (n) {
+    case 1: hipLaunchKernelGGL(cg_flush_kernel<1>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
+    case 2: hipLaunchKernelGGL(cg_flush_kernel<2>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
+    case 3: hipLaunchKernelGGL(cg_flush_kernel<3>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
+    default: hipLaunchKernelGGL(cg_flush_kernel<4>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
+  }
   return hipGetLastError();
 }
 

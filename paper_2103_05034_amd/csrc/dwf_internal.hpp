@@ -454,6 +454,7 @@ struct dwf_context {
   char* p64;
   char* q64;
   char* b64;         // FP64 even field for the red-black source
+  char* dir64;       // two more FP64 search directions per CG rhs (F64 handles)
   char* lo_r;        // low-precision CG vectors (F32/F16S handles)
   char* lo_p;
   char* lo_q;

@@ -86,6 +86,7 @@ Workspace plan_workspace(const int dims[4], int Ls, int prec, int max_nrhs, int 
     take(B_P64, fb(DWF_F64) * max_cg_rhs);
     take(B_Q64, fb(DWF_F64) * max_cg_rhs);
     take(B_B64, fb(DWF_F64) * max_cg_rhs);
+    if (prec == DWF_F64) take(B_DIR64, 2 * fb(DWF_F64) * max_cg_rhs);
     if (prec != DWF_F64) {
       take(B_T64, fb(DWF_F64) * max_cg_rhs);
       take(B_U64, fb(DWF_F64) * max_cg_rhs);

@@ -39,6 +39,8 @@ enum Buffer {
   B_P64,
   B_Q64,
   B_B64,
+  B_DIR64,        // two more FP64 search directions per CG rhs (FP64 handles): x is
+                  // updated once per four iterations from the last four directions
   B_T64,          // FP64 temporaries of low-precision handles
   B_U64,
   B_LO_R,         // FP32 CG vectors of low-precision handles

@@ -68,7 +68,7 @@ static void check_workspace(const int dims[4], int Ls, int prec, int max_nrhs, i
   CHECK(w.total % WS_ALIGN == 0, "total not aligned");
   // presence
   const bool cg = max_cg_rhs > 0, low = prec != DWF_F64;
-  const bool want[plan::B_COUNT] = {true, low, true, true, true, true, cg, cg, cg, cg, cg && low, cg && low,
+  const bool want[plan::B_COUNT] = {true, low, true, true, true, true, cg, cg, cg, cg, cg && !low, cg && low, cg && low,
                                     cg && low, cg && low, cg && low, cg && low, true, true, true, cg, true, true, true,
                                     true};
   // least sizes the kernels rely on
@@ -80,6 +80,7 @@ static void check_workspace(const int dims[4], int Ls, int prec, int max_nrhs, i
   need[plan::B_CHEB] = fb * std::max(max_nrhs, 2);
   for (int b : {plan::B_R64, plan::B_P64, plan::B_Q64, plan::B_B64, plan::B_T64, plan::B_U64})
     need[b] = SPINOR_BYTES[DWF_F64] * (size_t)Ls * V4h * max_cg_rhs;
+  need[plan::B_DIR64] = 2 * SPINOR_BYTES[DWF_F64] * (size_t)Ls * V4h * max_cg_rhs;
   need[plan::B_LO_R] = need[plan::B_LO_X] = SPINOR_BYTES[DWF_F32] * (size_t)Ls * V4h * max_cg_rhs;
   need[plan::B_LO_P] = need[plan::B_LO_Q] = fb * max_cg_rhs;
   need[plan::B_ORDER] = need[plan::B_BSITE] = 2 * V4h * sizeof(int);

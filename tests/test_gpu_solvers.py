@@ -299,3 +299,25 @@ def test_cg_independent_of_launch_shape(prec):
                 assert iters == ref[0], (order, spb, depth, rpb)
                 assert res == ref[1]
                 assert torch.equal(x, ref[2]), (order, spb, depth, rpb)
+
+
+@pytest.mark.parametrize("nrhs", [1, 2])
+def test_cg_fixed_iteration_counts(nrhs):
+    """CG stopped after 1..9 iterations (the FP64 solver adds its search
+    directions to x four iterations at a time, so these counts end with every
+    number of directions still pending) against the oracle's CG run for the
+    same number of iterations: the iterates are unique up to rounding."""
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, eps=0.3, seed=0)
+    b = even_fields(dims, Ls, nrhs, seed=7)
+    A = oracle_A(U)
+    b_dev = pack(op, b, EVEN)
+    for k in range(1, 10):
+        x = op.new_field(nrhs)
+        code, iters, res = op.cg(b_dev, x, nrhs, tol=1e-14, maxiter=k, allow_noconv=True)
+        xg = unpack(op, x, nrhs, EVEN)
+        for j in range(nrhs):
+            ref = krylov.cg(A, b[j], tol=1e-14, maxiter=k)
+            assert iters[j] == k == ref.iterations
+            assert rel(xg[j], ref.x) < 1e-12, (k, j)
+            assert abs(res[j] - ref.true_rel_residual) < 1e-12 * max(1.0, ref.true_rel_residual), (k, j)
