@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "dwf_internal.hpp"
 #include "kernels.hpp"
@@ -492,22 +493,53 @@ static hipError_t true_residual(dwf_handle h, const char* b, const char* x, char
   return blas_dot(h, DWF_F64, r, DWF_F64, r, nrhs, slot, false);
 }
 
+// Search directions of a CG whose x += alpha p waits: the current direction is
+// dir[n], and dir[0 .. n-1] hold the earlier ones whose alpha p is not yet in x
+// (their alphas in slots S_ALPHA_K + k).  The K-th direction's update adds all K
+// to x in the pass that forms the next direction, with the same roundings as one
+// update per iteration; x is then streamed once per K iterations.
+struct DeferredX {
+  static constexpr int K = 4;
+  char* dir[K];
+  int pr, pp;  // precisions of the residual and the directions
+  int n = 0;
+  char* current() const { return dir[n]; }
+  // after an iteration on dir[n] (alpha, beta and r updated): the next direction
+  hipError_t advance(dwf_context* h, char* x, const char* r, int nrhs) {
+    if (n < K - 1) {
+      const hipError_t e = cg_next_dir(h, pr, r, pp, dir[n], dir[n + 1], S_ALPHA_K + n, nrhs);
+      if (e == hipSuccess) ++n;
+      return e;
+    }
+    const int slot[K] = {S_ALPHA_K, S_ALPHA_K + 1, S_ALPHA_K + 2, S_ALPHA};
+    const hipError_t e = cg_flush_x(h, x, pr, r, pp, dir, slot, K, dir[0], nrhs);
+    if (e == hipSuccess) n = 0;
+    return e;
+  }
+  // adds the waiting directions to x; the current one becomes dir[0]
+  hipError_t flush(dwf_context* h, char* x, int nrhs) {
+    if (n == 0) return hipSuccess;
+    const int slot[K - 1] = {S_ALPHA_K, S_ALPHA_K + 1, S_ALPHA_K + 2};
+    const hipError_t e = cg_flush_x(h, x, pr, nullptr, pp, dir, slot, n, nullptr, nrhs);
+    if (e != hipSuccess) return e;
+    std::swap(dir[0], dir[n]);
+    n = 0;
+    return hipSuccess;
+  }
+};
+static_assert(DeferredX::K - 1 + S_ALPHA_K <= NSCAL, "slots for the waiting alphas");
+
 // FP64 CG on M_pc^dag M_pc.  On the first Schur form an iteration is the fused
 // operator step (alpha, r -= alpha A p with |r|^2, beta and the convergence step)
-// and the new direction p' = r + beta p written beside p, while x += alpha p waits:
-// every DEFER iterations one pass adds the last DEFER directions to x, with the
-// same roundings as one update per iteration, and writes the next direction.
-// That streams x once per DEFER iterations instead of every iteration.
+// and the new direction p' = r + beta p written beside p, with x += alpha p
+// deferred (DeferredX).
 static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, int maxiter, int* iters, double* resid) {
-  constexpr int DEFER = 4;
   const double tol2 = tol * tol;
   char *r = h->r64, *p = h->p64, *q = h->q64;
   const size_t fb64 = fbytes(h, DWF_F64) * (size_t)h->max_cg_rhs;
   // the directions of one deferral cycle, on the first Schur form (q is free there)
-  char* dir[DEFER] = {p, q, h->dir64, h->dir64 ? h->dir64 + fb64 : nullptr};
-  const int kept[DEFER] = {S_ALPHA_K, S_ALPHA_K + 1, S_ALPHA_K + 2, S_ALPHA};
+  DeferredX dx{{p, q, h->dir64, h->dir64 ? h->dir64 + fb64 : nullptr}, DWF_F64, DWF_F64};
   const bool defer = h->schur_form == 1 && h->dir64 != nullptr;
-  int pending = 0;  // directions whose alpha p is not yet in x
   HIP_TRY(true_residual(h, b, x, r, nrhs, S_RR));
   HIP_TRY(blas_dot(h, DWF_F64, b, DWF_F64, b, nrhs, S_BB, false));
   HIP_TRY(blas_copy(h, DWF_F64, r, DWF_F64, p, nrhs));
@@ -531,15 +563,8 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
       }
     }
     if (defer) {
-      const int m = it % DEFER;
-      HIP_TRY(cg_step_f64(h, dir[m], r, h->t64, h->u64, nrhs, tol2));
-      if (m < DEFER - 1) {
-        HIP_TRY(cg_next_dir(h, r, dir[m], dir[m + 1], kept[m], nrhs));
-        pending = m + 1;
-      } else {
-        HIP_TRY(cg_flush_x(h, x, dir, kept, DEFER, r, dir[0], nrhs));
-        pending = 0;
-      }
+      HIP_TRY(cg_step_f64(h, dx.current(), r, h->t64, h->u64, nrhs, tol2));
+      HIP_TRY(dx.advance(h, x, r, nrhs));
     } else if (h->schur_form == 1) {
       // alpha, r -= alpha A p, |r|^2, beta and the convergence step; then x += alpha p,
       // p = r + beta p (the convergence step changes neither alpha nor beta)
@@ -554,7 +579,7 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
       HIP_TRY(scal_converge(h, nrhs, tol2, true));
     }
   }
-  if (pending > 0) HIP_TRY(cg_flush_x(h, x, dir, kept, pending, nullptr, nullptr, nrhs));
+  HIP_TRY(dx.flush(h, x, nrhs));
   // true residual at exit
   HIP_TRY(true_residual(h, b, x, q, nrhs, S_TRUE));
   if (int rc = read_scalars(h, nrhs, sc)) return rc;
@@ -572,7 +597,8 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
 // light mass).  One iteration is four hop launches: t = M5D^{-1} D_hop p;
 // u = M5D p - D_hop t / 4 with p.Ap = |u|^2 reduced into alpha;
 // t = M5D^{-dag} D_hop^dag u; r -= alpha (M5D^dag u - D_hop^dag t / 4) with
-// |r|^2 reduced into beta; then x += alpha p and p = r + beta p in one pass.
+// |r|^2 reduced into beta; then p' = r + beta p beside p, with x += alpha p
+// deferred (DeferredX: x is streamed once per four iterations).
 // After each iteration the scalars are copied to pinned host memory, and the
 // host reads them one iteration later, while the next iteration runs.  A rhs
 // whose iterated |r| fell tenfold below its largest value since the last
@@ -596,6 +622,8 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
   HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
   HIP_TRY(blas_copy(h, DWF_F64, r64, DWF_F32, h->lo_r, nrhs));
   HIP_TRY(blas_copy(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+  // directions at the handle's precision; the FP64 p and q are free in this solver
+  DeferredX dx{{h->lo_p, h->lo_q, h->p64, h->q64}, DWF_F32, P};
   HIP_TRY(scal_set(h, nrhs, S_ACTIVE, 1.0));
   HIP_TRY(scal_set(h, nrhs, S_FLAG, 0.0));
   HIP_TRY(scal_set(h, nrhs, S_ITERS, 0.0));
@@ -626,13 +654,13 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
     int new_slot = -1;
     if (it < maxiter) {  // queue one iteration and the copy of its scalars
       HopArgs a{};
-      a.in = h->lo_p;
+      a.in = dx.current();
       a.out = t32;
       a.alpha = 1.0;
       HIP_TRY(launch_hop_ex(h, DWF_F32, P, DWF_F32, a, DWF_ODD, 0, EPI_M5INV, nrhs));
       HopArgs m{};
       m.in = t32;
-      m.x = h->lo_p;
+      m.x = dx.current();
       m.out = u32;
       m.alpha = -0.25;
       m.partial = h->hop_partials;
@@ -652,7 +680,7 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
       d.scal = h->scalars;
       HIP_TRY(launch_hop(h, DWF_F32, d, DWF_EVEN, 1, EPI_CGR, nrhs));
       HIP_TRY(reduce_sites(h, h->hop_partials, nb, nrhs, S_RR, 3, tol2));  // |r|^2, beta, max |r|^2
-      HIP_TRY(cg_update_xp(h, DWF_F64, x, DWF_F32, h->lo_r, P, h->lo_p, nrhs));
+      HIP_TRY(dx.advance(h, x, h->lo_r, nrhs));
       new_slot = prev_slot == 0 ? 1 : 0;
       HIP_TRY(hipMemcpyAsync(h->pin_scal + new_slot * slot_doubles, h->scalars, slot_doubles * sizeof(double),
                              hipMemcpyDeviceToHost, h->stream));
@@ -679,12 +707,13 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
     }
     if (update) {
       // after the iteration(s) already queued: the FP64 residual of the FP64 solution
+      HIP_TRY(dx.flush(h, x, nrhs));
       HIP_TRY(true_residual(h, b, x, r64, nrhs, S_RR));
       HIP_TRY(scal_copy(h, nrhs, S_TRUE, S_RR));
       HIP_TRY(scal_copy(h, nrhs, S_RRMAX, S_RR));
-      HIP_TRY(cg_reliable_p(h, r64, h->lo_r, P, h->lo_p, nrhs));
-      HIP_TRY(blas_dot(h, DWF_F32, h->lo_r, P, h->lo_p, nrhs, S_TMP, true));
-      HIP_TRY(cg_orth_p(h, h->lo_r, P, h->lo_p, nrhs));
+      HIP_TRY(cg_reliable_p(h, r64, h->lo_r, P, dx.current(), nrhs));
+      HIP_TRY(blas_dot(h, DWF_F32, h->lo_r, P, dx.current(), nrhs, S_TMP, true));
+      HIP_TRY(cg_orth_p(h, h->lo_r, P, dx.current(), nrhs));
       HIP_TRY(scal_converge(h, nrhs, tol2, false, 1));  // retire on the true residual
       if (int rc = read_scalars(h, nrhs, sc)) return rc;
       prev_slot = -1;  // a snapshot queued before the update is stale
@@ -713,6 +742,7 @@ static int cg_mixed_fused(dwf_handle h, const char* b, char* x, int nrhs, double
     }
     prev_slot = new_slot;
   }
+  HIP_TRY(dx.flush(h, x, nrhs));
   HIP_TRY(true_residual(h, b, x, r64, nrhs, S_TRUE));
   if (int rc = read_scalars(h, nrhs, sc)) return rc;
   std::vector<double> tr(nrhs);

@@ -224,24 +224,52 @@ __global__ void cg_xp_kernel(VecGeom g, char* __restrict__ x, const char* __rest
   }
 }
 
-// FP64 CG with the solution update deferred.  pn = r + beta p into a new buffer
-// (p is kept for the deferred x += alpha p), and alpha copied to slot `keep`.
+// Loads and stores of a field streamed once by a CG update: FP64 and FP32 with
+// non-temporal hints (the hop passes that follow then keep more of their
+// neighbour data in L2), FP16 + scale plainly.
+template <int P>
+__device__ __forceinline__ void load_once(const char* base, const VecGeom& g, long long i, cplx<double> v[12]) {
+  const long long hh = i / g.Ls;
+  const int ss = (int)(i - hh * g.Ls);
+  if constexpr (P == DWF_F64) {
+    Store<DWF_F64>::load_nt(base, g.V4h, g.Ls, hh, ss, v);
+  } else if constexpr (P == DWF_F32) {
+    cplx<float> t[12];
+    Store<DWF_F32>::load_nt(base, g.V4h, g.Ls, hh, ss, t);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) v[c] = {(double)t[c].re, (double)t[c].im};
+  } else {
+    vload<P>(base, g, i, v);
+  }
+}
+template <int P>
+__device__ __forceinline__ void store_once(char* base, const VecGeom& g, long long i, const cplx<double> v[12]) {
+  if constexpr (P == DWF_F64) {
+    const long long hh = i / g.Ls;
+    Store<DWF_F64>::store_nt(base, g.V4h, g.Ls, hh, (int)(i - hh * g.Ls), v);
+  } else {
+    vstore<P>(base, g, i, v);
+  }
+}
+
+// CG with the solution update deferred: pn = r + beta p into another buffer (p is
+// kept for the deferred x += alpha p), and alpha copied to slot `keep`.  The same
+// arithmetic as the p half of cg_xp_kernel.
+template <int PR, int PP>
 __global__ void cg_dir_kernel(VecGeom g, const char* __restrict__ r, const char* __restrict__ p,
-                              char* __restrict__ pn, size_t sf, double* __restrict__ scal, int keep) {
+                              char* __restrict__ pn, size_t sr, size_t sp, double* __restrict__ scal, int keep) {
   const int rhs = blockIdx.y;
   double* s = scal + rhs * NSCAL;
   if (blockIdx.x == 0 && threadIdx.x == 0) s[keep] = s[S_ALPHA];
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i >= g.n) return;
   const double beta = s[S_BETA];
-  const long long hh = i / g.Ls;
-  const int ss = (int)(i - hh * g.Ls);
   cplx<double> vr[12], vp[12];
-  Store<DWF_F64>::load_nt(p + rhs * sf, g.V4h, g.Ls, hh, ss, vp);
-  Store<DWF_F64>::load_nt(r + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+  load_once<PP>(p + rhs * sp, g, i, vp);
+  load_once<PR>(r + rhs * sr, g, i, vr);
 #pragma unroll
   for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
-  Store<DWF_F64>::store_nt(pn + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+  store_once<PP>(pn + rhs * sp, g, i, vr);
 }
 
 struct DirSet {
@@ -249,19 +277,17 @@ struct DirSet {
   int slot[4];       // scalar slot of each direction's alpha
 };
 
-// x += alpha_0 p_0 + ... + alpha_{N-1} p_{N-1}, one fma per term in this order and a
-// term skipped when its alpha is 0: the same roundings as N single updates
-// x += alpha p.  With pn: pn = r + beta p_{N-1} (pn may alias p_0; every thread
-// reads its elements before it writes them).
-template <int N>
-__global__ void cg_flush_kernel(VecGeom g, char* x, DirSet d, const char* r, char* pn, size_t sf,
-                                const double* __restrict__ scal) {
+// x += alpha_0 p_0 + ... + alpha_{N-1} p_{N-1} (x FP64), one fma per term in this
+// order and a term skipped when its alpha is 0: the same roundings as N single
+// updates x += alpha p.  With pn: pn = r + beta p_{N-1} (pn may alias p_0; every
+// thread reads its elements before it writes them).
+template <int PR, int PP, int N>
+__global__ void cg_flush_kernel(VecGeom g, char* x, DirSet d, const char* r, char* pn, size_t sx, size_t sr,
+                                size_t sp, const double* __restrict__ scal) {
   const int rhs = blockIdx.y;
   const long long i = (long long)blockIdx.x * BS + threadIdx.x;
   if (i >= g.n) return;
   const double* s = scal + rhs * NSCAL;
-  const long long hh = i / g.Ls;
-  const int ss = (int)(i - hh * g.Ls);
   double alpha[N];
   bool any = false;
 #pragma unroll
@@ -273,25 +299,25 @@ __global__ void cg_flush_kernel(VecGeom g, char* x, DirSet d, const char* r, cha
   bool have_last = false;
   if (any) {
     cplx<double> vx[12];
-    Store<DWF_F64>::load_nt(x + rhs * sf, g.V4h, g.Ls, hh, ss, vx);
+    load_once<DWF_F64>(x + rhs * sx, g, i, vx);
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       if (alpha[k] == 0.0) continue;
-      Store<DWF_F64>::load_nt(d.p[k] + rhs * sf, g.V4h, g.Ls, hh, ss, vp);
+      load_once<PP>(d.p[k] + rhs * sp, g, i, vp);
 #pragma unroll
       for (int c = 0; c < 12; ++c) vx[c] = {fma(alpha[k], vp[c].re, vx[c].re), fma(alpha[k], vp[c].im, vx[c].im)};
       have_last = k == N - 1;
     }
-    Store<DWF_F64>::store_nt(x + rhs * sf, g.V4h, g.Ls, hh, ss, vx);
+    store_once<DWF_F64>(x + rhs * sx, g, i, vx);
   }
   if (pn == nullptr) return;
   const double beta = s[S_BETA];
-  if (!have_last) Store<DWF_F64>::load_nt(d.p[N - 1] + rhs * sf, g.V4h, g.Ls, hh, ss, vp);
+  if (!have_last) load_once<PP>(d.p[N - 1] + rhs * sp, g, i, vp);
   cplx<double> vr[12];
-  Store<DWF_F64>::load_nt(r + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+  load_once<PR>(r + rhs * sr, g, i, vr);
 #pragma unroll
   for (int c = 0; c < 12; ++c) vr[c] = {fma(beta, vp[c].re, vr[c].re), fma(beta, vp[c].im, vr[c].im)};
-  Store<DWF_F64>::store_nt(pn + rhs * sf, g.V4h, g.Ls, hh, ss, vr);
+  store_once<PP>(pn + rhs * sp, g, i, vr);
 }
 
 // p = r + beta p.  With orth (right after a reliable update replaced r by the
@@ -702,16 +728,45 @@ hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r
   return hipGetLastError();
 }
 
-hipError_t cg_next_dir(dwf_context* ctx, const char* r, const char* p, char* pn, int keep, int nrhs) {
+template <int PR, int PP>
+static void dir_l(dwf_context* ctx, VecGeom g, const char* r, const char* p, char* pn, int keep, int nrhs) {
+  hipLaunchKernelGGL((cg_dir_kernel<PR, PP>), dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, r, p, pn,
+                     field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP), ctx->scalars, keep);
+}
+
+hipError_t cg_next_dir(dwf_context* ctx, int pr, const char* r, int pp, const char* p, char* pn, int keep, int nrhs) {
   if (keep < S_ALPHA_K || keep >= NSCAL) return hipErrorInvalidValue;
   VecGeom g = vgeom(ctx);
-  hipLaunchKernelGGL(cg_dir_kernel, dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, r, p, pn,
-                     field_bytes_rhs(ctx, DWF_F64), ctx->scalars, keep);
+  if (pr == DWF_F64 && pp == DWF_F64)
+    dir_l<DWF_F64, DWF_F64>(ctx, g, r, p, pn, keep, nrhs);
+  else if (pr == DWF_F32 && pp == DWF_F32)
+    dir_l<DWF_F32, DWF_F32>(ctx, g, r, p, pn, keep, nrhs);
+  else if (pr == DWF_F32 && pp == DWF_F16S)
+    dir_l<DWF_F32, DWF_F16S>(ctx, g, r, p, pn, keep, nrhs);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t cg_flush_x(dwf_context* ctx, char* x, char* const p[], const int slot[], int n, const char* r, char* pn,
-                      int nrhs) {
+template <int PR, int PP, int N>
+static void flush_n(dwf_context* ctx, VecGeom g, char* x, const DirSet& d, const char* r, char* pn, int nrhs) {
+  hipLaunchKernelGGL((cg_flush_kernel<PR, PP, N>), dim3(grid_n(g.n), nrhs), dim3(BS), 0, ctx->stream, g, x, d, r, pn,
+                     field_bytes_rhs(ctx, DWF_F64), field_bytes_rhs(ctx, PR), field_bytes_rhs(ctx, PP),
+                     ctx->scalars);
+}
+
+template <int PR, int PP>
+static void flush_l(dwf_context* ctx, VecGeom g, char* x, const DirSet& d, int n, const char* r, char* pn, int nrhs) {
+  switch (n) {
+    case 1: flush_n<PR, PP, 1>(ctx, g, x, d, r, pn, nrhs); break;
+    case 2: flush_n<PR, PP, 2>(ctx, g, x, d, r, pn, nrhs); break;
+    case 3: flush_n<PR, PP, 3>(ctx, g, x, d, r, pn, nrhs); break;
+    default: flush_n<PR, PP, 4>(ctx, g, x, d, r, pn, nrhs); break;
+  }
+}
+
+hipError_t cg_flush_x(dwf_context* ctx, char* x, int pr, const char* r, int pp, char* const p[], const int slot[],
+                      int n, char* pn, int nrhs) {
   if (n < 1 || n > 4 || (pn != nullptr && r == nullptr)) return hipErrorInvalidValue;
   DirSet d{};
   for (int k = 0; k < n; ++k) {
@@ -720,14 +775,14 @@ hipError_t cg_flush_x(dwf_context* ctx, char* x, char* const p[], const int slot
     d.slot[k] = slot[k];
   }
   VecGeom g = vgeom(ctx);
-  const dim3 grid(grid_n(g.n), nrhs);
-  const size_t sf = field_bytes_rhs(ctx, DWF_F64);
-  switch (n) {
-    case 1: hipLaunchKernelGGL(cg_flush_kernel<1>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
-    case 2: hipLaunchKernelGGL(cg_flush_kernel<2>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
-    case 3: hipLaunchKernelGGL(cg_flush_kernel<3>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
-    default: hipLaunchKernelGGL(cg_flush_kernel<4>, grid, dim3(BS), 0, ctx->stream, g, x, d, r, pn, sf, ctx->scalars); break;
-  }
+  if (pr == DWF_F64 && pp == DWF_F64)
+    flush_l<DWF_F64, DWF_F64>(ctx, g, x, d, n, r, pn, nrhs);
+  else if (pr == DWF_F32 && pp == DWF_F32)
+    flush_l<DWF_F32, DWF_F32>(ctx, g, x, d, n, r, pn, nrhs);
+  else if (pr == DWF_F32 && pp == DWF_F16S)
+    flush_l<DWF_F32, DWF_F16S>(ctx, g, x, d, n, r, pn, nrhs);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -92,13 +92,14 @@ hipError_t cg_update_p(dwf_context* ctx, int pr, const char* r, int pp, char* p,
 // r -= alpha q with |r|^2 -> S_RR ; then x += alpha p and p = r + beta p in one pass (old p)
 hipError_t cg_update_r(dwf_context* ctx, int pr, char* r, int pq, const char* q, int nrhs);
 hipError_t cg_update_xp(dwf_context* ctx, int px, char* x, int pr, const char* r, int pp, char* p, int nrhs);
-// FP64 CG with the x update deferred: pn = r + beta p (p kept), and alpha copied to slot keep
-hipError_t cg_next_dir(dwf_context* ctx, const char* r, const char* p, char* pn, int keep, int nrhs);
-// x += alpha_0 p_0 + ... + alpha_{n-1} p_{n-1} (alpha_k from slot[k]; terms in this order, each
-// skipped when its alpha is 0), then, when pn is given, pn = r + beta p_{n-1} (pn may be p_0).
-// FP64, 1 <= n <= 4.
-hipError_t cg_flush_x(dwf_context* ctx, char* x, char* const p[], const int slot[], int n, const char* r, char* pn,
-                      int nrhs);
+// CG with the x update deferred: pn = r + beta p (p kept), and alpha copied to slot keep
+// (r at pr, p and pn at pp: F64/F64, F32/F32 or F32/F16S)
+hipError_t cg_next_dir(dwf_context* ctx, int pr, const char* r, int pp, const char* p, char* pn, int keep, int nrhs);
+// x += alpha_0 p_0 + ... + alpha_{n-1} p_{n-1} (x FP64; alpha_k from slot[k]; terms in this
+// order, each skipped when its alpha is 0), then, when pn is given, pn = r + beta p_{n-1}
+// (pn may be p_0).  1 <= n <= 4; precisions as cg_next_dir.
+hipError_t cg_flush_x(dwf_context* ctx, char* x, int pr, const char* r, int pp, char* const p[], const int slot[],
+                      int n, char* pn, int nrhs);
 // reliable update of the low-precision CG: p += r_true - r_iter, then r_iter = r_true (r_true FP64,
 // r_iter FP32, p at pp)
 hipError_t cg_reliable_p(dwf_context* ctx, const char* r_true, char* r_iter, int pp, char* p, int nrhs);
