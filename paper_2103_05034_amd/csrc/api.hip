@@ -1095,12 +1095,125 @@ int dwf_dot(dwf_handle h, int prec, const void* a, const void* b, int nrhs, doub
   return DWF_OK;
 }
 
+// Cholesky QR, twice (Two level preconditioner section: an orthonormal blocked
+// basis; this is the whole-lattice case).  One round: G = V^dag V in FP64 from a
+// tall-skinny Gram kernel, G = R^dag R on the host, V <- V R^{-1} in place.  The
+// second round repairs the orthogonality the first loses to the conditioning,
+// and R = R2 R1.  Q and R are CGS2's (the QR factorisation with a real positive
+// diagonal is unique) up to rounding.  Returns GS_USE_CGS2, with the vectors
+// untouched, when the first round's Gram matrix is too close to singular for
+// this form or the scratch is too small; the caller then runs CGS2.
+static int cholesky_upper(const std::vector<double>& G, int n, std::vector<double>& R, double min_ratio) {
+  // G[k][j] = <v_j, v_k> (j <= k) -> upper R with G = R^dag R, R[j][k] at (j * n + k)
+  R.assign((size_t)2 * n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = G[2 * ((size_t)j * n + j)];
+    const double djj = d;
+    for (int i = 0; i < j; ++i) d -= R[2 * ((size_t)i * n + j)] * R[2 * ((size_t)i * n + j)] +
+                                      R[2 * ((size_t)i * n + j) + 1] * R[2 * ((size_t)i * n + j) + 1];
+    if (!(d > min_ratio * djj) || !std::isfinite(d)) return DWF_EBREAKDOWN;
+    const double rjj = std::sqrt(d);
+    R[2 * ((size_t)j * n + j)] = rjj;
+    for (int k = j + 1; k < n; ++k) {
+      double re = G[2 * ((size_t)k * n + j)], im = G[2 * ((size_t)k * n + j) + 1];  // <v_j, v_k>
+      for (int i = 0; i < j; ++i) {  // - conj(R_ij) R_ik
+        const double ar = R[2 * ((size_t)i * n + j)], ai = R[2 * ((size_t)i * n + j) + 1];
+        const double br = R[2 * ((size_t)i * n + k)], bi = R[2 * ((size_t)i * n + k) + 1];
+        re -= ar * br + ai * bi;
+        im -= ar * bi - ai * br;
+      }
+      R[2 * ((size_t)j * n + k)] = re / rjj;
+      R[2 * ((size_t)j * n + k) + 1] = im / rjj;
+    }
+  }
+  return DWF_OK;
+}
+
+// W = R^{-1} for upper triangular R with a real positive diagonal
+static void invert_upper(const std::vector<double>& R, int n, std::vector<double>& W) {
+  W.assign((size_t)2 * n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    W[2 * ((size_t)k * n + k)] = 1.0 / R[2 * ((size_t)k * n + k)];
+    for (int j = k - 1; j >= 0; --j) {
+      double re = 0, im = 0;
+      for (int i = j + 1; i <= k; ++i) {  // sum R_ji W_ik
+        const double ar = R[2 * ((size_t)j * n + i)], ai = R[2 * ((size_t)j * n + i) + 1];
+        const double br = W[2 * ((size_t)i * n + k)], bi = W[2 * ((size_t)i * n + k) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      const double rjj = R[2 * ((size_t)j * n + j)];
+      W[2 * ((size_t)j * n + k)] = -re / rjj;
+      W[2 * ((size_t)j * n + k) + 1] = -im / rjj;
+    }
+  }
+}
+
+constexpr int GS_USE_CGS2 = 1;
+
+static int gs_cholqr2(dwf_handle h, char* Q, int n, std::vector<double>& Rout) {
+  const int P = h->prec;
+  const size_t nn = (size_t)n * n;
+  // scratch: per-workgroup partial Gram matrices, then G, in t_buf; W in u_buf
+  const size_t cap = fbytes(h, P) * (size_t)h->partial_count;
+  const size_t per = nn * 2 * sizeof(double);
+  if (cap < 2 * per) return GS_USE_CGS2;
+  const long long m = h->g.V4h * h->g.Ls * 12;
+  long long nwg = (long long)(cap / per) - 1;
+  nwg = std::min<long long>({nwg, 2048, (m + 255) / 256});
+  if (nwg < 1) return GS_USE_CGS2;
+  double* partial = reinterpret_cast<double*>(h->t_buf);
+  double* Gd = partial + 2 * nn * (size_t)nwg;
+  double* Wd = reinterpret_cast<double*>(h->u_buf);
+  std::vector<double> G(2 * nn), R1, R2, W;
+  for (int round = 0; round < 2; ++round) {
+    HIP_TRY(ts_gram(h, P, Q, n, partial, (int)nwg, Gd));
+    HIP_TRY(hipMemcpyAsync(G.data(), Gd, 2 * nn * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (int rc = sync(h)) return rc;
+    // first round: a pivot below 1e-14 of its diagonal entry (a condition number
+    // beyond about 1e7) leaves the set to CGS2
+    std::vector<double>& R = round == 0 ? R1 : R2;
+    if (cholesky_upper(G, n, R, round == 0 ? 1e-14 : 0.0) != DWF_OK) {
+      if (round == 0) return GS_USE_CGS2;
+      return fail(DWF_EBREAKDOWN, "dwf_gram_schmidt: the vectors are numerically dependent");
+    }
+    invert_upper(R, n, W);
+    HIP_TRY(hipMemcpyAsync(Wd, W.data(), 2 * nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(ts_combine(h, P, Q, n, Wd));
+    if (int rc = sync(h)) return rc;  // W's host copy is reused next round
+  }
+  // R = R2 R1 (both upper triangular)
+  Rout.assign(2 * nn, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = j; k < n; ++k) {
+      double re = 0, im = 0;
+      for (int i = j; i <= k; ++i) {
+        const double ar = R2[2 * ((size_t)j * n + i)], ai = R2[2 * ((size_t)j * n + i) + 1];
+        const double br = R1[2 * ((size_t)i * n + k)], bi = R1[2 * ((size_t)i * n + k) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      Rout[2 * ((size_t)j * n + k)] = re;
+      Rout[2 * ((size_t)j * n + k) + 1] = im;
+    }
+  return DWF_OK;
+}
+
 int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host) {
   if (int r = check_h(h)) return r;
   if (!vecs || nvecs < 1 || nvecs > GS_MAX) return fail(DWF_EINVAL, "dwf_gram_schmidt: nvecs must be in [1, %d]", GS_MAX);
   const int P = h->prec;
   const size_t fb = fbytes(h, P);
   char* Q = reinterpret_cast<char*>(vecs);
+  if ((P == DWF_F64 || P == DWF_F32) && nvecs <= TS_NMAX) {
+    std::vector<double> Rq;
+    const int rc = gs_cholqr2(h, Q, nvecs, Rq);
+    if (rc == DWF_OK) {
+      if (R_host) std::memcpy(R_host, Rq.data(), Rq.size() * sizeof(double));
+      return DWF_OK;
+    }
+    if (rc != GS_USE_CGS2) return rc;
+  }
   std::vector<double> R((size_t)nvecs * nvecs * 2, 0.0), cf(2 * (size_t)nvecs);
   std::vector<double> sc;
   const int chunk = (int)h->partial_count;

@@ -869,4 +869,171 @@ hipError_t gs_scale(dwf_context* ctx, int prec, char* v, const double* inv_norm)
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Cholesky-QR orthonormalisation of up to TS_NMAX fields (FP64 or FP32 storage).
+// A field is taken as a flat array of m complex values (the layout is the same
+// for every field, so inner products do not depend on it).
+// ---------------------------------------------------------------------------
+
+constexpr int TS_TPT = 3;  // 2 x 2 tiles per thread: (n/2)(n/2 + 1)/2 <= 528 for n <= 64
+
+// Per workgroup, the Gram matrix of its entries [e0, e0 + span): partial[wg][k][j] =
+// sum conj(v_j) v_k for j <= k, in FP64.  Rows of `ch` entries pass through LDS
+// with all n fields at once, and each thread accumulates 2 x 2 tiles of (j, k).
+template <typename R>
+__global__ void __launch_bounds__(256) ts_gram_kernel(const char* __restrict__ V, size_t stride, long long m, int n,
+                                                      long long span, int ch, double* __restrict__ partial) {
+  extern __shared__ char smem[];
+  cplx<R>* sm = reinterpret_cast<cplx<R>*>(smem);  // [ch][n]
+  const long long e0 = (long long)blockIdx.x * span;
+  const long long e1 = min(m, e0 + span);
+  const int half = (n + 1) / 2;
+  const int ntiles = half * (half + 1) / 2;
+  double acc[TS_TPT][8];
+  int ta[TS_TPT], tb[TS_TPT];
+#pragma unroll
+  for (int q = 0; q < TS_TPT; ++q) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[q][i] = 0;
+    int t = threadIdx.x + q * blockDim.x, row = 0;  // tile index -> (ta <= tb)
+    while (row < half && t >= half - row) {
+      t -= half - row;
+      ++row;
+    }
+    ta[q] = row;
+    tb[q] = row + t;
+  }
+  for (long long r0 = e0; r0 < e1; r0 += ch) {
+    const int cs = (int)min((long long)ch, e1 - r0);
+    __syncthreads();  // previous rows consumed
+    for (int item = threadIdx.x; item < cs * n; item += blockDim.x) {
+      const int j = item / cs, e = item - j * cs;  // consecutive threads: consecutive entries
+      sm[(size_t)e * n + j] = reinterpret_cast<const cplx<R>*>(V + (size_t)j * stride)[r0 + e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TS_TPT; ++q) {
+      if (threadIdx.x + q * blockDim.x >= ntiles) continue;
+      const int j0 = 2 * ta[q], k0 = 2 * tb[q];
+      const bool j1 = j0 + 1 < n, k1 = k0 + 1 < n;
+      for (int r = 0; r < cs; ++r) {
+        const cplx<R>* row = sm + (size_t)r * n;
+        const cplx<R> x0 = row[j0], y0 = row[k0];
+        const cplx<R> x1 = j1 ? row[j0 + 1] : cplx<R>{0, 0};
+        const cplx<R> y1 = k1 ? row[k0 + 1] : cplx<R>{0, 0};
+        // conj(x) y
+        acc[q][0] = fma((double)x0.re, (double)y0.re, fma((double)x0.im, (double)y0.im, acc[q][0]));
+        acc[q][1] = fma((double)x0.re, (double)y0.im, fma(-(double)x0.im, (double)y0.re, acc[q][1]));
+        acc[q][2] = fma((double)x0.re, (double)y1.re, fma((double)x0.im, (double)y1.im, acc[q][2]));
+        acc[q][3] = fma((double)x0.re, (double)y1.im, fma(-(double)x0.im, (double)y1.re, acc[q][3]));
+        acc[q][4] = fma((double)x1.re, (double)y0.re, fma((double)x1.im, (double)y0.im, acc[q][4]));
+        acc[q][5] = fma((double)x1.re, (double)y0.im, fma(-(double)x1.im, (double)y0.re, acc[q][5]));
+        acc[q][6] = fma((double)x1.re, (double)y1.re, fma((double)x1.im, (double)y1.im, acc[q][6]));
+        acc[q][7] = fma((double)x1.re, (double)y1.im, fma(-(double)x1.im, (double)y1.re, acc[q][7]));
+      }
+    }
+  }
+  double* G = partial + 2 * (size_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int q = 0; q < TS_TPT; ++q) {
+    if (threadIdx.x + q * blockDim.x >= ntiles) continue;
+    const int j0 = 2 * ta[q], k0 = 2 * tb[q];
+#pragma unroll
+    for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+      for (int dk = 0; dk < 2; ++dk) {
+        const int j = j0 + dj, k = k0 + dk;
+        if (j >= n || k >= n || j > k) continue;
+        G[2 * ((size_t)k * n + j)] = acc[q][2 * (2 * dj + dk)];
+        G[2 * ((size_t)k * n + j) + 1] = acc[q][2 * (2 * dj + dk) + 1];
+      }
+  }
+}
+
+// G[k][j] = sum over the workgroups, in workgroup order, of partial[wg][k][j] (j <= k)
+__global__ void ts_gram_sum_kernel(const double* __restrict__ partial, int nwg, int n, double* __restrict__ G) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int k = idx / n, j = idx - k * n;
+  if (j > k) return;
+  double re = 0, im = 0;
+  for (int w = 0; w < nwg; ++w) {
+    re += partial[2 * ((size_t)w * n * n + idx)];
+    im += partial[2 * ((size_t)w * n * n + idx) + 1];
+  }
+  G[2 * idx] = re;
+  G[2 * idx + 1] = im;
+}
+
+// In place v_k <- sum_{j <= k} W[j][k] v_j for every k (W upper triangular,
+// complex FP64, W[j][k] at j * n + k), entry by entry: one entry per thread, the
+// outputs in tiles of TS_KT from the top down, so that the v_j a tile reads (j below
+// the tile's top) are not yet overwritten.  FP64 arithmetic.
+constexpr int TS_KT = 16;
+
+template <typename R>
+__global__ void __launch_bounds__(256) ts_combine_kernel(char* V, size_t stride, long long m, int n,
+                                                         const double* __restrict__ W) {
+  extern __shared__ double wsm[];  // [n][n] complex
+  for (int i = threadIdx.x; i < 2 * n * n; i += blockDim.x) wsm[i] = W[i];
+  __syncthreads();
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  for (int k0 = (n - 1) / TS_KT * TS_KT; k0 >= 0; k0 -= TS_KT) {
+    double ar[TS_KT], ai[TS_KT];
+#pragma unroll
+    for (int t = 0; t < TS_KT; ++t) ar[t] = ai[t] = 0;
+    const int jend = min(n, k0 + TS_KT);
+    for (int j = 0; j < jend; ++j) {
+      const cplx<R> v = reinterpret_cast<const cplx<R>*>(V + (size_t)j * stride)[e];
+      const double vr = v.re, vi = v.im;
+#pragma unroll
+      for (int t = 0; t < TS_KT; ++t) {
+        const int k = k0 + t;
+        if (k >= n || j > k) continue;
+        const double wr = wsm[2 * (j * n + k)], wi = wsm[2 * (j * n + k) + 1];
+        ar[t] = fma(wr, vr, fma(-wi, vi, ar[t]));
+        ai[t] = fma(wr, vi, fma(wi, vr, ai[t]));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TS_KT; ++t) {
+      const int k = k0 + t;
+      if (k >= n) continue;
+      reinterpret_cast<cplx<R>*>(V + (size_t)k * stride)[e] = cplx<R>{(R)ar[t], (R)ai[t]};
+    }
+  }
+}
+
+hipError_t ts_gram(dwf_context* ctx, int prec, const char* V, int n, double* partial, int nwg, double* G) {
+  if (n < 1 || n > TS_NMAX || nwg < 1 || (prec != DWF_F64 && prec != DWF_F32)) return hipErrorInvalidValue;
+  const size_t stride = field_bytes_rhs(ctx, prec);
+  const long long m = ctx->g.V4h * ctx->g.Ls * 12;
+  const long long span = (m + nwg - 1) / nwg;
+  const int ch = prec == DWF_F64 ? 32 : 64;
+  const size_t lds = (size_t)ch * n * (prec == DWF_F64 ? 16 : 8);
+  if (prec == DWF_F64)
+    hipLaunchKernelGGL(ts_gram_kernel<double>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, m, n, span, ch,
+                       partial);
+  else
+    hipLaunchKernelGGL(ts_gram_kernel<float>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, m, n, span, ch,
+                       partial);
+  hipLaunchKernelGGL(ts_gram_sum_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream, partial, nwg, n, G);
+  return hipGetLastError();
+}
+
+hipError_t ts_combine(dwf_context* ctx, int prec, char* V, int n, const double* W) {
+  if (n < 1 || n > TS_NMAX || (prec != DWF_F64 && prec != DWF_F32)) return hipErrorInvalidValue;
+  const size_t stride = field_bytes_rhs(ctx, prec);
+  const long long m = ctx->g.V4h * ctx->g.Ls * 12;
+  const dim3 grid((unsigned)((m + 255) / 256));
+  const size_t lds = (size_t)2 * n * n * sizeof(double);
+  if (prec == DWF_F64)
+    hipLaunchKernelGGL(ts_combine_kernel<double>, grid, dim3(256), lds, ctx->stream, V, stride, m, n, W);
+  else
+    hipLaunchKernelGGL(ts_combine_kernel<float>, grid, dim3(256), lds, ctx->stream, V, stride, m, n, W);
+  return hipGetLastError();
+}
+
 }  // namespace dwf

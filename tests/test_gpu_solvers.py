@@ -321,3 +321,49 @@ def test_cg_fixed_iteration_counts(nrhs):
             assert iters[j] == k == ref.iterations
             assert rel(xg[j], ref.x) < 1e-12, (k, j)
             assert abs(res[j] - ref.true_rel_residual) < 1e-12 * max(1.0, ref.true_rel_residual), (k, j)
+
+
+@pytest.mark.parametrize("prec,tol", [(F64, 1e-12), (F32, 2e-5)])
+@pytest.mark.parametrize("n", [1, 17, 40, 64, 65])
+def test_gram_schmidt_set_sizes(prec, tol, n):
+    """Sets of up to 64 vectors at FP64 and FP32 go through Cholesky QR twice, larger
+    sets through CGS2: both against the oracle's CGS2 (Q R with a positive real
+    diagonal is unique), on a set with a spread of norms and two near-parallel pairs."""
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=prec)
+    v = even_fields(dims, Ls, n, seed=20 + n)
+    v *= np.exp(np.linspace(-3.0, 3.0, n))[:, None, None, None, None, None, None, None]
+    if n > 3:
+        v[2] = v[2] + 40.0 * v[1]
+        v[n - 1] = v[n - 1] + 25.0 * v[0] * np.exp(3.0 - (-3.0))
+    buf = pack(op, v, EVEN)
+    src = unpack(op, buf, n, EVEN)
+    R = op.gram_schmidt(buf, n)
+    Q = unpack(op, buf, n, EVEN)
+    Qo, Ro = krylov.gram_schmidt(list(src))
+    for k in range(n):
+        assert rel(Q[k], Qo[k]) < tol, k
+    assert np.max(np.abs(R - Ro)) < tol * np.max(np.abs(Ro))
+    assert np.all(np.abs(np.diag(R).imag) == 0) and np.all(np.diag(R).real > 0)
+    G = np.array([[np.vdot(Q[i].ravel(), Q[j].ravel()) for j in range(n)] for i in range(n)])
+    assert np.max(np.abs(G - np.eye(n))) < (1e-13 if prec == F64 else 1e-5)
+
+
+def test_gram_schmidt_nearly_dependent_set_falls_back():
+    """A set too ill-conditioned for Cholesky QR (condition number ~1e9) is left to
+    CGS2, which still returns an orthonormal Q with Q R = V."""
+    dims, Ls = C1
+    op, U = make_operator(dims, Ls, seed=0, prec=F64)
+    n = 8
+    v = even_fields(dims, Ls, n, seed=40)
+    v[5] = v[2] + 1e-9 * v[5]
+    buf = pack(op, v, EVEN)
+    src = unpack(op, buf, n, EVEN)
+    R = op.gram_schmidt(buf, n)
+    Q = unpack(op, buf, n, EVEN)
+    G = np.array([[np.vdot(Q[i].ravel(), Q[j].ravel()) for j in range(n)] for i in range(n)])
+    assert np.max(np.abs(G - np.eye(n))) < 1e-12
+    V = np.stack([s.ravel() for s in src], axis=1)
+    QR = np.stack([q.ravel() for q in Q], axis=1) @ R
+    assert np.linalg.norm(QR - V) < 1e-12 * np.linalg.norm(V)
+    assert np.all(np.diag(R).real > 0)
