@@ -79,3 +79,30 @@ def force(U, phi, M5, mf, tol=1e-14, maxiter=100000, dense=False):
     X = solve_normal(U, phi, M5, mf, tol, maxiter, dense)
     Y = L.mpc(U, X, M5, mf)
     return link_gradient(U, X, Y, M5, mf), 2.0 * X
+
+
+def su3_generators():
+    """T^a = lambda^a / 2 with the Gell-Mann matrices lambda^a, a = 1..8 (index 0..7):
+    Hermitian, traceless, tr(T^a T^b) = delta_ab / 2."""
+    lam = np.zeros((8, 3, 3), dtype=np.complex128)
+    lam[0][0, 1] = lam[0][1, 0] = 1
+    lam[1][0, 1], lam[1][1, 0] = -1j, 1j
+    lam[2][0, 0], lam[2][1, 1] = 1, -1
+    lam[3][0, 2] = lam[3][2, 0] = 1
+    lam[4][0, 2], lam[4][2, 0] = -1j, 1j
+    lam[5][1, 2] = lam[5][2, 1] = 1
+    lam[6][1, 2], lam[6][2, 1] = -1j, 1j
+    lam[7] = np.diag([1, 1, -2]) / np.sqrt(3)
+    return lam / 2
+
+
+def lie_force(U, G):
+    """Derivative of S along the Lie-algebra directions of each link:
+    F^a_mu(x) = dS/d omega at omega = 0 for U_mu(x) -> exp(i omega T^a) U_mu(x).
+
+    The variation is dU = i omega T^a U, and dS = Re sum conj(G) dU = Re tr(G^dag dU)
+    in the gradient convention above, so F^a = Re tr(i T^a U G^dag) = -Im tr(T^a U G^dag).
+    Returns F[..., mu, a] (real)."""
+    T = su3_generators()
+    M = np.einsum("...ab,...cb->...ac", U, np.conj(G))  # U G^dag
+    return -np.einsum("kab,...ba->...k", T, M).imag

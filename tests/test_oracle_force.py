@@ -84,3 +84,38 @@ def test_phi_gradient(setup):
     fd = (_action_dense(U, phi + eps * E) - _action_dense(U, phi - eps * E)) / (2 * eps)
     an = float(np.sum(np.conj(gphi) * E).real)
     assert abs(fd - an) < 1e-6 * abs(an)
+
+
+def test_su3_generators():
+    T = F.su3_generators()
+    for a in range(8):
+        assert np.allclose(T[a], T[a].conj().T) and abs(np.trace(T[a])) < 1e-15
+        for b in range(8):
+            assert abs(np.trace(T[a] @ T[b]) - 0.5 * (a == b)) < 1e-15
+    # [T^1, T^2] = i T^3 (structure constant f_123 = 1)
+    assert np.allclose(T[0] @ T[1] - T[1] @ T[0], 1j * T[2])
+
+
+def _expi(H, eps):
+    """exp(i eps H) for Hermitian H from its eigendecomposition."""
+    w, V = np.linalg.eigh(H)
+    return (V * np.exp(1j * eps * w)) @ V.conj().T
+
+
+def test_lie_force_vs_central_differences(setup):
+    """F^a_mu(x) against central differences of the dense action along
+    U_mu(x) -> exp(+-i eps T^a) U_mu(x), the eight directions on four links
+    (the update keeps the links in SU(3))."""
+    dims, Ls, U, phi, G, _ = setup
+    T = F.su3_generators()
+    Fl = F.lie_force(U, G)
+    eps = 1e-5
+    links = [(0, 0, 0, 0, 0), (1, 0, 1, 0, 2), (0, 1, 1, 1, 3), (1, 1, 0, 1, 1)]
+    scale = np.abs(Fl).max()
+    for link in links:
+        for a in range(8):
+            Up, Um = U.copy(), U.copy()
+            Up[link] = _expi(T[a], eps) @ U[link]
+            Um[link] = _expi(T[a], -eps) @ U[link]
+            fd = (_action_dense(Up, phi) - _action_dense(Um, phi)) / (2 * eps)
+            assert abs(fd - Fl[link][a]) < 1e-7 * max(abs(Fl[link][a]), 1e-2 * scale), (link, a)
