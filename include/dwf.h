@@ -458,6 +458,18 @@ int dwf_hdcr_solve(dwf_hdcr hd, const void* eta, void* psi, double tol, int maxi
  * convention G = dS/dRe U + i dS/dIm U.  Needs a DWF_F64 handle. */
 int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U);
 
+/* The same force in the Lie algebra, the form an HMC momentum update takes
+ * (Conclusions: HMC): for every link, F^a_mu(x) = dS/d omega at omega = 0 along
+ * U_mu(x) -> exp(i omega T^a) U_mu(x), which in the gradient convention of
+ * dwf_force is F^a = -Im tr(T^a U_mu(x) G_mu(x)^dag), with T^a = lambda^a / 2
+ * and lambda^1 .. lambda^8 the Gell-Mann matrices in their usual order.
+ * U and grad_U: device arrays in the natural link layout
+ * [T][Z][Y][X][4][3][3] complex128 (the links the handle was given and the
+ * output of dwf_force); F: device array [T][Z][Y][X][4][8] double, written.
+ * Caller-owned; ordered on the handle's stream.  Any handle of the lattice;
+ * DWF_EINVAL on a null pointer. */
+int dwf_lie_force(dwf_handle h, const void* U, const void* grad_U, void* F);
+
 /* ---- introspection -------------------------------------------------------- */
 
 /* Library plumbing (no passage of the paper defines this call).

@@ -96,6 +96,7 @@ _PROTOS = {
     "dwf_dot": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
     "dwf_dot_noalloc": (_i, [_c_int_p, _i, _i, _vp, _vp, _i, _vp, _vp]),
     "dwf_force": (_i, [_vp, _vp, _vp, _vp]),
+    "dwf_lie_force": (_i, [_vp, _vp, _vp, _vp]),
     "dwf_set_schur_form": (_i, [_vp, _i]),
     "dwf_solve_unprec": (_i, [_vp, _vp, _vp, _d, _i, _c_int_p, _c_dbl_p]),
     "dwf_set_blocks": (_i, [_vp, _c_int_p, _c_int_p]),
@@ -573,6 +574,20 @@ class Operator:
         self._sync_stream()
         _check(self.lib.dwf_force(self.h, px, py, pg))
         return grad
+
+    def lie_force(self, U, grad, F=None):
+        """F[t, z, y, x, mu, a] = -Im tr(T^a U_mu(x) grad_mu(x)^dag), T^a = lambda^a / 2: the
+        derivative of the action along exp(i omega T^a) U_mu(x), from dwf_force's gradient."""
+        import torch
+
+        pu, pg = self._links(U, what="U"), self._links(grad, what="grad")
+        shape = self.link_shape()[:5] + (8,)
+        if F is None:
+            F = torch.empty(shape, dtype=torch.float64, device=self.device)
+        pf = _tensor_ptr(F, self.device, "F", dtype=torch.float64, shape=shape)
+        self._sync_stream()
+        _check(self.lib.dwf_lie_force(self.h, pu, pg, pf))
+        return F
 
     def set_tile(self, sites_per_block, pipeline_depth=0, rhs_per_block=0):
         _check(self.lib.dwf_set_tile(self.h, sites_per_block, pipeline_depth, rhs_per_block))

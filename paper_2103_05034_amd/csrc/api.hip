@@ -1270,6 +1270,13 @@ int dwf_force(dwf_handle h, const void* X_e, const void* Y_e, void* grad_U) {
   return DWF_OK;
 }
 
+int dwf_lie_force(dwf_handle h, const void* U, const void* grad_U, void* F) {
+  if (int r = check_h(h)) return r;
+  if (!U || !grad_U || !F) return fail(DWF_EINVAL, "dwf_lie_force: null pointer");
+  HIP_TRY(launch_lie_force(h, U, grad_U, reinterpret_cast<double*>(F)));
+  return DWF_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Introspection
 // ---------------------------------------------------------------------------

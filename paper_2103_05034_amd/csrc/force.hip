@@ -275,6 +275,49 @@ __global__ void __launch_bounds__(256) force_dir_kernel(ForceArgs fa) {
   }
 }
 
+// Lie-algebra force of every link, one thread per link: with M = U G^dag,
+// F^a = -Im tr(T^a M), T^a = lambda^a / 2 and tr(lambda^a M) = sum_ij lambda^a_ij M_ji
+// for the Gell-Mann matrices lambda^1 .. lambda^8.
+__global__ void lie_force_kernel(const double2* __restrict__ U, const double2* __restrict__ G,
+                                 double* __restrict__ F, long long nlinks) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nlinks) return;
+  cplx<double> u[9], g[9], m[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const double2 a = U[i * 9 + k], b = G[i * 9 + k];
+    u[k] = {a.x, a.y};
+    g[k] = {b.x, b.y};
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      cplx<double> acc = {0, 0};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc = cfma_conj(g[3 * c + b], u[3 * a + b], acc);  // U_ab conj(G_cb)
+      m[3 * a + c] = acc;
+    }
+  auto M = [&](int r, int c) { return m[3 * r + c]; };
+  double* f = F + i * 8;
+  f[0] = -0.5 * (M(1, 0).im + M(0, 1).im);
+  f[1] = -0.5 * (M(0, 1).re - M(1, 0).re);
+  f[2] = -0.5 * (M(0, 0).im - M(1, 1).im);
+  f[3] = -0.5 * (M(2, 0).im + M(0, 2).im);
+  f[4] = -0.5 * (M(0, 2).re - M(2, 0).re);
+  f[5] = -0.5 * (M(2, 1).im + M(1, 2).im);
+  f[6] = -0.5 * (M(1, 2).re - M(2, 1).re);
+  f[7] = -0.5 / sqrt(3.0) * (M(0, 0).im + M(1, 1).im - 2.0 * M(2, 2).im);
+}
+
+hipError_t launch_lie_force(dwf_context* ctx, const void* U, const void* G, double* F) {
+  const long long nlinks = 2 * ctx->g.V4h * 4;
+  const unsigned grid = (unsigned)((nlinks + 255) / 256);
+  hipLaunchKernelGGL(lie_force_kernel, dim3(grid), dim3(256), 0, ctx->stream, reinterpret_cast<const double2*>(U),
+                     reinterpret_cast<const double2*>(G), F, nlinks);
+  return hipGetLastError();
+}
+
 hipError_t launch_force(dwf_context* ctx, const char* a_even, const char* a_odd, const char* b_even,
                         const char* b_odd, double* grad_U) {
   ForceArgs fa;

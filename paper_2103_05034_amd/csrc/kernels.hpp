@@ -144,5 +144,7 @@ hipError_t launch_block_cholesky(dwf_context* c, const double* gram, double* w, 
 // force.hip
 hipError_t launch_force(dwf_context* ctx, const char* a_even, const char* a_odd, const char* b_even,
                         const char* b_odd, double* grad_U);
+// F[link][a] = -Im tr(T^a U G^dag) for every link (natural layouts; F real, 8 per link)
+hipError_t launch_lie_force(dwf_context* ctx, const void* U, const void* G, double* F);
 
 }  // namespace dwf

@@ -89,3 +89,23 @@ def test_force_vs_finite_differences_resolvent():
         fd = diff / (2 * eps)
         an = float(np.sum(np.conj(G) * E).real)
         assert abs(fd - an) < 1e-6 * max(abs(an), 1e-2 * np.abs(G).max())
+
+
+@pytest.mark.parametrize("dims,Ls", [((2, 2, 2, 2), 4), ((4, 4, 6, 8), 5)])
+def test_lie_force(dims, Ls):
+    """dwf_lie_force on the GPU gradient against the oracle's Lie-algebra force of the
+    oracle gradient (the oracle's form is pinned by central differences along
+    exp(i eps T^a) U), and the same map applied to the GPU gradient itself."""
+    import torch
+
+    op, U = make_operator(dims, Ls, eps=0.5, seed=36)
+    X = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=37), EVEN)
+    Y = L.on_parity(synth.gaussian_fermion(dims, Ls, seed=38), EVEN)
+    G = op.force(pack(op, X[None], EVEN), pack(op, Y[None], EVEN))
+    Ud = torch.from_numpy(U).to(G.device)
+    Fd = op.lie_force(Ud, G)
+    torch.cuda.synchronize()
+    Fg = Fd.cpu().numpy()
+    assert Fg.shape == U.shape[:5] + (8,)
+    assert rel(Fg, F.lie_force(U, G.cpu().numpy())) < 1e-14
+    assert rel(Fg, F.lie_force(U, F.link_gradient(U, X, Y, M5, MF))) < 1e-13
