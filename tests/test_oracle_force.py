@@ -104,13 +104,13 @@ def _expi(H, eps):
 
 def test_lie_force_vs_central_differences(setup):
     """F^a_mu(x) against central differences of the dense action along
-    U_mu(x) -> exp(+-i eps T^a) U_mu(x), the eight directions on four links
-    (the update keeps the links in SU(3))."""
+    U_mu(x) -> exp(+-i eps T^a) U_mu(x), the eight directions on two links of
+    different directions and parities (the update keeps the links in SU(3))."""
     dims, Ls, U, phi, G, _ = setup
     T = F.su3_generators()
     Fl = F.lie_force(U, G)
     eps = 1e-5
-    links = [(0, 0, 0, 0, 0), (1, 0, 1, 0, 2), (0, 1, 1, 1, 3), (1, 1, 0, 1, 1)]
+    links = [(0, 0, 0, 0, 0), (0, 1, 1, 1, 3)]
     scale = np.abs(Fl).max()
     for link in links:
         for a in range(8):
