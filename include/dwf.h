@@ -233,12 +233,12 @@ int dwf_chebyshev_smoother(dwf_handle h, int order, double lo, double hi, const 
 
 /* SYNCHRONOUS.  In place Q R = V for nvecs packed even fields (handle
  * precision), the orthonormal basis that the projector P_S of the Two level
- * preconditioner section assumes, with FP64 inner products.  FP64 and FP32
- * handles with nvecs <= 64 take Cholesky QR twice (one Gram matrix of all the
- * vectors per round, V <- V R^{-1} in place); a set whose Gram matrix is too
- * close to singular for it (condition number beyond about 1e7), FP16 + scale
- * handles and larger sets take classical Gram-Schmidt applied twice.  Both give
- * the unique Q R with a positive real diagonal, up to rounding.
+ * preconditioner section assumes, with FP64 inner products.  Sets of
+ * nvecs <= 64 take Cholesky QR twice (one Gram matrix of all the vectors per
+ * round, V <- V R^{-1} in place); a set whose Gram matrix is too close to
+ * singular for it (condition number beyond about 1e7), or too large for the
+ * handle's scratch, and larger sets take classical Gram-Schmidt applied twice.
+ * Both give the unique Q R with a positive real diagonal, up to rounding.
  * R (nvecs x nvecs complex128, row-major, upper triangular, positive real
  * diagonal) is written to host memory R_host if non-NULL.  DWF_EBREAKDOWN if
  * the vectors are numerically dependent. */

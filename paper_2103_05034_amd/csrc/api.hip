@@ -1205,7 +1205,7 @@ int dwf_gram_schmidt(dwf_handle h, void* vecs, int nvecs, double* R_host) {
   const int P = h->prec;
   const size_t fb = fbytes(h, P);
   char* Q = reinterpret_cast<char*>(vecs);
-  if ((P == DWF_F64 || P == DWF_F32) && nvecs <= TS_NMAX) {
+  if (nvecs <= TS_NMAX) {
     std::vector<double> Rq;
     const int rc = gs_cholqr2(h, Q, nvecs, Rq);
     if (rc == DWF_OK) {

@@ -871,70 +871,55 @@ hipError_t gs_scale(dwf_context* ctx, int prec, char* v, const double* inv_norm)
 
 
 // ---------------------------------------------------------------------------
-// Cholesky-QR orthonormalisation of up to TS_NMAX fields (FP64 or FP32 storage).
-// A field is taken as a flat array of m complex values (the layout is the same
-// for every field, so inner products do not depend on it).
+// Cholesky-QR orthonormalisation of up to TS_NMAX fields.  At FP64 and FP32 a
+// field is taken as a flat array of m complex values (the layout is the same for
+// every field, so inner products do not depend on it); FP16 + scale fields are
+// read and written a spinor (12 complex values and their scale) at a time.
 // ---------------------------------------------------------------------------
 
 constexpr int TS_TPT = 3;  // 2 x 2 tiles per thread: (n/2)(n/2 + 1)/2 <= 528 for n <= 64
 
-// Per workgroup, the Gram matrix of its entries [e0, e0 + span): partial[wg][k][j] =
-// sum conj(v_j) v_k for j <= k, in FP64.  Rows of `ch` entries pass through LDS
-// with all n fields at once, and each thread accumulates 2 x 2 tiles of (j, k).
+// Tile (ta <= tb) of the upper triangle of (n/2 rounded up)^2 2 x 2 tiles, row-major.
+__device__ __forceinline__ void ts_tile_coords(int t, int half, int& ta, int& tb) {
+  int row = 0;
+  while (row < half && t >= half - row) {
+    t -= half - row;
+    ++row;
+  }
+  ta = row;
+  tb = row + t;
+}
+
+// acc += the 2 x 2 tiles' conj(v_j) v_k over `rows` staged rows sm[row][n]
 template <typename R>
-__global__ void __launch_bounds__(256) ts_gram_kernel(const char* __restrict__ V, size_t stride, long long m, int n,
-                                                      long long span, int ch, double* __restrict__ partial) {
-  extern __shared__ char smem[];
-  cplx<R>* sm = reinterpret_cast<cplx<R>*>(smem);  // [ch][n]
-  const long long e0 = (long long)blockIdx.x * span;
-  const long long e1 = min(m, e0 + span);
-  const int half = (n + 1) / 2;
-  const int ntiles = half * (half + 1) / 2;
-  double acc[TS_TPT][8];
-  int ta[TS_TPT], tb[TS_TPT];
+__device__ __forceinline__ void ts_tiles(const cplx<R>* sm, int rows, int n, int ntiles, const int ta[TS_TPT],
+                                         const int tb[TS_TPT], double acc[TS_TPT][8]) {
 #pragma unroll
   for (int q = 0; q < TS_TPT; ++q) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc[q][i] = 0;
-    int t = threadIdx.x + q * blockDim.x, row = 0;  // tile index -> (ta <= tb)
-    while (row < half && t >= half - row) {
-      t -= half - row;
-      ++row;
-    }
-    ta[q] = row;
-    tb[q] = row + t;
-  }
-  for (long long r0 = e0; r0 < e1; r0 += ch) {
-    const int cs = (int)min((long long)ch, e1 - r0);
-    __syncthreads();  // previous rows consumed
-    for (int item = threadIdx.x; item < cs * n; item += blockDim.x) {
-      const int j = item / cs, e = item - j * cs;  // consecutive threads: consecutive entries
-      sm[(size_t)e * n + j] = reinterpret_cast<const cplx<R>*>(V + (size_t)j * stride)[r0 + e];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < TS_TPT; ++q) {
-      if (threadIdx.x + q * blockDim.x >= ntiles) continue;
-      const int j0 = 2 * ta[q], k0 = 2 * tb[q];
-      const bool j1 = j0 + 1 < n, k1 = k0 + 1 < n;
-      for (int r = 0; r < cs; ++r) {
-        const cplx<R>* row = sm + (size_t)r * n;
-        const cplx<R> x0 = row[j0], y0 = row[k0];
-        const cplx<R> x1 = j1 ? row[j0 + 1] : cplx<R>{0, 0};
-        const cplx<R> y1 = k1 ? row[k0 + 1] : cplx<R>{0, 0};
-        // conj(x) y
-        acc[q][0] = fma((double)x0.re, (double)y0.re, fma((double)x0.im, (double)y0.im, acc[q][0]));
-        acc[q][1] = fma((double)x0.re, (double)y0.im, fma(-(double)x0.im, (double)y0.re, acc[q][1]));
-        acc[q][2] = fma((double)x0.re, (double)y1.re, fma((double)x0.im, (double)y1.im, acc[q][2]));
-        acc[q][3] = fma((double)x0.re, (double)y1.im, fma(-(double)x0.im, (double)y1.re, acc[q][3]));
-        acc[q][4] = fma((double)x1.re, (double)y0.re, fma((double)x1.im, (double)y0.im, acc[q][4]));
-        acc[q][5] = fma((double)x1.re, (double)y0.im, fma(-(double)x1.im, (double)y0.re, acc[q][5]));
-        acc[q][6] = fma((double)x1.re, (double)y1.re, fma((double)x1.im, (double)y1.im, acc[q][6]));
-        acc[q][7] = fma((double)x1.re, (double)y1.im, fma(-(double)x1.im, (double)y1.re, acc[q][7]));
-      }
+    if (threadIdx.x + q * blockDim.x >= ntiles) continue;
+    const int j0 = 2 * ta[q], k0 = 2 * tb[q];
+    const bool j1 = j0 + 1 < n, k1 = k0 + 1 < n;
+    for (int r = 0; r < rows; ++r) {
+      const cplx<R>* row = sm + (size_t)r * n;
+      const cplx<R> x0 = row[j0], y0 = row[k0];
+      const cplx<R> x1 = j1 ? row[j0 + 1] : cplx<R>{0, 0};
+      const cplx<R> y1 = k1 ? row[k0 + 1] : cplx<R>{0, 0};
+      // conj(x) y
+      acc[q][0] = fma((double)x0.re, (double)y0.re, fma((double)x0.im, (double)y0.im, acc[q][0]));
+      acc[q][1] = fma((double)x0.re, (double)y0.im, fma(-(double)x0.im, (double)y0.re, acc[q][1]));
+      acc[q][2] = fma((double)x0.re, (double)y1.re, fma((double)x0.im, (double)y1.im, acc[q][2]));
+      acc[q][3] = fma((double)x0.re, (double)y1.im, fma(-(double)x0.im, (double)y1.re, acc[q][3]));
+      acc[q][4] = fma((double)x1.re, (double)y0.re, fma((double)x1.im, (double)y0.im, acc[q][4]));
+      acc[q][5] = fma((double)x1.re, (double)y0.im, fma(-(double)x1.im, (double)y0.re, acc[q][5]));
+      acc[q][6] = fma((double)x1.re, (double)y1.re, fma((double)x1.im, (double)y1.im, acc[q][6]));
+      acc[q][7] = fma((double)x1.re, (double)y1.im, fma(-(double)x1.im, (double)y1.re, acc[q][7]));
     }
   }
-  double* G = partial + 2 * (size_t)blockIdx.x * n * n;
+}
+
+// G[k][j] (j <= k) of the workgroup's tiles
+__device__ __forceinline__ void ts_store_tiles(double* G, int n, int ntiles, const int ta[TS_TPT],
+                                               const int tb[TS_TPT], const double acc[TS_TPT][8]) {
 #pragma unroll
   for (int q = 0; q < TS_TPT; ++q) {
     if (threadIdx.x + q * blockDim.x >= ntiles) continue;
@@ -949,6 +934,52 @@ __global__ void __launch_bounds__(256) ts_gram_kernel(const char* __restrict__ V
         G[2 * ((size_t)k * n + j) + 1] = acc[q][2 * (2 * dj + dk) + 1];
       }
   }
+}
+
+// Per workgroup, the Gram matrix of its part of the fields: partial[wg][k][j] =
+// sum conj(v_j) v_k for j <= k, in FP64.  Units [u0, u0 + span) (complex values at
+// FP64 / FP32, spinors at FP16 + scale) pass through LDS `cu` units at a time with
+// all n fields at once, and each thread accumulates 2 x 2 tiles of (j, k).
+template <int P>
+__global__ void __launch_bounds__(256) ts_gram_kernel(const char* __restrict__ V, size_t stride, long long units,
+                                                      int n, long long span, int cu, VecGeom g,
+                                                      double* __restrict__ partial) {
+  using R = typename Store<P>::real;
+  constexpr int RPU = P == DWF_F16S ? 12 : 1;  // staged rows per unit
+  extern __shared__ char smem[];
+  cplx<R>* sm = reinterpret_cast<cplx<R>*>(smem);  // [cu * RPU][n]
+  const long long u0 = (long long)blockIdx.x * span;
+  const long long u1 = min(units, u0 + span);
+  const int half = (n + 1) / 2;
+  const int ntiles = half * (half + 1) / 2;
+  double acc[TS_TPT][8];
+  int ta[TS_TPT], tb[TS_TPT];
+#pragma unroll
+  for (int q = 0; q < TS_TPT; ++q) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[q][i] = 0;
+    ts_tile_coords(threadIdx.x + q * blockDim.x, half, ta[q], tb[q]);
+  }
+  for (long long r0 = u0; r0 < u1; r0 += cu) {
+    const int cs = (int)min((long long)cu, u1 - r0);
+    __syncthreads();  // previous rows consumed
+    for (int item = threadIdx.x; item < cs * n; item += blockDim.x) {
+      const int j = item / cs, e = item - j * cs;  // consecutive threads: consecutive units
+      const char* f = V + (size_t)j * stride;
+      if constexpr (P == DWF_F16S) {
+        const long long sp = r0 + e, h = sp / g.Ls;
+        cplx<float> v[12];
+        Store<DWF_F16S>::load(f, g.V4h, g.Ls, h, (int)(sp - h * g.Ls), v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sm[(size_t)(e * 12 + c) * n + j] = v[c];
+      } else {
+        sm[(size_t)e * n + j] = reinterpret_cast<const cplx<R>*>(f)[r0 + e];
+      }
+    }
+    __syncthreads();
+    ts_tiles(sm, cs * RPU, n, ntiles, ta, tb, acc);
+  }
+  ts_store_tiles(partial + 2 * (size_t)blockIdx.x * n * n, n, ntiles, ta, tb, acc);
 }
 
 // G[k][j] = sum over the workgroups, in workgroup order, of partial[wg][k][j] (j <= k)
@@ -967,10 +998,13 @@ __global__ void ts_gram_sum_kernel(const double* __restrict__ partial, int nwg, 
 }
 
 // In place v_k <- sum_{j <= k} W[j][k] v_j for every k (W upper triangular,
-// complex FP64, W[j][k] at j * n + k), entry by entry: one entry per thread, the
-// outputs in tiles of TS_KT from the top down, so that the v_j a tile reads (j below
-// the tile's top) are not yet overwritten.  FP64 arithmetic.
+// complex FP64, W[j][k] at j * n + k), one unit per thread: the outputs in tiles
+// from the top down, so that the v_j a tile reads (j below the tile's top) are not
+// yet overwritten.  FP64 and FP32: one complex value per thread, tiles of 16,
+// FP64 arithmetic; FP16 + scale: one spinor per thread (the scale is per spinor),
+// tiles of 4, FP32 arithmetic (the result is rounded to FP16).
 constexpr int TS_KT = 16;
+constexpr int TS_KT16 = 4;
 
 template <typename R>
 __global__ void __launch_bounds__(256) ts_combine_kernel(char* V, size_t stride, long long m, int n,
@@ -1006,29 +1040,77 @@ __global__ void __launch_bounds__(256) ts_combine_kernel(char* V, size_t stride,
   }
 }
 
+__global__ void __launch_bounds__(256) ts_combine_f16_kernel(char* V, size_t stride, VecGeom g, int n,
+                                                             const double* __restrict__ W) {
+  extern __shared__ double wsm[];  // [n][n] complex
+  for (int i = threadIdx.x; i < 2 * n * n; i += blockDim.x) wsm[i] = W[i];
+  __syncthreads();
+  const long long sp = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (sp >= g.n) return;
+  const long long h = sp / g.Ls;
+  const int s = (int)(sp - h * g.Ls);
+  for (int k0 = (n - 1) / TS_KT16 * TS_KT16; k0 >= 0; k0 -= TS_KT16) {
+    cplx<float> acc[TS_KT16][12];
+#pragma unroll
+    for (int t = 0; t < TS_KT16; ++t)
+#pragma unroll
+      for (int c = 0; c < 12; ++c) acc[t][c] = {0.f, 0.f};
+    const int jend = min(n, k0 + TS_KT16);
+    for (int j = 0; j < jend; ++j) {
+      cplx<float> v[12];
+      Store<DWF_F16S>::load(V + (size_t)j * stride, g.V4h, g.Ls, h, s, v);
+#pragma unroll
+      for (int t = 0; t < TS_KT16; ++t) {
+        const int k = k0 + t;
+        if (k >= n || j > k) continue;
+        const float wr = (float)wsm[2 * (j * n + k)], wi = (float)wsm[2 * (j * n + k) + 1];
+#pragma unroll
+        for (int c = 0; c < 12; ++c)
+          acc[t][c] = {fmaf(wr, v[c].re, fmaf(-wi, v[c].im, acc[t][c].re)),
+                       fmaf(wr, v[c].im, fmaf(wi, v[c].re, acc[t][c].im))};
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TS_KT16; ++t) {
+      const int k = k0 + t;
+      if (k < n) Store<DWF_F16S>::store(V + (size_t)k * stride, g.V4h, g.Ls, h, s, acc[t]);
+    }
+  }
+}
+
 hipError_t ts_gram(dwf_context* ctx, int prec, const char* V, int n, double* partial, int nwg, double* G) {
-  if (n < 1 || n > TS_NMAX || nwg < 1 || (prec != DWF_F64 && prec != DWF_F32)) return hipErrorInvalidValue;
+  if (n < 1 || n > TS_NMAX || nwg < 1 || prec < DWF_F64 || prec > DWF_F16S) return hipErrorInvalidValue;
+  const VecGeom g = vgeom(ctx);
   const size_t stride = field_bytes_rhs(ctx, prec);
-  const long long m = ctx->g.V4h * ctx->g.Ls * 12;
-  const long long span = (m + nwg - 1) / nwg;
-  const int ch = prec == DWF_F64 ? 32 : 64;
-  const size_t lds = (size_t)ch * n * (prec == DWF_F64 ? 16 : 8);
+  const long long units = prec == DWF_F16S ? g.n : g.n * 12;  // spinors, or complex values
+  const long long span = (units + nwg - 1) / nwg;
+  const int cu = prec == DWF_F64 ? 32 : (prec == DWF_F32 ? 64 : 4);  // 32 KB of staged rows at n = 64 (F16S 24 KB)
+  const size_t lds = (size_t)cu * (prec == DWF_F16S ? 12 : 1) * n * (prec == DWF_F64 ? 16 : 8);
   if (prec == DWF_F64)
-    hipLaunchKernelGGL(ts_gram_kernel<double>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, m, n, span, ch,
-                       partial);
+    hipLaunchKernelGGL(ts_gram_kernel<DWF_F64>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, units, n, span, cu,
+                       g, partial);
+  else if (prec == DWF_F32)
+    hipLaunchKernelGGL(ts_gram_kernel<DWF_F32>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, units, n, span, cu,
+                       g, partial);
   else
-    hipLaunchKernelGGL(ts_gram_kernel<float>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, m, n, span, ch,
-                       partial);
+    hipLaunchKernelGGL(ts_gram_kernel<DWF_F16S>, dim3(nwg), dim3(256), lds, ctx->stream, V, stride, units, n, span,
+                       cu, g, partial);
   hipLaunchKernelGGL(ts_gram_sum_kernel, dim3((n * n + 255) / 256), dim3(256), 0, ctx->stream, partial, nwg, n, G);
   return hipGetLastError();
 }
 
 hipError_t ts_combine(dwf_context* ctx, int prec, char* V, int n, const double* W) {
-  if (n < 1 || n > TS_NMAX || (prec != DWF_F64 && prec != DWF_F32)) return hipErrorInvalidValue;
+  if (n < 1 || n > TS_NMAX || prec < DWF_F64 || prec > DWF_F16S) return hipErrorInvalidValue;
+  const VecGeom g = vgeom(ctx);
   const size_t stride = field_bytes_rhs(ctx, prec);
-  const long long m = ctx->g.V4h * ctx->g.Ls * 12;
-  const dim3 grid((unsigned)((m + 255) / 256));
   const size_t lds = (size_t)2 * n * n * sizeof(double);
+  if (prec == DWF_F16S) {
+    hipLaunchKernelGGL(ts_combine_f16_kernel, dim3((unsigned)((g.n + 255) / 256)), dim3(256), lds, ctx->stream, V,
+                       stride, g, n, W);
+    return hipGetLastError();
+  }
+  const long long m = g.n * 12;
+  const dim3 grid((unsigned)((m + 255) / 256));
   if (prec == DWF_F64)
     hipLaunchKernelGGL(ts_combine_kernel<double>, grid, dim3(256), lds, ctx->stream, V, stride, m, n, W);
   else

@@ -116,8 +116,8 @@ hipError_t scal_converge(dwf_context* ctx, int nrhs, double tol2, bool count_ite
 // GS helpers: dots of v against Q_k (k < j) into coef[k]; v -= sum_k coef[k] Q_k
 hipError_t gs_multidot(dwf_context* ctx, int prec, const char* Q, const char* v, int j, double* coef);
 hipError_t gs_multiaxpy(dwf_context* ctx, int prec, const char* Q, char* v, int j, const double* coef);
-// Cholesky-QR pieces for up to TS_NMAX fields at FP64 or FP32 storage (fields taken as
-// flat complex arrays, consecutive at field_bytes_rhs apart).  ts_gram: G[k][j] =
+// Cholesky-QR pieces for up to TS_NMAX fields at any storage precision (fields
+// consecutive at field_bytes_rhs apart).  ts_gram: G[k][j] =
 // <v_j, v_k> for j <= k (complex FP64, n x n) from nwg per-workgroup partial sums in
 // `partial` (nwg * n * n complex), added in workgroup order.  ts_combine: in place
 // v_k <- sum_{j <= k} W[j][k] v_j (W upper triangular, complex FP64, W[j][k] at j * n + k).

@@ -323,12 +323,17 @@ def test_cg_fixed_iteration_counts(nrhs):
             assert abs(res[j] - ref.true_rel_residual) < 1e-12 * max(1.0, ref.true_rel_residual), (k, j)
 
 
-@pytest.mark.parametrize("prec,tol", [(F64, 1e-12), (F32, 2e-5)])
+@pytest.mark.parametrize("prec,tol", [(F64, 1e-12), (F32, 2e-5), (F16S, 3e-3)])
 @pytest.mark.parametrize("n", [1, 17, 40, 64, 65])
 def test_gram_schmidt_set_sizes(prec, tol, n):
-    """Sets of up to 64 vectors at FP64 and FP32 go through Cholesky QR twice, larger
-    sets through CGS2: both against the oracle's CGS2 (Q R with a positive real
-    diagonal is unique), on a set with a spread of norms and two near-parallel pairs."""
+    """Sets of up to 64 vectors go through Cholesky QR twice, larger sets through
+    CGS2: both against the oracle's CGS2 of the stored inputs (Q R with a positive
+    real diagonal is unique), on a set with a spread of norms and two near-parallel
+    pairs.  FP16 + scale: the output is rounded to FP16 (2^-11 relative per value);
+    CGS2 also stores every intermediate direction in FP16, and the 40x near-parallel
+    pair amplifies that rounding, hence its looser bound."""
+    if prec == F16S and n > 64:
+        tol = 3e-2
     dims, Ls = C1
     op, U = make_operator(dims, Ls, seed=0, prec=prec)
     v = even_fields(dims, Ls, n, seed=20 + n)
@@ -346,7 +351,7 @@ def test_gram_schmidt_set_sizes(prec, tol, n):
     assert np.max(np.abs(R - Ro)) < tol * np.max(np.abs(Ro))
     assert np.all(np.abs(np.diag(R).imag) == 0) and np.all(np.diag(R).real > 0)
     G = np.array([[np.vdot(Q[i].ravel(), Q[j].ravel()) for j in range(n)] for i in range(n)])
-    assert np.max(np.abs(G - np.eye(n))) < (1e-13 if prec == F64 else 1e-5)
+    assert np.max(np.abs(G - np.eye(n))) < {F64: 1e-13, F32: 1e-5, F16S: 5e-3}[prec]
 
 
 def test_gram_schmidt_nearly_dependent_set_falls_back():
