@@ -86,6 +86,22 @@ CG_ITERATION_HOPS = (
 )
 
 
+# kernels whose counters `--traffic` summarises, per workload: the four hop launches of a CG
+# iteration, and the four passes of a Chebyshev step of the 40-rhs FP32 filter (M_pc: M5D^-1 and
+# M5D epilogues; M_pc^dag: M5D^-dag, then the recurrence fused into the last pass)
+TRAFFIC_KERNELS = {
+    "rb_solve": [p for p, _ in CG_ITERATION_HOPS],
+    "batched": [
+        "void dwf::hop_kernel<1, 1, 1, false, 1,",
+        "void dwf::hop_kernel<1, 1, 1, false, 2,",
+        "void dwf::hop_kernel<1, 1, 1, true, 1,",
+        "void dwf::hop_kernel<1, 1, 1, true, 3,",
+    ],
+}
+# dispatches of each kind taken (the last ones: the timed work, after any autotuning)
+TRAFFIC_LAST = {"rb_solve": None, "batched": 24}
+
+
 def cg_hop_bytes_per_launch(V5h, Ls):
     """Algorithmic HBM bytes per hop launch, averaged over the four launches of a CG iteration."""
     S, Lb = SPINOR_BYTES[0], LINK_BYTES[0]
@@ -93,12 +109,12 @@ def cg_hop_bytes_per_launch(V5h, Ls):
     return V5h * per_site
 
 
-def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, prefixes=None):
+def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, prefixes=None, last=None):
     """HBM bytes per hop launch of a CG iteration from four rocprofv3 --pmc runs (FETCH_SIZE and
     WRITE_SIZE of the rb_solve bench, and of the copy workload).  Each counter is scaled by the
     factor that maps its reading on the copy kernel (copy_bytes read, copy_bytes written) onto
     the known size; the result is the mean over the four launch kinds of a CG iteration (or over
-    the kernels named by `prefixes`)."""
+    the kernels named by `prefixes`), each over its last `last` dispatches if given."""
     import csv
     import glob
     from collections import defaultdict
@@ -110,9 +126,9 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
         acc = defaultdict(float)
         names = {}
         for r in rows:
-            acc[r["Dispatch_Id"]] += float(r["Counter_Value"])
-            names[r["Dispatch_Id"]] = r["Kernel_Name"]
-        return [(names[k], v * 1024.0) for k, v in acc.items()]  # counters are KiB per dispatch
+            acc[int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+            names[int(r["Dispatch_Id"])] = r["Kernel_Name"]
+        return [(names[k], acc[k] * 1024.0) for k in sorted(acc)]  # counters are KiB per dispatch
 
     def copy_kib(d):
         return max(v for _, v in per_dispatch(d))  # the 4 GiB copy dominates every other dispatch
@@ -122,8 +138,8 @@ def summarize_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy
     fetch, write = per_dispatch(fetch_dir), per_dispatch(write_dir)
     kinds = {}
     for prefix in prefixes or [p for p, _ in CG_ITERATION_HOPS]:
-        fv = [v for n, v in fetch if n.startswith(prefix)]
-        wv = [v for n, v in write if n.startswith(prefix)]
+        fv = [v for n, v in fetch if n.startswith(prefix)][-(last or 0):]
+        wv = [v for n, v in write if n.startswith(prefix)][-(last or 0):]
         if not fv or not wv:
             raise SystemExit(f"no dispatch of {prefix!r} in the counter runs")
         kinds[prefix] = {
@@ -523,7 +539,7 @@ def mixed_cg_pass_bytes(Ls, prec_p):
     return (Sp + S32 + link, 2 * S32 + Sp + link, 2 * S32 + link, 4 * S32 + link)
 
 
-def leg_batched(args, steps=3, warmup=1):
+def leg_batched(args, steps=3, warmup=1, fixed_order=False):
     """40 complex64 subspace vectors through the order-32 filter in one multi-rhs launch per pass,
     then FP64-accumulated Gram-Schmidt; compared with the same work in FP64 one vector at a time."""
     import torch
@@ -538,9 +554,15 @@ def leg_batched(args, steps=3, warmup=1):
     V5h = X * Y * Z * T * Ls // 2
     U = torch.from_numpy(synth.gauge_links(dims, cfg["eps"], seed=0)).to("cuda")
     op = dwf.Operator(U, dims, Ls, cfg["M5"], cfg["mf"], prec=dwf.DWF_F32, max_nrhs=nvec, max_cg_rhs=0)
+    if fixed_order and args.box:  # a fixed traversal order (--workload batched, e.g. for counter runs)
+        op.set_order_box(*(int(v) for v in args.box.split(",")))
+    elif fixed_order and args.order >= 0:
+        op.set_order(args.order)
     spb, depth, _ = op.autotune(nvec, 3)
     rpb = op.tile[2]
-    log(f"batched FP32 autotune: spb={spb} depth={depth} rhs/workgroup={rpb}")
+    mode, box = op.get_order()
+    order_desc = {"mode": mode, "box": list(box)} if mode == 3 else {"mode": mode}
+    log(f"batched FP32 autotune: spb={spb} depth={depth} rhs/workgroup={rpb} order {order_desc}")
     vecs = op.new_field(nvec)
     _fill_gaussian(op, vecs, nvec, dims, Ls, seed=2)
     pristine = vecs.clone()
@@ -553,6 +575,7 @@ def leg_batched(args, steps=3, warmup=1):
     # one filter step = 4 launches over nvec rhs
     per_launch = V5h * nvec * cheb_step_bytes(dwf.DWF_F32, Ls, nvec) / 4
     roof = _roofline(per_launch, hop_ms, hop_n, "hop_kernel, FP32, 40 rhs per launch (filter passes)")
+    roof["traffic"] = measured_traffic("batched", order_desc)
     op.close()
     del op, vecs, pristine
     torch.cuda.empty_cache()
@@ -588,7 +611,8 @@ def leg_batched(args, steps=3, warmup=1):
         "config": {
             "workload": "40 complex64 vectors, order-32 Chebyshev filter [0.05,60] of M_pc^dag M_pc in one "
             "multi-rhs launch per pass + FP64-accumulated Gram-Schmidt, 16^3x32 Ls=16",
-            "autotuned_tile": {"sites_per_block": spb, "pipeline_depth": depth, "rhs_per_block": rpb},
+            "autotuned_tile": {"sites_per_block": spb, "pipeline_depth": depth, "rhs_per_block": rpb,
+                               "order": order_desc},
             "fp64_one_at_a_time_vecs_per_s": nvec / t_64,
             "speedup_vs_fp64_unbatched": t_64 / per_step,
             "fp32_vs_fp64_rel_diff_first_two_vectors": agree,
@@ -598,7 +622,7 @@ def leg_batched(args, steps=3, warmup=1):
 
 
 def run_batched(args):
-    leg = leg_batched(args, max(args.steps, 1), args.warmup)
+    leg = leg_batched(args, max(args.steps, 1), args.warmup, fixed_order=True)
     return {"metric": METRIC, "n_gpus": 1, "warmup": args.warmup, "scaling": "weak", "vs_baseline": None,
             "data": "synthetic", **leg}
 
@@ -1255,6 +1279,8 @@ def main():
         help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this bench and of --workload copy "
         "into profiles/hop_traffic.json (no GPU needed)",
     )
+    ap.add_argument("--traffic-workload", default="rb_solve", choices=sorted(TRAFFIC_KERNELS),
+                    help="with --traffic: the workload the counter runs were taken on")
     ap.add_argument(
         "--traffic-force",
         nargs=4,
@@ -1284,21 +1310,24 @@ def main():
     if args.traffic:
         import hashlib
 
-        rec = summarize_traffic(*args.traffic, copy_bytes=WORKLOADS["copy"]["bytes"])
+        wl = args.traffic_workload
+        rec = summarize_traffic(*args.traffic, copy_bytes=WORKLOADS["copy"]["bytes"],
+                                prefixes=TRAFFIC_KERNELS[wl], last=TRAFFIC_LAST[wl])
         order = ({"mode": 3, "box": [int(v) for v in args.box.split(",")]} if args.box
                  else {"mode": max(args.order, 0)})
         digest = hashlib.sha256(open(HOP_SOURCE, "rb").read()).hexdigest()
-        # one record per traversal order, kept while the hop source is unchanged
+        # one record per workload and traversal order, kept while the hop source is unchanged
         try:
             out = json.load(open(TRAFFIC_FILE))
         except (OSError, ValueError):
             out = {}
-        if out.get("hop_source_sha256") != digest or "orders" not in out.get("workloads", {}).get("rb_solve", {}):
-            out = {"hop_source_sha256": digest, "workloads": {"rb_solve": {"orders": {}}}}
-        out["workloads"]["rb_solve"]["orders"][_order_key(order)] = {"order": order, **rec}
+        if out.get("hop_source_sha256") != digest:
+            out = {"hop_source_sha256": digest, "workloads": {}}
+        out.setdefault("workloads", {}).setdefault(wl, {}).setdefault("orders", {})
+        out["workloads"][wl]["orders"][_order_key(order)] = {"order": order, **rec}
         with open(TRAFFIC_FILE, "w") as f:
             json.dump(out, f, indent=1)
-        print(json.dumps(out["workloads"]["rb_solve"]["orders"][_order_key(order)], indent=1))
+        print(json.dumps(out["workloads"][wl]["orders"][_order_key(order)], indent=1))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(
