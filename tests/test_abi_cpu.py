@@ -92,6 +92,7 @@ def test_calls_on_null_handle_fail_cleanly(lib):
     assert lib.dwf_mpc(None, None, None, 1, 0) == dwf.DWF_EINVAL
     assert "null handle" in dwf.last_error()
     assert lib.dwf_set_progress(None, dwf.PROGRESS_FN(), None, 0) == dwf.DWF_EINVAL
+    assert lib.dwf_lie_force(None, None, None, None) == dwf.DWF_EINVAL
     assert lib.dwf_destroy(None) == dwf.DWF_OK
 
 
@@ -190,7 +191,7 @@ def test_method_calls_cite_a_section():
     method = [
         "dwf_create", "dwf_dhop", "dwf_m5d", "dwf_m5d_inv", "dwf_ddw", "dwf_mpc", "dwf_mpcdagmpc", "dwf_cg",
         "dwf_solve_rb", "dwf_power", "dwf_chebyshev_filter", "dwf_chebyshev_series", "dwf_chebyshev_smoother",
-        "dwf_gram_schmidt", "dwf_force", "dwf_pack", "dwf_unpack", "dwf_set_schur_form", "dwf_solve_unprec",
+        "dwf_gram_schmidt", "dwf_force", "dwf_lie_force", "dwf_pack", "dwf_unpack", "dwf_set_schur_form", "dwf_solve_unprec",
         "dwf_set_blocks", "dwf_chiral_split", "dwf_block_orthonormalize", "dwf_restrict", "dwf_prolong", "dwf_hdw",
         "dwf_hdcr_filter", "dwf_hdcr_series", "dwf_hdcr_set_basis", "dwf_hdcr_coarse_solve", "dwf_hdcr_smoother",
         "dwf_hdcr_vcycle", "dwf_hdcr_solve",
