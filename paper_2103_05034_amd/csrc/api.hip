@@ -548,11 +548,15 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
   HIP_TRY(scal_set(h, nrhs, S_ITERS, 0.0));
   HIP_TRY(scal_converge(h, nrhs, tol2, false));
   std::vector<double> sc;
+  // The host looks at the scalars every `check` iterations, and sooner when the
+  // residual's fall since its last look predicts convergence before the next one:
+  // iterations queued after convergence still run (as no-ops) at full cost.
   const int check = 8;
   bool stopped = false;
-  int last = 0;
+  int last = 0, next_look = 0, last_look = 0;
+  std::vector<double> rr_seen(nrhs, -1.0);
   for (int it = 0; it < maxiter; ++it) {
-    if (it % check == 0) {
+    if (it == next_look) {
       if (int rc = read_scalars(h, nrhs, sc)) return rc;
       bool any = false;
       for (int rr = 0; rr < nrhs; ++rr) any |= sc[(size_t)rr * NSCAL + S_ACTIVE] != 0.0;
@@ -561,6 +565,25 @@ static int cg_f64(dwf_handle h, const char* b, char* x, int nrhs, double tol, in
         stopped = true;
         break;
       }
+      int step = check;
+      if (it > last_look) {
+        int need = 0;  // iterations the slowest active rhs is predicted to need
+        for (int rr = 0; rr < nrhs; ++rr) {
+          const double* sr = &sc[(size_t)rr * NSCAL];
+          if (sr[S_ACTIVE] == 0.0) continue;
+          const double now = sr[S_RR], prev = rr_seen[rr], goal = tol2 * sr[S_BB];
+          double n = check;
+          if (prev > 0.0 && now > 0.0 && now < prev && goal > 0.0) {
+            const double fall = std::log(now / prev) / (it - last_look);  // per iteration, < 0
+            n = std::log(goal / now) / fall;
+          }
+          need = std::max(need, n >= check ? check : (int)std::ceil(n));
+        }
+        step = std::max(1, std::min(check, need));
+      }
+      for (int rr = 0; rr < nrhs; ++rr) rr_seen[rr] = sc[(size_t)rr * NSCAL + S_RR];
+      last_look = it;
+      next_look = it + step;
     }
     if (defer) {
       HIP_TRY(cg_step_f64(h, dx.current(), r, h->t64, h->u64, nrhs, tol2));
