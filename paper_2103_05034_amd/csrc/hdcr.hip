@@ -582,7 +582,8 @@ hipError_t coarse_matvec(dwf_hdcr_s* hd, const double2* x, double2* y) {
 
 // c = A^{-1} d by CG on A^2 c = A d from c = 0; stops when |A d - A^2 c| <= tol |A d|.
 // The scalars stay on the device: once converged the remaining iterations of a batch
-// are no-ops (alpha = 0), and the host looks at the state every CG_BATCH iterations.
+// are no-ops (alpha = 0), and the host looks at the state every CG_BATCH iterations,
+// or sooner when the fall of |r|^2 over the last batch predicts convergence within it.
 constexpr int CG_BATCH = 8;
 
 int coarse_cgnr(dwf_hdcr_s* hd, const double2* d, double2* cvec, double tol, int maxiter, int* iters) {
@@ -609,8 +610,10 @@ int coarse_cgnr(dwf_hdcr_s* hd, const double2* d, double2* cvec, double tol, int
   };
   if (int rc = read_state()) return rc;
   const unsigned gb = blocks_for(n);
+  int batch_size = CG_BATCH;
   for (int done = 0; st[CS_ACTIVE] != 0.0 && done < maxiter;) {
-    const int batch = std::min(CG_BATCH, maxiter - done);
+    const int batch = std::min(batch_size, maxiter - done);
+    const double rr_before = st[CS_RR];
     for (int k = 0; k < batch; ++k) {
       HIP_TRY(coarse_matvec(hd, p, q));                       // q = A p
       norm_into(q, CS_QQ);                                    // |q|^2 = p.A^2 p
@@ -625,6 +628,13 @@ int coarse_cgnr(dwf_hdcr_s* hd, const double2* d, double2* cvec, double tol, int
     done += batch;
     if (int rc = read_state()) return rc;
     if (st[CS_FLAG] != 0.0) return fail(DWF_EBREAKDOWN, "coarse CG breakdown");
+    // iterations still needed at the rate |r|^2 fell over this batch
+    batch_size = CG_BATCH;
+    const double now = st[CS_RR], goal = st[CS_STOP];
+    if (rr_before > 0.0 && now > 0.0 && now < rr_before && goal > 0.0 && now > goal) {
+      const double left = std::log(goal / now) / (std::log(now / rr_before) / batch);
+      if (left < CG_BATCH) batch_size = std::max(1, (int)std::ceil(left));
+    }
   }
   const int it = (int)st[CS_ITERS];
   if (iters) *iters = it;
