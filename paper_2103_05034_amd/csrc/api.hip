@@ -1126,52 +1126,6 @@ int dwf_dot(dwf_handle h, int prec, const void* a, const void* b, int nrhs, doub
 // diagonal is unique) up to rounding.  Returns GS_USE_CGS2, with the vectors
 // untouched, when the first round's Gram matrix is too close to singular for
 // this form or the scratch is too small; the caller then runs CGS2.
-static int cholesky_upper(const std::vector<double>& G, int n, std::vector<double>& R, double min_ratio) {
-  // G[k][j] = <v_j, v_k> (j <= k) -> upper R with G = R^dag R, R[j][k] at (j * n + k)
-  R.assign((size_t)2 * n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    double d = G[2 * ((size_t)j * n + j)];
-    const double djj = d;
-    for (int i = 0; i < j; ++i) d -= R[2 * ((size_t)i * n + j)] * R[2 * ((size_t)i * n + j)] +
-                                      R[2 * ((size_t)i * n + j) + 1] * R[2 * ((size_t)i * n + j) + 1];
-    if (!(d > min_ratio * djj) || !std::isfinite(d)) return DWF_EBREAKDOWN;
-    const double rjj = std::sqrt(d);
-    R[2 * ((size_t)j * n + j)] = rjj;
-    for (int k = j + 1; k < n; ++k) {
-      double re = G[2 * ((size_t)k * n + j)], im = G[2 * ((size_t)k * n + j) + 1];  // <v_j, v_k>
-      for (int i = 0; i < j; ++i) {  // - conj(R_ij) R_ik
-        const double ar = R[2 * ((size_t)i * n + j)], ai = R[2 * ((size_t)i * n + j) + 1];
-        const double br = R[2 * ((size_t)i * n + k)], bi = R[2 * ((size_t)i * n + k) + 1];
-        re -= ar * br + ai * bi;
-        im -= ar * bi - ai * br;
-      }
-      R[2 * ((size_t)j * n + k)] = re / rjj;
-      R[2 * ((size_t)j * n + k) + 1] = im / rjj;
-    }
-  }
-  return DWF_OK;
-}
-
-// W = R^{-1} for upper triangular R with a real positive diagonal
-static void invert_upper(const std::vector<double>& R, int n, std::vector<double>& W) {
-  W.assign((size_t)2 * n * n, 0.0);
-  for (int k = 0; k < n; ++k) {
-    W[2 * ((size_t)k * n + k)] = 1.0 / R[2 * ((size_t)k * n + k)];
-    for (int j = k - 1; j >= 0; --j) {
-      double re = 0, im = 0;
-      for (int i = j + 1; i <= k; ++i) {  // sum R_ji W_ik
-        const double ar = R[2 * ((size_t)j * n + i)], ai = R[2 * ((size_t)j * n + i) + 1];
-        const double br = W[2 * ((size_t)i * n + k)], bi = W[2 * ((size_t)i * n + k) + 1];
-        re += ar * br - ai * bi;
-        im += ar * bi + ai * br;
-      }
-      const double rjj = R[2 * ((size_t)j * n + j)];
-      W[2 * ((size_t)j * n + k)] = -re / rjj;
-      W[2 * ((size_t)j * n + k) + 1] = -im / rjj;
-    }
-  }
-}
-
 constexpr int GS_USE_CGS2 = 1;
 
 static int gs_cholqr2(dwf_handle h, char* Q, int n, std::vector<double>& Rout) {
@@ -1196,29 +1150,16 @@ static int gs_cholqr2(dwf_handle h, char* Q, int n, std::vector<double>& Rout) {
     // first round: a pivot below 1e-14 of its diagonal entry (a condition number
     // beyond about 1e7) leaves the set to CGS2
     std::vector<double>& R = round == 0 ? R1 : R2;
-    if (cholesky_upper(G, n, R, round == 0 ? 1e-14 : 0.0) != DWF_OK) {
+    if (!plan::cholesky_upper(G, n, R, round == 0 ? 1e-14 : 0.0)) {
       if (round == 0) return GS_USE_CGS2;
       return fail(DWF_EBREAKDOWN, "dwf_gram_schmidt: the vectors are numerically dependent");
     }
-    invert_upper(R, n, W);
+    plan::invert_upper(R, n, W);
     HIP_TRY(hipMemcpyAsync(Wd, W.data(), 2 * nn * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(ts_combine(h, P, Q, n, Wd));
     if (int rc = sync(h)) return rc;  // W's host copy is reused next round
   }
-  // R = R2 R1 (both upper triangular)
-  Rout.assign(2 * nn, 0.0);
-  for (int j = 0; j < n; ++j)
-    for (int k = j; k < n; ++k) {
-      double re = 0, im = 0;
-      for (int i = j; i <= k; ++i) {
-        const double ar = R2[2 * ((size_t)j * n + i)], ai = R2[2 * ((size_t)j * n + i) + 1];
-        const double br = R1[2 * ((size_t)i * n + k)], bi = R1[2 * ((size_t)i * n + k) + 1];
-        re += ar * br - ai * bi;
-        im += ar * bi + ai * br;
-      }
-      Rout[2 * ((size_t)j * n + k)] = re;
-      Rout[2 * ((size_t)j * n + k) + 1] = im;
-    }
+  plan::multiply_upper(R2, R1, n, Rout);  // R = R2 R1
   return DWF_OK;
 }
 

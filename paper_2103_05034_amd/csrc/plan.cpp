@@ -1,7 +1,9 @@
-// Host-side planning: argument checks, workspace layout, traversal orders
-// and coarse-space block tables (no device code).
+// Host-side planning: argument checks, workspace layout, traversal orders,
+// coarse-space block tables and the host arithmetic of the Cholesky QR (no
+// device code).
 #include "plan.hpp"
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -292,6 +294,66 @@ void tune_clear() {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   g_tune.clear();
   g_tune_loaded = false;
+}
+
+bool cholesky_upper(const std::vector<double>& G, int n, std::vector<double>& R, double min_ratio) {
+  R.assign((size_t)2 * n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    double d = G[2 * ((size_t)j * n + j)];
+    const double djj = d;
+    for (int i = 0; i < j; ++i) d -= R[2 * ((size_t)i * n + j)] * R[2 * ((size_t)i * n + j)] +
+                                      R[2 * ((size_t)i * n + j) + 1] * R[2 * ((size_t)i * n + j) + 1];
+    if (!(d > min_ratio * djj) || !std::isfinite(d)) return false;
+    const double rjj = std::sqrt(d);
+    R[2 * ((size_t)j * n + j)] = rjj;
+    for (int k = j + 1; k < n; ++k) {
+      double re = G[2 * ((size_t)k * n + j)], im = G[2 * ((size_t)k * n + j) + 1];  // <v_j, v_k>
+      for (int i = 0; i < j; ++i) {  // - conj(R_ij) R_ik
+        const double ar = R[2 * ((size_t)i * n + j)], ai = R[2 * ((size_t)i * n + j) + 1];
+        const double br = R[2 * ((size_t)i * n + k)], bi = R[2 * ((size_t)i * n + k) + 1];
+        re -= ar * br + ai * bi;
+        im -= ar * bi - ai * br;
+      }
+      R[2 * ((size_t)j * n + k)] = re / rjj;
+      R[2 * ((size_t)j * n + k) + 1] = im / rjj;
+    }
+  }
+  return true;
+}
+
+void invert_upper(const std::vector<double>& R, int n, std::vector<double>& W) {
+  W.assign((size_t)2 * n * n, 0.0);
+  for (int k = 0; k < n; ++k) {
+    W[2 * ((size_t)k * n + k)] = 1.0 / R[2 * ((size_t)k * n + k)];
+    for (int j = k - 1; j >= 0; --j) {
+      double re = 0, im = 0;
+      for (int i = j + 1; i <= k; ++i) {  // sum R_ji W_ik
+        const double ar = R[2 * ((size_t)j * n + i)], ai = R[2 * ((size_t)j * n + i) + 1];
+        const double br = W[2 * ((size_t)i * n + k)], bi = W[2 * ((size_t)i * n + k) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      const double rjj = R[2 * ((size_t)j * n + j)];
+      W[2 * ((size_t)j * n + k)] = -re / rjj;
+      W[2 * ((size_t)j * n + k) + 1] = -im / rjj;
+    }
+  }
+}
+
+void multiply_upper(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C) {
+  C.assign((size_t)2 * n * n, 0.0);
+  for (int j = 0; j < n; ++j)
+    for (int k = j; k < n; ++k) {
+      double re = 0, im = 0;
+      for (int i = j; i <= k; ++i) {
+        const double ar = A[2 * ((size_t)j * n + i)], ai = A[2 * ((size_t)j * n + i) + 1];
+        const double br = B[2 * ((size_t)i * n + k)], bi = B[2 * ((size_t)i * n + k) + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      C[2 * ((size_t)j * n + k)] = re;
+      C[2 * ((size_t)j * n + k) + 1] = im;
+    }
 }
 
 }  // namespace plan

@@ -1,5 +1,6 @@
 // Host-side planning behind the entry points: argument checks, the layout of
-// a handle's workspace and the site traversal orders of the hop kernels.
+// a handle's workspace, the site traversal orders of the hop kernels and the
+// host arithmetic of the Cholesky QR.
 // Plain C++17 with no HIP dependency, so the same source also builds into a
 // host-only test program under AddressSanitizer and UBSan.
 #pragma once
@@ -135,6 +136,17 @@ void tune_store(const TuneKey& k, const TuneEntry& e, const char* path);
 // Empties the process cache; the file is left as it is and read again on the
 // next lookup.
 void tune_clear();
+
+// Host side of the Cholesky QR of dwf_gram_schmidt.  Complex n x n matrices as
+// interleaved (re, im) doubles, row-major.  From the lower triangle of a Gram
+// matrix, G[k][j] = <v_j, v_k> for j <= k, the upper R with G = R^dag R and a real
+// positive diagonal; false when a pivot is not above min_ratio times its diagonal
+// entry of G (or is not finite).
+bool cholesky_upper(const std::vector<double>& G, int n, std::vector<double>& R, double min_ratio);
+// W = R^{-1} for upper triangular R with a real positive diagonal.
+void invert_upper(const std::vector<double>& R, int n, std::vector<double>& W);
+// C = A B for upper triangular A and B.
+void multiply_upper(const std::vector<double>& A, const std::vector<double>& B, int n, std::vector<double>& C);
 
 }  // namespace plan
 }  // namespace dwf

@@ -6,6 +6,8 @@
 // "all checks passed" and one "total" line per planned shape.  argv[1]: a
 // directory for the tuning-cache file.
 #include <algorithm>
+#include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -329,8 +331,81 @@ static void check_tune_cache(const std::string& dir) {
   std::remove(path.c_str());
 }
 
+// Host arithmetic of the Cholesky QR: R^dag R reproduces the Gram matrix of a
+// random complex set (norms spread over e^{+-3}, a near-parallel pair), R W = 1,
+// the triangular product against a full product, and the breakdown answers.
+static void check_cholesky() {
+  unsigned long long st = 12345;
+  auto rnd = [&]() {  // uniform in (-1, 1) from a 64-bit LCG
+    st = st * 6364136223846793005ULL + 1442695040888963407ULL;
+    return (double)(st >> 11) / (double)(1ULL << 52) - 1.0;
+  };
+  using C = std::complex<double>;
+  for (int n : {1, 2, 5, 17, 40, 64}) {
+    const int m = 3 * n + 7;
+    std::vector<C> V((size_t)m * n);
+    for (int k = 0; k < n; ++k) {
+      const double sc = std::exp(-3.0 + 6.0 * k / std::max(1, n - 1));
+      for (int i = 0; i < m; ++i) V[(size_t)i * n + k] = sc * C(rnd(), rnd());
+    }
+    if (n > 3)
+      for (int i = 0; i < m; ++i) V[(size_t)i * n + 2] += 40.0 * V[(size_t)i * n + 1];
+    std::vector<double> G((size_t)2 * n * n, 0.0), R, W, P;
+    double gmax = 0;
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j <= k; ++j) {
+        C g = 0;
+        for (int i = 0; i < m; ++i) g += std::conj(V[(size_t)i * n + j]) * V[(size_t)i * n + k];
+        G[2 * ((size_t)k * n + j)] = g.real();
+        G[2 * ((size_t)k * n + j) + 1] = g.imag();
+        gmax = std::max(gmax, std::abs(g));
+      }
+    CHECK(plan::cholesky_upper(G, n, R, 1e-14), "cholesky rejected a well-posed set, n %d", n);
+    auto at = [&](const std::vector<double>& A, int r, int c) { return C(A[2 * ((size_t)r * n + c)], A[2 * ((size_t)r * n + c) + 1]); };
+    double err = 0, low = 0, diag_ok = 1;
+    for (int j = 0; j < n; ++j) {
+      if (!(at(R, j, j).real() > 0) || at(R, j, j).imag() != 0) diag_ok = 0;
+      for (int k = 0; k < n; ++k) {
+        if (k < j) low = std::max(low, std::abs(at(R, j, k)));
+        if (k < j) continue;
+        C s = 0;  // (R^dag R)_{jk} = sum_i conj(R_ij) R_ik
+        for (int i = 0; i <= j; ++i) s += std::conj(at(R, i, j)) * at(R, i, k);
+        err = std::max(err, std::abs(s - at(G, k, j)));
+      }
+    }
+    CHECK(err < 1e-13 * gmax, "R^dag R != G (n %d, error %g of %g)", n, err, gmax);
+    CHECK(low == 0 && diag_ok, "R not upper triangular with a positive real diagonal (n %d)", n);
+    plan::invert_upper(R, n, W);
+    double ierr = 0;
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        C s = 0;
+        for (int i = 0; i < n; ++i) s += at(R, j, i) * at(W, i, k);
+        ierr = std::max(ierr, std::abs(s - (j == k ? 1.0 : 0.0)));
+      }
+    CHECK(ierr < 1e-10, "R W != 1 (n %d, error %g)", n, ierr);
+    plan::multiply_upper(R, W, n, P);
+    double perr = 0;
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) perr = std::max(perr, std::abs(at(P, j, k) - (j == k ? 1.0 : 0.0)));
+    CHECK(perr < 1e-10, "multiply_upper(R, R^-1) != 1 (n %d, error %g)", n, perr);
+    if (n >= 2) {  // a repeated vector: no positive second pivot
+      std::vector<double> Gs = G;
+      Gs[2 * ((size_t)1 * n + 1)] = G[0];
+      Gs[2 * ((size_t)1 * n + 0)] = G[0];
+      Gs[2 * ((size_t)1 * n + 0) + 1] = 0;
+      CHECK(!plan::cholesky_upper(Gs, n, R, 1e-14), "cholesky accepted a singular Gram matrix (n %d)", n);
+    }
+  }
+  std::vector<double> neg = {-1.0, 0.0}, R;
+  CHECK(!plan::cholesky_upper(neg, 1, R, 0.0), "cholesky accepted a negative pivot");
+  std::vector<double> nan1 = {std::nan(""), 0.0};
+  CHECK(!plan::cholesky_upper(nan1, 1, R, 0.0), "cholesky accepted a NaN pivot");
+}
+
 int main(int argc, char** argv) {
   check_valid_dims();
+  check_cholesky();
   check_tune_cache(argc > 1 ? argv[1] : ".");
   const int shapes[][4] = {{2, 2, 2, 2}, {4, 4, 6, 8}, {8, 4, 4, 8}, {16, 16, 16, 32}, {24, 24, 24, 48}, {6, 2, 10, 4}};
   for (const auto& d : shapes)
